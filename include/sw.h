@@ -1,0 +1,227 @@
+/*
+ * sw.h -- C-ABI of the MI355X implicit seismic-wave analysis library.
+ *
+ * One analysis ("case") is the implicit 3D wave-propagation analysis that the
+ * paper runs once per candidate ground model and input direction
+ * (Section 3: 236 models x 3 directions): linear elastodynamics
+ * (Section 2, Eq. GE:ORG) on second-order (10-node) tetrahedra, traction-free
+ * top, absorbing sides and base, the input velocity wave applied at the base
+ * as a force (Sections 2-3), marched in time by the Newmark-beta method
+ * (Section 3) with beta = 1/4, gamma = 1/2, every step's system
+ *     (c_M M + c_K K + 2/dt C_abs) du = b,
+ *     c_M = 4/dt^2 + 2 alpha/dt,  c_K = 1 + 2 beta_R/dt,
+ * solved by preconditioned conjugate gradients (Section 3 names a CG solver)
+ * around a matrix-free element-by-element operator, to a relative residual
+ * ||b - A du||_2 <= rtol ||b||_2 recomputed in FP64.  The outputs are
+ * velocities at surface observation points and the misfit ERR of
+ * Eq. (eqerr).
+ *
+ * Conventions
+ *   - Vectors on the device are FP64, node-major: value[3 * node + comp].
+ *   - tet10: vertices 0..3 then edge nodes 01, 12, 02, 03, 13, 23; positive
+ *     volume; edge nodes at edge midpoints (straight-sided elements).
+ *   - tri6: vertices 0..2 then edge nodes 01, 12, 20.
+ *   - face_role: 1 = absorbing side face, 2 = absorbing base face that also
+ *     carries the input force 2 Z v_in, Z = rho Vp n n^T + rho Vs (I - n n^T)
+ *     with the material of the owning tet.
+ *   - material rows are (Vp, Vs, rho).
+ *
+ * Ownership
+ *   - Host arrays passed to *_create are copied before the call returns.
+ *   - Device memory is owned by the caller: each object works inside the
+ *     workspace the caller passes (size from the matching *_workspace_bytes
+ *     call, 256-byte aligned base) and borrows it until destroyed.  The
+ *     library itself never allocates device memory.
+ *   - All device work is enqueued on the context's stream.
+ *
+ * Errors
+ *   - Every call returns SW_OK (0) or a negative status; sw_last_error()
+ *     returns a message for the last failure on the calling thread.  Host
+ *     validation (sizes, index ranges, element orientation, parameters) runs
+ *     before any device work, so a rejected call leaves no device state
+ *     changed.  Non-convergence is not an error of the step call: the step
+ *     completes and the case's flags record it.
+ *   - One context per host thread; calls on one context are not thread safe.
+ */
+#ifndef SW_H
+#define SW_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#if defined(__GNUC__)
+#define SW_API __attribute__((visibility("default")))
+#else
+#define SW_API
+#endif
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct sw_ctx sw_ctx;
+typedef struct sw_mesh sw_mesh;
+typedef struct sw_case sw_case;
+typedef struct sw_batch sw_batch;
+typedef struct sw_mlp sw_mlp;
+
+enum {
+  SW_OK = 0,
+  SW_EINVAL = -1,   /* bad argument or parameter */
+  SW_ENOWS = -2,    /* workspace missing, misaligned or too small */
+  SW_EMESH = -3,    /* invalid mesh (index out of range, inverted or curved element) */
+  SW_ENOCONV = -4,  /* reserved: convergence failure is reported through flags */
+  SW_EHIP = -5,     /* HIP runtime error */
+  SW_ESTATE = -6    /* object used in the wrong state */
+};
+
+/* sw_case_stats.flags bits */
+enum { SW_FLAG_NOCONV = 1, SW_FLAG_NONFINITE = 2, SW_FLAG_GUESS_FALLBACK = 4 };
+
+/* precision of the per-step solve */
+enum {
+  SW_FP64 = 0,        /* FP64 preconditioned CG on the FP64 operator */
+  SW_MIXED_FP32 = 1   /* FP32 inner CG (FP32 operator, FP32 vectors) inside FP64
+                         iterative refinement; FP64 true residual and update */
+};
+
+/* initial guess of each step's solve */
+enum {
+  SW_GUESS_ZERO = 0,  /* du0 = 0 */
+  SW_GUESS_POLY = 1,  /* Lagrange extrapolation of the last poly_order + 1 increments */
+  SW_GUESS_MLP = 2    /* poly extrapolation plus a learned per-DOF correction */
+};
+
+/* operators for sw_case_apply (bit mask; the terms are summed) */
+enum {
+  SW_OP_M = 1,     /* consistent mass M */
+  SW_OP_K = 2,     /* stiffness K */
+  SW_OP_CABS = 4,  /* dashpot matrix C_abs */
+  SW_OP_A = 8      /* step operator c_M M + c_K K + 2/dt C_abs (exclusive of the others) */
+};
+
+/* Message of the last failed call on this thread (never NULL). */
+SW_API const char* sw_last_error(void);
+
+/* Library version string. */
+SW_API const char* sw_version(void);
+
+/* Context on HIP device `device`; `hip_stream` is a hipStream_t (NULL = the
+ * null stream) on which all work of objects made from this context runs. */
+SW_API int sw_ctx_create(int device, void* hip_stream, sw_ctx** out);
+SW_API int sw_ctx_destroy(sw_ctx* ctx);
+
+/* ----------------------------------------------------------------- mesh */
+
+typedef struct {
+  int64_t n_nodes, n_tets, n_faces;
+  const double* xyz;          /* host, n_nodes x 3 */
+  const int32_t* tet10;       /* host, n_tets x 10 */
+  const int32_t* tri6;        /* host, n_faces x 6 */
+  const int32_t* face_tet;    /* host, n_faces: the tet each face belongs to */
+  const uint8_t* face_role;   /* host, n_faces: 1 side, 2 base */
+} sw_mesh_desc;
+
+/* Device workspace needed by sw_mesh_create for this mesh. */
+SW_API int sw_mesh_workspace_bytes(const sw_mesh_desc* desc, size_t* bytes);
+/* Validates the mesh (index ranges, positive volumes, edge nodes at edge
+ * midpoints to 1e-9 relative, faces being faces of their owning tet),
+ * builds the device layout and uploads it into dev_ws. */
+SW_API int sw_mesh_create(sw_ctx* ctx, const sw_mesh_desc* desc, void* dev_ws, size_t ws_bytes, sw_mesh** out);
+SW_API int sw_mesh_destroy(sw_mesh* mesh);
+
+/* ----------------------------------------------------------------- case */
+
+typedef struct {
+  double dt;             /* time step, > 0 */
+  double ray_alpha;      /* Rayleigh mass coefficient (1/s), >= 0 */
+  double ray_beta;       /* Rayleigh stiffness coefficient (s), >= 0 */
+  double rtol;           /* relative residual target, in (0, 1) */
+  int32_t max_iter;      /* CG iteration cap per step (inner + outer) */
+  int32_t precision;     /* SW_FP64 or SW_MIXED_FP32 */
+  int32_t guess;         /* SW_GUESS_* */
+  int32_t poly_order;    /* 0..3, used by SW_GUESS_POLY / SW_GUESS_MLP */
+  double inner_rtol;     /* SW_MIXED_FP32: inner CG relative tolerance (0 = default 1e-3) */
+  int32_t n_mat;         /* rows of mat, 1..255 */
+  const double* mat;     /* host, n_mat x 3 rows (Vp, Vs, rho), Vp^2 > 2 Vs^2 */
+  const uint8_t* tet_mat;/* host, n_tets material ids */
+  int32_t n_rec;         /* receivers (>= 0) */
+  const int32_t* rec_node; /* host, n_rec node ids */
+  int64_t n_steps;       /* capacity of the march (steps 1..n_steps) */
+  const double* v_in;    /* host, (n_steps + 1) x 3 incident velocity at t = n dt */
+} sw_case_desc;
+
+SW_API int sw_case_workspace_bytes(const sw_mesh* mesh, const sw_case_desc* desc, size_t* bytes);
+/* Copies the case data to the device and builds the 3x3 block-Jacobi
+ * preconditioner (FP64 inverse of the diagonal blocks of A). */
+SW_API int sw_case_create(sw_ctx* ctx, sw_mesh* mesh, const sw_case_desc* desc, void* dev_ws, size_t ws_bytes,
+                   sw_case** out);
+SW_API int sw_case_destroy(sw_case* c);
+
+/* State (u, v, a) as host arrays of 3*n_nodes doubles and the step index;
+ * set_state also clears the increment history used by the guesses.  NULL
+ * pointers leave (set) or skip (get) that vector. */
+SW_API int sw_case_set_state(sw_case* c, const double* u, const double* v, const double* a, int64_t step);
+SW_API int sw_case_get_state(const sw_case* c, double* u, double* v, double* a, int64_t* step);
+
+/* March n steps (synchronous on return).  Fails with SW_ESTATE beyond the
+ * case's n_steps capacity. */
+SW_API int sw_case_step(sw_case* c, int32_t n);
+
+typedef struct {
+  int64_t steps;             /* steps completed */
+  int64_t cg_iters;          /* total CG iterations (inner iterations for mixed) */
+  int64_t ir_outer;          /* total FP64 true-residual evaluations */
+  double max_true_rel_res;   /* max over steps of ||b - A du|| / ||b|| (FP64) */
+  int32_t flags;             /* SW_FLAG_* */
+} sw_case_stats;
+
+SW_API int sw_case_stats_get(const sw_case* c, sw_case_stats* out);
+/* Per-step log for steps step0+1 .. step0+n: CG iterations and the final
+ * FP64 relative residual (host arrays; either may be NULL). */
+SW_API int sw_case_step_log(const sw_case* c, int64_t step0, int64_t n, int32_t* iters, double* rel_res);
+
+/* Receiver velocities of steps step0+1 .. step0+n into host out
+ * (n x n_rec x 3). */
+SW_API int sw_case_waveforms(const sw_case* c, int64_t step0, int64_t n, double* out);
+/* Device pointer of the waveform buffer (n_steps x n_rec x 3, FP64). */
+SW_API int sw_case_waveform_device(const sw_case* c, const double** out);
+
+/* y = op x for device vectors of 3*n_nodes doubles (op: SW_OP_*),
+ * synchronous.  For testing and for callers composing their own solvers. */
+SW_API int sw_case_apply(sw_case* c, int32_t op, const double* x_dev, double* y_dev);
+/* Same with the FP32 operator used by the SW_MIXED_FP32 inner solve. */
+SW_API int sw_case_apply_f32(sw_case* c, int32_t op, const float* x_dev, float* y_dev);
+/* Right-hand side b of the next step (from the current state) into y_dev. */
+SW_API int sw_case_rhs(sw_case* c, double* y_dev);
+/* Diagonal 3x3 blocks of A, 6 doubles per node (xx yy zz yz xz xy), into y_dev. */
+SW_API int sw_case_diag_blocks(sw_case* c, double* y_dev);
+
+/* ERR of Eq. (eqerr) between device waveforms U and obs (n_steps x n_rec x
+ * 3, FP64): the mean over (receiver, component) pairs of
+ * ||U - obs||_2 / ||obs||_2 over time.  Pairs whose observed norm is <=
+ * 1e-12 of the largest are skipped; the mean is over the pairs used
+ * (*n_pairs).  dev_ws: device scratch of sw_misfit_workspace_bytes(n_rec)
+ * bytes, 8-byte aligned.  Synchronous; result to host. */
+SW_API int sw_misfit_workspace_bytes(int32_t n_rec, size_t* bytes);
+SW_API int sw_misfit(sw_ctx* ctx, int32_t n_rec, int64_t n_steps, const double* U_dev, const double* obs_dev,
+              void* dev_ws, size_t ws_bytes, double* err, int32_t* n_pairs);
+/* ERR of the case's recorded waveforms (steps 1..current) against obs_dev
+ * (same layout, at least as many steps), using the case's own scratch. */
+SW_API int sw_case_misfit(sw_case* c, const double* obs_dev, double* err, int32_t* n_pairs);
+
+/* ----------------------------------------------------------------- batch */
+
+/* A batch marches several cases together.  Cases that share a mesh, a
+ * precision and a guess kind are fused into lane groups whose kernels read
+ * the mesh once per operator application for all lanes. */
+SW_API int sw_batch_workspace_bytes(sw_case* const* cases, int32_t n, size_t* bytes);
+SW_API int sw_batch_create(sw_ctx* ctx, sw_case* const* cases, int32_t n, void* dev_ws, size_t ws_bytes,
+                    sw_batch** out);
+SW_API int sw_batch_step(sw_batch* b, int32_t n_steps);
+SW_API int sw_batch_destroy(sw_batch* b);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SW_H */

@@ -1,0 +1,261 @@
+"""MI355X implicit seismic-wave analysis: Python binding of libsw.
+
+Argument marshalling only: every step of the analysis runs in the HIP
+kernels of libsw.so.  PyTorch supplies device memory (caller-owned
+workspaces) and the stream.  Importing this package does not load the
+library; the first object created does, and fails loudly if the library is
+not built or no HIP device is present.
+
+Typical use::
+
+    ctx = Context()
+    mesh = Mesh(ctx, m)            # m: xyz, tet10, tri6, face_tet, face_role arrays
+    case = Case(ctx, mesh, c)      # c: mat, tet_mat, rec_node, v_in, dt, ray_alpha, ray_beta
+    case.step(c.n_steps)
+    w = case.waveforms()           # (n_steps, n_rec, 3) receiver velocities
+"""
+from __future__ import annotations
+
+import ctypes as C
+
+import numpy as np
+
+from . import _lib as L
+from ._lib import SwError  # noqa: F401
+
+PRECISIONS = {"fp64": L.SW_FP64, "mixed": L.SW_MIXED_FP32, "mixed_fp32": L.SW_MIXED_FP32}
+GUESSES = {"zero": L.SW_GUESS_ZERO, "poly": L.SW_GUESS_POLY, "mlp": L.SW_GUESS_MLP}
+OPS = {"M": L.SW_OP_M, "K": L.SW_OP_K, "Cabs": L.SW_OP_CABS, "A": L.SW_OP_A}
+
+
+def _torch():
+    import torch
+    if not torch.cuda.is_available():
+        raise RuntimeError("no HIP device visible: the analysis runs only on the GPU")
+    return torch
+
+
+def _ptr(a):
+    return C.c_void_p(a.ctypes.data) if isinstance(a, np.ndarray) else C.c_void_p(a.data_ptr())
+
+
+def _workspace(nbytes, device):
+    torch = _torch()
+    # 256-byte aligned base (torch's caching allocator aligns to >= 512 B)
+    t = torch.empty(max(int(nbytes), 256), dtype=torch.uint8, device=device)
+    assert t.data_ptr() % 256 == 0
+    return t
+
+
+class Context:
+    def __init__(self, device: int = 0, stream=None):
+        torch = _torch()
+        self.lib = L.load()
+        self.device = torch.device("cuda", device)
+        if stream is None:
+            stream = torch.cuda.current_stream(self.device)
+        self.stream = stream
+        h = C.c_void_p()
+        L.check(self.lib.sw_ctx_create(device, C.c_void_p(stream.cuda_stream), C.byref(h)))
+        self.h = h
+
+    def __del__(self):
+        if getattr(self, "h", None):
+            self.lib.sw_ctx_destroy(self.h)
+            self.h = None
+
+
+class Mesh:
+    def __init__(self, ctx: Context, m):
+        self.ctx = ctx
+        lib = ctx.lib
+        self._xyz = np.ascontiguousarray(m.xyz, np.float64)
+        self._tet = np.ascontiguousarray(m.tet10, np.int32)
+        self._tri = np.ascontiguousarray(m.tri6, np.int32).reshape(-1, 6)
+        self._ft = np.ascontiguousarray(m.face_tet, np.int32)
+        self._fr = np.ascontiguousarray(m.face_role, np.uint8)
+        self.n_nodes, self.n_tets, self.n_faces = len(self._xyz), len(self._tet), len(self._tri)
+        d = L.MeshDesc(self.n_nodes, self.n_tets, self.n_faces, _ptr(self._xyz), _ptr(self._tet),
+                       _ptr(self._tri), _ptr(self._ft), _ptr(self._fr))
+        nb = C.c_size_t()
+        L.check(lib.sw_mesh_workspace_bytes(C.byref(d), C.byref(nb)))
+        self.ws = _workspace(nb.value, ctx.device)
+        h = C.c_void_p()
+        L.check(lib.sw_mesh_create(ctx.h, C.byref(d), C.c_void_p(self.ws.data_ptr()), nb.value, C.byref(h)))
+        self.h = h
+        del self._xyz, self._tet, self._tri, self._ft, self._fr
+
+    def __del__(self):
+        if getattr(self, "h", None):
+            self.ctx.lib.sw_mesh_destroy(self.h)
+            self.h = None
+
+
+class Case:
+    """One analysis on ``mesh``.  ``c`` provides mat, tet_mat, rec_node,
+    v_in ((n_steps+1) x 3), dt, ray_alpha, ray_beta (and n_steps)."""
+
+    def __init__(self, ctx: Context, mesh: Mesh, c, rtol=1e-8, max_iter=10000, precision="fp64",
+                 guess="zero", poly_order=2, inner_rtol=0.0, n_steps=None):
+        self.ctx, self.mesh = ctx, mesh
+        lib = ctx.lib
+        v_in = np.ascontiguousarray(c.v_in, np.float64)
+        n_steps = (len(v_in) - 1) if n_steps is None else int(n_steps)
+        if len(v_in) < n_steps + 1:
+            raise ValueError("v_in shorter than n_steps + 1")
+        v_in = np.ascontiguousarray(v_in[: n_steps + 1])
+        mat = np.ascontiguousarray(c.mat, np.float64)
+        tet_mat = np.ascontiguousarray(c.tet_mat, np.uint8)
+        rec = np.ascontiguousarray(c.rec_node, np.int32)
+        self.n_rec, self.n_steps = len(rec), n_steps
+        self.n_dof = 3 * mesh.n_nodes
+        d = L.CaseDesc(float(c.dt), float(c.ray_alpha), float(c.ray_beta), float(rtol), int(max_iter),
+                       PRECISIONS[precision], GUESSES[guess], int(poly_order), float(inner_rtol),
+                       len(mat), _ptr(mat), _ptr(tet_mat), len(rec), _ptr(rec), n_steps, _ptr(v_in))
+        nb = C.c_size_t()
+        L.check(lib.sw_case_workspace_bytes(mesh.h, C.byref(d), C.byref(nb)))
+        self.ws_bytes = nb.value
+        self.ws = _workspace(nb.value, ctx.device)
+        h = C.c_void_p()
+        L.check(lib.sw_case_create(ctx.h, mesh.h, C.byref(d), C.c_void_p(self.ws.data_ptr()), nb.value,
+                                   C.byref(h)))
+        self.h = h
+
+    def __del__(self):
+        if getattr(self, "h", None):
+            self.ctx.lib.sw_case_destroy(self.h)
+            self.h = None
+
+    # -- march
+    def step(self, n=1):
+        L.check(self.ctx.lib.sw_case_step(self.h, int(n)))
+
+    def stats(self):
+        s = L.CaseStats()
+        L.check(self.ctx.lib.sw_case_stats_get(self.h, C.byref(s)))
+        return dict(steps=s.steps, cg_iters=s.cg_iters, ir_outer=s.ir_outer,
+                    max_true_rel_res=s.max_true_rel_res, flags=s.flags)
+
+    def step_log(self, step0=0, n=None):
+        n = self.stats()["steps"] - step0 if n is None else n
+        it = np.zeros(n, np.int32)
+        rel = np.zeros(n, np.float64)
+        L.check(self.ctx.lib.sw_case_step_log(self.h, step0, n, _ptr(it), _ptr(rel)))
+        return it, rel
+
+    def waveforms(self, step0=0, n=None):
+        n = self.stats()["steps"] - step0 if n is None else n
+        out = np.zeros((n, self.n_rec, 3))
+        L.check(self.ctx.lib.sw_case_waveforms(self.h, step0, n, _ptr(out)))
+        return out
+
+    def waveform_device(self):
+        """Device waveform buffer as a torch tensor view (n_steps, n_rec, 3)."""
+        torch = _torch()
+        p = C.c_void_p()
+        L.check(self.ctx.lib.sw_case_waveform_device(self.h, C.byref(p)))
+        base = self.ws.data_ptr()
+        off = p.value - base
+        n = self.n_steps * self.n_rec * 3
+        return self.ws[off: off + 8 * n].view(torch.float64).view(self.n_steps, self.n_rec, 3)
+
+    # -- state
+    def set_state(self, u=None, v=None, a=None, step=0):
+        arr = [None if x is None else np.ascontiguousarray(x, np.float64) for x in (u, v, a)]
+        ptrs = [C.c_void_p(0) if x is None else _ptr(x) for x in arr]
+        L.check(self.ctx.lib.sw_case_set_state(self.h, *ptrs, int(step)))
+
+    def get_state(self):
+        u, v, a = (np.zeros(self.n_dof) for _ in range(3))
+        st = C.c_int64()
+        L.check(self.ctx.lib.sw_case_get_state(self.h, _ptr(u), _ptr(v), _ptr(a), C.byref(st)))
+        return u, v, a, st.value
+
+    # -- operators (device tensors)
+    def _vec(self, x, dtype):
+        torch = _torch()
+        x = x.to(self.ctx.device, dtype).contiguous().reshape(-1)
+        if x.numel() != self.n_dof:
+            raise ValueError(f"vector has {x.numel()} entries, expected {self.n_dof}")
+        return x
+
+    def apply(self, op, x):
+        torch = _torch()
+        x = self._vec(x, torch.float64)
+        y = torch.empty_like(x)
+        mask = op if isinstance(op, int) else sum(OPS[o] for o in op.split("+"))
+        L.check(self.ctx.lib.sw_case_apply(self.h, mask, C.c_void_p(x.data_ptr()), C.c_void_p(y.data_ptr())))
+        return y
+
+    def apply_f32(self, op, x):
+        torch = _torch()
+        x = self._vec(x, torch.float32)
+        y = torch.empty_like(x)
+        mask = op if isinstance(op, int) else sum(OPS[o] for o in op.split("+"))
+        L.check(self.ctx.lib.sw_case_apply_f32(self.h, mask, C.c_void_p(x.data_ptr()), C.c_void_p(y.data_ptr())))
+        return y
+
+    def rhs(self):
+        torch = _torch()
+        y = torch.empty(self.n_dof, dtype=torch.float64, device=self.ctx.device)
+        L.check(self.ctx.lib.sw_case_rhs(self.h, C.c_void_p(y.data_ptr())))
+        return y
+
+    def diag_blocks(self):
+        torch = _torch()
+        y = torch.empty(self.mesh.n_nodes * 6, dtype=torch.float64, device=self.ctx.device)
+        L.check(self.ctx.lib.sw_case_diag_blocks(self.h, C.c_void_p(y.data_ptr())))
+        return y.view(-1, 6)
+
+    def misfit(self, obs):
+        """ERR of the recorded waveforms against obs (device tensor)."""
+        torch = _torch()
+        obs = obs.to(self.ctx.device, torch.float64).contiguous()
+        need = self.stats()["steps"] * self.n_rec * 3
+        if obs.numel() < need or (obs.dim() == 3 and obs.shape[1:] != (self.n_rec, 3)):
+            raise ValueError(f"obs must hold at least {need} values laid out (steps, {self.n_rec}, 3)")
+        e = C.c_double()
+        n = C.c_int32()
+        L.check(self.ctx.lib.sw_case_misfit(self.h, C.c_void_p(obs.data_ptr()), C.byref(e), C.byref(n)))
+        return e.value, n.value
+
+
+def misfit(ctx: Context, U, obs):
+    """ERR of Eq. (eqerr) between device waveforms U and obs, (n_steps, n_rec, 3)."""
+    torch = _torch()
+    U = U.to(ctx.device, torch.float64).contiguous()
+    obs = obs.to(ctx.device, torch.float64).contiguous()
+    if U.dim() != 3 or U.shape != obs.shape or U.shape[2] != 3:
+        raise ValueError("U and obs must both be (n_steps, n_rec, 3)")
+    n_steps, n_rec = U.shape[0], U.shape[1]
+    nb = C.c_size_t()
+    L.check(ctx.lib.sw_misfit_workspace_bytes(n_rec, C.byref(nb)))
+    ws = _workspace(nb.value, ctx.device)
+    e = C.c_double()
+    n = C.c_int32()
+    L.check(ctx.lib.sw_misfit(ctx.h, n_rec, n_steps, C.c_void_p(U.data_ptr()), C.c_void_p(obs.data_ptr()),
+                              C.c_void_p(ws.data_ptr()), nb.value, C.byref(e), C.byref(n)))
+    return e.value, n.value
+
+
+class Batch:
+    """Several cases marched together (see sw_batch_* in include/sw.h)."""
+
+    def __init__(self, ctx: Context, cases):
+        self.ctx, self.cases = ctx, list(cases)
+        arr = (C.c_void_p * len(self.cases))(*[c.h.value for c in self.cases])
+        nb = C.c_size_t()
+        L.check(ctx.lib.sw_batch_workspace_bytes(arr, len(self.cases), C.byref(nb)))
+        self.ws = _workspace(nb.value, ctx.device)
+        h = C.c_void_p()
+        L.check(ctx.lib.sw_batch_create(ctx.h, arr, len(self.cases), C.c_void_p(self.ws.data_ptr()), nb.value,
+                                        C.byref(h)))
+        self.h = h
+
+    def step(self, n=1):
+        L.check(self.ctx.lib.sw_batch_step(self.h, int(n)))
+
+    def __del__(self):
+        if getattr(self, "h", None):
+            self.ctx.lib.sw_batch_destroy(self.h)
+            self.h = None

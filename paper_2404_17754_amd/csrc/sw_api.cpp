@@ -1,0 +1,877 @@
+// C-ABI runtime of the implicit wave-propagation library: validation,
+// workspace layout, preconditioner setup and the per-step driver.
+//
+// Per step (Newmark average acceleration, Section 3):
+//   1. right-hand side b = F^{n+1} + M (a + (4/dt + alpha) v) - K (u - beta v)
+//      + C_abs v  (one EBE pass with two inputs + one face pass)
+//   2. ||b||^2, tolerance, initial guess
+//   3. preconditioned CG on A du = b in chunks of iterations that run with
+//      no host round trip (device-side convergence flag); FP64, or FP32 inner
+//      solves inside FP64 iterative refinement
+//   4. FP64 true residual ||b - A du|| / ||b|| checked against rtol
+//   5. Newmark update of (u, v, a), increment history, receiver record.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/sw.h"
+#include "sw_internal.h"
+
+using namespace sw;
+
+// ------------------------------------------------------------ errors
+
+static thread_local std::string g_err = "no error";
+
+static int fail(int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return code;
+}
+
+#define HIPC(expr)                                                                                  \
+  do {                                                                                              \
+    hipError_t _e = (expr);                                                                         \
+    if (_e != hipSuccess) return fail(SW_EHIP, "%s failed: %s", #expr, hipGetErrorString(_e)); \
+  } while (0)
+
+#define LAUNCHED()                                                                                       \
+  do {                                                                                                   \
+    hipError_t _e = hipGetLastError();                                                                   \
+    if (_e != hipSuccess) return fail(SW_EHIP, "kernel launch failed: %s", hipGetErrorString(_e)); \
+  } while (0)
+
+extern "C" const char* sw_last_error(void) { return g_err.c_str(); }
+extern "C" const char* sw_version(void) { return "sw 0.1 (gfx950)"; }
+
+// ------------------------------------------------------------ workspace
+
+namespace {
+
+struct Carver {
+  uint8_t* base;
+  size_t off = 0;
+  explicit Carver(void* b) : base((uint8_t*)b) {}
+  template <typename T>
+  T* take(size_t count) {
+    off = (off + 255) & ~(size_t)255;
+    T* p = base ? (T*)(base + off) : nullptr;
+    off += count * sizeof(T);
+    return p;
+  }
+};
+
+inline int64_t pad64(int64_t n) { return (n + 63) / 64 * 64; }
+
+}  // namespace
+
+// ------------------------------------------------------------ objects
+
+struct sw_ctx {
+  int device;
+  hipStream_t stream;
+};
+
+struct sw_mesh {
+  sw_ctx* ctx;
+  MeshDev dev;
+  int64_t n_nodes, n_tets, n_faces;
+};
+
+struct sw_case {
+  sw_ctx* ctx;
+  sw_mesh* mesh;
+  // parameters
+  double dt, alpha, beta, rtol, inner_rtol;
+  int32_t max_iter, precision, guess, poly_order, n_mat, n_rec;
+  int64_t n_steps;
+  double cM, cK, cC;
+  // device
+  MatDev* mats;
+  uint8_t* tet_mat;
+  int32_t* rec;
+  double* vin;
+  double *u, *v, *a, *b, *x, *r, *z, *p, *q;
+  double* hist;  // [4][n_dof]
+  double *diag6, *pinv64;
+  float* pinv32;
+  float *r32, *d32, *z32, *p32, *q32;
+  double* wave;
+  int32_t* log_it;
+  double* log_rel;
+  CgCtl *ctl64, *ctl32;
+  int32_t* bad;
+  double* mis_buf;
+  double* mis_out;
+  // host state
+  int64_t step = 0;
+  int hist_head = 3, hist_count = 0;
+  int last_iters = 16;
+  sw_case_stats stats{};
+};
+
+struct sw_batch {
+  sw_ctx* ctx;
+  std::vector<sw_case*> cases;
+};
+
+extern "C" int sw_ctx_create(int device, void* hip_stream, sw_ctx** out) {
+  if (!out) return fail(SW_EINVAL, "out is NULL");
+  int n = 0;
+  HIPC(hipGetDeviceCount(&n));
+  if (device < 0 || device >= n) return fail(SW_EINVAL, "device %d out of range (%d devices)", device, n);
+  HIPC(hipSetDevice(device));
+  sw_ctx* c = new sw_ctx{device, (hipStream_t)hip_stream};
+  *out = c;
+  return SW_OK;
+}
+
+extern "C" int sw_ctx_destroy(sw_ctx* ctx) {
+  delete ctx;
+  return SW_OK;
+}
+
+// ------------------------------------------------------------ mesh
+
+static size_t mesh_layout(const sw_mesh_desc* d, Carver& cv, MeshDev* md) {
+  const int64_t ts = pad64(d->n_tets), fs = pad64(std::max<int64_t>(d->n_faces, 1));
+  auto conn = cv.take<int32_t>(10 * ts);
+  auto xyz = cv.take<double>(3 * d->n_nodes);
+  auto fconn = cv.take<int32_t>(6 * fs);
+  auto ftet = cv.take<int32_t>(fs);
+  auto frole = cv.take<uint8_t>(fs);
+  if (md) {
+    md->n_nodes = d->n_nodes;
+    md->n_tets = d->n_tets;
+    md->n_faces = d->n_faces;
+    md->tet_stride = ts;
+    md->face_stride = fs;
+    md->conn = conn;
+    md->xyz = xyz;
+    md->fconn = fconn;
+    md->face_tet = ftet;
+    md->face_role = frole;
+  }
+  return cv.off;
+}
+
+static int validate_mesh(const sw_mesh_desc* d) {
+  if (!d) return fail(SW_EINVAL, "mesh desc is NULL");
+  if (d->n_nodes <= 0 || d->n_tets <= 0 || d->n_faces < 0)
+    return fail(SW_EINVAL, "bad mesh sizes (nodes %lld tets %lld faces %lld)", (long long)d->n_nodes,
+                (long long)d->n_tets, (long long)d->n_faces);
+  if (d->n_nodes > (int64_t)INT32_MAX / 3) return fail(SW_EINVAL, "too many nodes for int32 indexing");
+  if (!d->xyz || !d->tet10 || (d->n_faces > 0 && (!d->tri6 || !d->face_tet || !d->face_role)))
+    return fail(SW_EINVAL, "NULL mesh array");
+  for (int64_t i = 0; i < 3 * d->n_nodes; ++i)
+    if (!std::isfinite(d->xyz[i])) return fail(SW_EMESH, "non-finite coordinate at node %lld", (long long)(i / 3));
+  static const int EA[6] = {0, 1, 0, 0, 1, 2}, EB[6] = {1, 2, 2, 3, 3, 3};
+  for (int64_t e = 0; e < d->n_tets; ++e) {
+    const int32_t* t = d->tet10 + 10 * e;
+    for (int k = 0; k < 10; ++k)
+      if (t[k] < 0 || t[k] >= d->n_nodes)
+        return fail(SW_EMESH, "tet %lld node %d index %d out of range", (long long)e, k, t[k]);
+    const double* X[4];
+    for (int k = 0; k < 4; ++k) X[k] = d->xyz + 3 * (int64_t)t[k];
+    double c1[3], c2[3], c3[3];
+    for (int q = 0; q < 3; ++q) {
+      c1[q] = X[1][q] - X[0][q];
+      c2[q] = X[2][q] - X[0][q];
+      c3[q] = X[3][q] - X[0][q];
+    }
+    const double det = c1[0] * (c2[1] * c3[2] - c2[2] * c3[1]) - c1[1] * (c2[0] * c3[2] - c2[2] * c3[0]) +
+                       c1[2] * (c2[0] * c3[1] - c2[1] * c3[0]);
+    if (!(det > 0.0)) return fail(SW_EMESH, "tet %lld has non-positive volume (%g)", (long long)e, det / 6.0);
+    for (int k = 0; k < 6; ++k) {
+      const double* A = X[EA[k]];
+      const double* B = X[EB[k]];
+      const double* M = d->xyz + 3 * (int64_t)t[4 + k];
+      double len2 = 0.0, err2 = 0.0;
+      for (int q = 0; q < 3; ++q) {
+        len2 += (B[q] - A[q]) * (B[q] - A[q]);
+        const double m = 0.5 * (A[q] + B[q]) - M[q];
+        err2 += m * m;
+      }
+      if (err2 > 1e-18 * len2)
+        return fail(SW_EMESH, "tet %lld edge node %d is not at its edge midpoint", (long long)e, 4 + k);
+    }
+  }
+  for (int64_t f = 0; f < d->n_faces; ++f) {
+    const int32_t* tr = d->tri6 + 6 * f;
+    const int32_t ow = d->face_tet[f];
+    if (ow < 0 || ow >= d->n_tets) return fail(SW_EMESH, "face %lld owner %d out of range", (long long)f, ow);
+    if (d->face_role[f] != 1 && d->face_role[f] != 2)
+      return fail(SW_EMESH, "face %lld has role %d (expected 1 or 2)", (long long)f, (int)d->face_role[f]);
+    const int32_t* t = d->tet10 + 10 * (int64_t)ow;
+    for (int k = 0; k < 6; ++k) {
+      bool found = false;
+      for (int j = 0; j < 10; ++j) found |= (t[j] == tr[k]);
+      if (!found) return fail(SW_EMESH, "face %lld node %d is not a node of its tet", (long long)f, k);
+      if (k < 3) {
+        bool vert = false;
+        for (int j = 0; j < 4; ++j) vert |= (t[j] == tr[k]);
+        if (!vert) return fail(SW_EMESH, "face %lld vertex %d is not a vertex of its tet", (long long)f, k);
+      }
+    }
+  }
+  return SW_OK;
+}
+
+extern "C" int sw_mesh_workspace_bytes(const sw_mesh_desc* d, size_t* bytes) {
+  if (!d || !bytes) return fail(SW_EINVAL, "NULL argument");
+  if (d->n_nodes <= 0 || d->n_tets <= 0 || d->n_faces < 0) return fail(SW_EINVAL, "bad mesh sizes");
+  Carver cv(nullptr);
+  *bytes = mesh_layout(d, cv, nullptr);
+  return SW_OK;
+}
+
+extern "C" int sw_mesh_create(sw_ctx* ctx, const sw_mesh_desc* d, void* ws, size_t ws_bytes, sw_mesh** out) {
+  if (!ctx || !out) return fail(SW_EINVAL, "NULL argument");
+  int rc = validate_mesh(d);
+  if (rc) return rc;
+  Carver dry(nullptr);
+  const size_t need = mesh_layout(d, dry, nullptr);
+  if (!ws || ((uintptr_t)ws & 255)) return fail(SW_ENOWS, "mesh workspace NULL or not 256-byte aligned");
+  if (ws_bytes < need) return fail(SW_ENOWS, "mesh workspace %zu bytes < %zu needed", ws_bytes, need);
+  HIPC(hipSetDevice(ctx->device));
+  Carver cv(ws);
+  MeshDev md;
+  mesh_layout(d, cv, &md);
+  // element-coalesced connectivity: conn[k][e]
+  std::vector<int32_t> conn(10 * md.tet_stride, 0);
+  for (int64_t e = 0; e < d->n_tets; ++e)
+    for (int k = 0; k < 10; ++k) conn[k * md.tet_stride + e] = d->tet10[10 * e + k];
+  std::vector<int32_t> fconn(6 * md.face_stride, 0), ftet(md.face_stride, 0);
+  std::vector<uint8_t> frole(md.face_stride, 0);
+  for (int64_t f = 0; f < d->n_faces; ++f) {
+    for (int k = 0; k < 6; ++k) fconn[k * md.face_stride + f] = d->tri6[6 * f + k];
+    ftet[f] = d->face_tet[f];
+    frole[f] = d->face_role[f];
+  }
+  hipStream_t s = ctx->stream;
+  HIPC(hipMemcpyAsync((void*)md.conn, conn.data(), conn.size() * 4, hipMemcpyHostToDevice, s));
+  HIPC(hipMemcpyAsync((void*)md.xyz, d->xyz, 3 * d->n_nodes * 8, hipMemcpyHostToDevice, s));
+  HIPC(hipMemcpyAsync((void*)md.fconn, fconn.data(), fconn.size() * 4, hipMemcpyHostToDevice, s));
+  HIPC(hipMemcpyAsync((void*)md.face_tet, ftet.data(), ftet.size() * 4, hipMemcpyHostToDevice, s));
+  HIPC(hipMemcpyAsync((void*)md.face_role, frole.data(), frole.size(), hipMemcpyHostToDevice, s));
+  HIPC(hipStreamSynchronize(s));
+  sw_mesh* m = new sw_mesh{ctx, md, d->n_nodes, d->n_tets, d->n_faces};
+  *out = m;
+  return SW_OK;
+}
+
+extern "C" int sw_mesh_destroy(sw_mesh* m) {
+  delete m;
+  return SW_OK;
+}
+
+// ------------------------------------------------------------ case
+
+static size_t case_layout(const sw_mesh* m, const sw_case_desc* d, Carver& cv, sw_case* c) {
+  const int64_t nn = m->n_nodes, nd = 3 * nn;
+  const bool mixed = d->precision == SW_MIXED_FP32;
+  auto mats = cv.take<MatDev>(d->n_mat);
+  auto tm = cv.take<uint8_t>(m->n_tets);
+  auto rec = cv.take<int32_t>(std::max(d->n_rec, 1));
+  auto vin = cv.take<double>(3 * (d->n_steps + 1));
+  double* vec[9];
+  for (int i = 0; i < 9; ++i) vec[i] = cv.take<double>(nd);
+  auto hist = cv.take<double>(4 * nd);
+  auto diag6 = cv.take<double>(6 * nn);
+  auto pinv64 = cv.take<double>(6 * nn);
+  auto pinv32 = cv.take<float>(6 * nn);
+  float* f32[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
+  if (mixed)
+    for (int i = 0; i < 5; ++i) f32[i] = cv.take<float>(nd);
+  auto wave = cv.take<double>(std::max<int64_t>(d->n_steps * 3 * d->n_rec, 1));
+  auto log_it = cv.take<int32_t>(d->n_steps);
+  auto log_rel = cv.take<double>(d->n_steps);
+  auto ctl = cv.take<CgCtl>(2);
+  auto bad = cv.take<int32_t>(1);
+  auto mis_buf = cv.take<double>(2 * 3 * std::max(d->n_rec, 1));
+  auto mis_out = cv.take<double>(2);
+  if (c) {
+    c->mats = mats;
+    c->tet_mat = tm;
+    c->rec = rec;
+    c->vin = vin;
+    c->u = vec[0];
+    c->v = vec[1];
+    c->a = vec[2];
+    c->b = vec[3];
+    c->x = vec[4];
+    c->r = vec[5];
+    c->z = vec[6];
+    c->p = vec[7];
+    c->q = vec[8];
+    c->hist = hist;
+    c->diag6 = diag6;
+    c->pinv64 = pinv64;
+    c->pinv32 = pinv32;
+    c->r32 = f32[0];
+    c->d32 = f32[1];
+    c->z32 = f32[2];
+    c->p32 = f32[3];
+    c->q32 = f32[4];
+    c->wave = wave;
+    c->log_it = log_it;
+    c->log_rel = log_rel;
+    c->ctl64 = ctl;
+    c->ctl32 = ctl ? ctl + 1 : nullptr;
+    c->bad = bad;
+    c->mis_buf = mis_buf;
+    c->mis_out = mis_out;
+  }
+  return cv.off;
+}
+
+static int validate_case(const sw_mesh* m, const sw_case_desc* d) {
+  if (!m || !d) return fail(SW_EINVAL, "NULL argument");
+  if (!(d->dt > 0.0) || !std::isfinite(d->dt)) return fail(SW_EINVAL, "dt must be > 0");
+  if (!(d->ray_alpha >= 0.0) || !(d->ray_beta >= 0.0)) return fail(SW_EINVAL, "Rayleigh coefficients must be >= 0");
+  if (!(d->rtol > 0.0 && d->rtol < 1.0)) return fail(SW_EINVAL, "rtol must be in (0, 1)");
+  if (d->max_iter <= 0) return fail(SW_EINVAL, "max_iter must be > 0");
+  if (d->precision != SW_FP64 && d->precision != SW_MIXED_FP32) return fail(SW_EINVAL, "unknown precision %d", d->precision);
+  if (d->guess != SW_GUESS_ZERO && d->guess != SW_GUESS_POLY && d->guess != SW_GUESS_MLP)
+    return fail(SW_EINVAL, "unknown guess kind %d", d->guess);
+  if (d->guess == SW_GUESS_MLP) return fail(SW_EINVAL, "SW_GUESS_MLP needs an attached network");
+  if (d->poly_order < 0 || d->poly_order > 3) return fail(SW_EINVAL, "poly_order must be 0..3");
+  if (!(d->inner_rtol >= 0.0 && d->inner_rtol < 1.0)) return fail(SW_EINVAL, "inner_rtol must be in [0, 1)");
+  if (d->n_mat < 1 || d->n_mat > 255 || !d->mat) return fail(SW_EINVAL, "n_mat must be 1..255 with a table");
+  for (int i = 0; i < d->n_mat; ++i) {
+    const double vp = d->mat[3 * i], vs = d->mat[3 * i + 1], rho = d->mat[3 * i + 2];
+    if (!(vp > 0 && vs > 0 && rho > 0) || !(vp * vp > 4.0 / 3.0 * vs * vs))
+      return fail(SW_EINVAL, "material %d (Vp %g Vs %g rho %g) is not a valid elastic solid", i, vp, vs, rho);
+  }
+  if (!d->tet_mat) return fail(SW_EINVAL, "tet_mat is NULL");
+  for (int64_t e = 0; e < m->n_tets; ++e)
+    if (d->tet_mat[e] >= d->n_mat) return fail(SW_EINVAL, "tet %lld material %d >= n_mat", (long long)e, d->tet_mat[e]);
+  if (d->n_rec < 0 || (d->n_rec > 0 && !d->rec_node)) return fail(SW_EINVAL, "bad receivers");
+  for (int i = 0; i < d->n_rec; ++i)
+    if (d->rec_node[i] < 0 || d->rec_node[i] >= m->n_nodes) return fail(SW_EINVAL, "receiver %d node out of range", i);
+  if (d->n_steps < 1 || !d->v_in) return fail(SW_EINVAL, "n_steps must be >= 1 with a v_in array");
+  for (int64_t i = 0; i < 3 * (d->n_steps + 1); ++i)
+    if (!std::isfinite(d->v_in[i])) return fail(SW_EINVAL, "non-finite v_in");
+  return SW_OK;
+}
+
+extern "C" int sw_case_workspace_bytes(const sw_mesh* m, const sw_case_desc* d, size_t* bytes) {
+  if (!m || !d || !bytes) return fail(SW_EINVAL, "NULL argument");
+  if (d->n_mat < 1 || d->n_rec < 0 || d->n_steps < 1) return fail(SW_EINVAL, "bad case sizes");
+  Carver cv(nullptr);
+  *bytes = case_layout(m, d, cv, nullptr);
+  return SW_OK;
+}
+
+static int apply_op_f64(sw_case* c, int op, const double* x, double* y, CgCtl* ctl, int iter) {
+  const MeshDev& md = c->mesh->dev;
+  hipStream_t s = c->ctx->stream;
+  double sM, sK, sC;
+  if (op == SW_OP_A) {
+    sM = c->cM;
+    sK = c->cK;
+    sC = c->cC;
+  } else {
+    sM = (op & SW_OP_M) ? 1.0 : 0.0;
+    sK = (op & SW_OP_K) ? 1.0 : 0.0;
+    sC = (op & SW_OP_CABS) ? 1.0 : 0.0;
+  }
+  if (sM != 0.0 || sK != 0.0) launch_ebe_apply_f64(md, c->tet_mat, c->mats, sM, sK, x, y, ctl, iter, s);
+  if (sC != 0.0) launch_face_apply_f64(md, c->tet_mat, c->mats, sC, x, y, ctl, s);
+  LAUNCHED();
+  return SW_OK;
+}
+
+static int apply_op_f32(sw_case* c, int op, const float* x, float* y, CgCtl* ctl, int iter) {
+  const MeshDev& md = c->mesh->dev;
+  hipStream_t s = c->ctx->stream;
+  double sM, sK, sC;
+  if (op == SW_OP_A) {
+    sM = c->cM;
+    sK = c->cK;
+    sC = c->cC;
+  } else {
+    sM = (op & SW_OP_M) ? 1.0 : 0.0;
+    sK = (op & SW_OP_K) ? 1.0 : 0.0;
+    sC = (op & SW_OP_CABS) ? 1.0 : 0.0;
+  }
+  if (sM != 0.0 || sK != 0.0) launch_ebe_apply_f32(md, c->tet_mat, c->mats, sM, sK, x, y, ctl, iter, s);
+  if (sC != 0.0) launch_face_apply_f32(md, c->tet_mat, c->mats, sC, x, y, ctl, s);
+  LAUNCHED();
+  return SW_OK;
+}
+
+extern "C" int sw_case_create(sw_ctx* ctx, sw_mesh* m, const sw_case_desc* d, void* ws, size_t ws_bytes,
+                              sw_case** out) {
+  if (!ctx || !out) return fail(SW_EINVAL, "NULL argument");
+  int rc = validate_case(m, d);
+  if (rc) return rc;
+  Carver dry(nullptr);
+  const size_t need = case_layout(m, d, dry, nullptr);
+  if (!ws || ((uintptr_t)ws & 255)) return fail(SW_ENOWS, "case workspace NULL or not 256-byte aligned");
+  if (ws_bytes < need) return fail(SW_ENOWS, "case workspace %zu bytes < %zu needed", ws_bytes, need);
+  HIPC(hipSetDevice(ctx->device));
+  sw_case* c = new sw_case();
+  c->ctx = ctx;
+  c->mesh = m;
+  c->dt = d->dt;
+  c->alpha = d->ray_alpha;
+  c->beta = d->ray_beta;
+  c->rtol = d->rtol;
+  c->inner_rtol = d->inner_rtol > 0.0 ? d->inner_rtol : 1e-3;
+  c->max_iter = d->max_iter;
+  c->precision = d->precision;
+  c->guess = d->guess;
+  c->poly_order = d->poly_order;
+  c->n_mat = d->n_mat;
+  c->n_rec = d->n_rec;
+  c->n_steps = d->n_steps;
+  c->cM = 4.0 / (d->dt * d->dt) + 2.0 * d->ray_alpha / d->dt;
+  c->cK = 1.0 + 2.0 * d->ray_beta / d->dt;
+  c->cC = 2.0 / d->dt;
+  Carver cv(ws);
+  case_layout(m, d, cv, c);
+  hipStream_t s = ctx->stream;
+  std::vector<MatDev> mats(d->n_mat);
+  for (int i = 0; i < d->n_mat; ++i) {
+    const double vp = d->mat[3 * i], vs = d->mat[3 * i + 1], rho = d->mat[3 * i + 2];
+    mats[i].mu = rho * vs * vs;
+    mats[i].lam = rho * vp * vp - 2.0 * mats[i].mu;
+    mats[i].rho = rho;
+    mats[i].zp = rho * vp;
+    mats[i].zs = rho * vs;
+  }
+  const int64_t nn = m->n_nodes, nd = 3 * nn;
+  auto cleanup = [&](int code) {
+    delete c;
+    return code;
+  };
+#define HIPX(expr)                                                                                  \
+  do {                                                                                              \
+    hipError_t _e = (expr);                                                                         \
+    if (_e != hipSuccess) return cleanup(fail(SW_EHIP, "%s failed: %s", #expr, hipGetErrorString(_e))); \
+  } while (0)
+  HIPX(hipMemcpyAsync(c->mats, mats.data(), mats.size() * sizeof(MatDev), hipMemcpyHostToDevice, s));
+  HIPX(hipMemcpyAsync(c->tet_mat, d->tet_mat, m->n_tets, hipMemcpyHostToDevice, s));
+  if (d->n_rec > 0) HIPX(hipMemcpyAsync(c->rec, d->rec_node, 4 * (size_t)d->n_rec, hipMemcpyHostToDevice, s));
+  HIPX(hipMemcpyAsync(c->vin, d->v_in, 8 * 3 * (size_t)(d->n_steps + 1), hipMemcpyHostToDevice, s));
+  double* zero_vecs[] = {c->u, c->v, c->a, c->b, c->x, c->r, c->z, c->p, c->q};
+  for (double* zv : zero_vecs) launch_fill_f64(nd, zv, 0.0, s);
+  launch_fill_f64(4 * nd, c->hist, 0.0, s);
+  if (c->precision == SW_MIXED_FP32) {
+    float* zf[] = {c->r32, c->d32, c->z32, c->p32, c->q32};
+    for (float* zv : zf) launch_fill_f32(nd, zv, 0.0f, s);
+  }
+  launch_fill_f64(std::max<int64_t>(c->n_steps * 3 * c->n_rec, 1), c->wave, 0.0, s);
+  launch_fill_f64((int64_t)(2 * sizeof(CgCtl) / 8), (double*)c->ctl64, 0.0, s);
+  HIPX(hipMemsetAsync(c->log_it, 0, 4 * (size_t)c->n_steps, s));
+  launch_fill_f64(c->n_steps, c->log_rel, 0.0, s);
+  // preconditioner: inverse 3x3 diagonal blocks of A
+  launch_fill_f64(6 * nn, c->diag6, 0.0, s);
+  HIPX(hipMemsetAsync(c->bad, 0, 4, s));
+  launch_diag_blocks(m->dev, c->tet_mat, c->mats, c->cM, c->cK, c->cC, c->diag6, s);
+  launch_invert_blocks(nn, c->diag6, c->pinv64, c->pinv32, c->bad, s);
+  HIPX(hipGetLastError());
+  int32_t bad = 0;
+  HIPX(hipMemcpyAsync(&bad, c->bad, 4, hipMemcpyDeviceToHost, s));
+  HIPX(hipStreamSynchronize(s));
+  if (bad) return cleanup(fail(SW_EINVAL, "a diagonal block of the step operator is not positive definite"));
+#undef HIPX
+  *out = c;
+  return SW_OK;
+}
+
+extern "C" int sw_case_destroy(sw_case* c) {
+  delete c;
+  return SW_OK;
+}
+
+extern "C" int sw_case_set_state(sw_case* c, const double* u, const double* v, const double* a, int64_t step) {
+  if (!c) return fail(SW_EINVAL, "NULL case");
+  if (step < 0 || step > c->n_steps) return fail(SW_EINVAL, "step %lld out of range", (long long)step);
+  HIPC(hipSetDevice(c->ctx->device));
+  const size_t nb = 8 * 3 * (size_t)c->mesh->n_nodes;
+  hipStream_t s = c->ctx->stream;
+  if (u) HIPC(hipMemcpyAsync(c->u, u, nb, hipMemcpyHostToDevice, s));
+  if (v) HIPC(hipMemcpyAsync(c->v, v, nb, hipMemcpyHostToDevice, s));
+  if (a) HIPC(hipMemcpyAsync(c->a, a, nb, hipMemcpyHostToDevice, s));
+  launch_fill_f64(4 * 3 * c->mesh->n_nodes, c->hist, 0.0, s);
+  LAUNCHED();
+  HIPC(hipStreamSynchronize(s));
+  c->step = step;
+  c->hist_count = 0;
+  c->hist_head = 3;
+  return SW_OK;
+}
+
+extern "C" int sw_case_get_state(const sw_case* c, double* u, double* v, double* a, int64_t* step) {
+  if (!c) return fail(SW_EINVAL, "NULL case");
+  HIPC(hipSetDevice(c->ctx->device));
+  const size_t nb = 8 * 3 * (size_t)c->mesh->n_nodes;
+  hipStream_t s = c->ctx->stream;
+  if (u) HIPC(hipMemcpyAsync(u, c->u, nb, hipMemcpyDeviceToHost, s));
+  if (v) HIPC(hipMemcpyAsync(v, c->v, nb, hipMemcpyDeviceToHost, s));
+  if (a) HIPC(hipMemcpyAsync(a, c->a, nb, hipMemcpyDeviceToHost, s));
+  HIPC(hipStreamSynchronize(s));
+  if (step) *step = c->step;
+  return SW_OK;
+}
+
+// ------------------------------------------------------------ solver
+
+namespace {
+
+// Right-hand side of step c->step -> c->step + 1 into y (cleared first).
+int build_rhs(sw_case* c, double* y) {
+  const MeshDev& md = c->mesh->dev;
+  hipStream_t s = c->ctx->stream;
+  const int64_t nd = 3 * c->mesh->n_nodes;
+  launch_fill_f64(nd, y, 0.0, s);
+  launch_ebe_rhs(md, c->tet_mat, c->mats, 4.0 / c->dt + c->alpha, c->beta, c->u, c->v, c->a, y, s);
+  launch_face_rhs(md, c->tet_mat, c->mats, c->v, c->vin + 3 * (c->step + 1), y, s);
+  LAUNCHED();
+  return SW_OK;
+}
+
+int read_ctl(sw_case* c, CgCtl* dev, CgCtl* host) {
+  HIPC(hipMemcpyAsync(host, dev, sizeof(CgCtl), hipMemcpyDeviceToHost, c->ctx->stream));
+  HIPC(hipStreamSynchronize(c->ctx->stream));
+  return SW_OK;
+}
+
+// Runs CG iterations of the solve in `ctl` until its done flag is set.
+// iter_base: iterations already spent in this step (for the cap).
+template <bool F32>
+int cg_loop(sw_case* c, CgCtl* ctl, int iter_base, int first_chunk, int* iters_out) {
+  const int64_t nn = c->mesh->n_nodes;
+  hipStream_t s = c->ctx->stream;
+  int it = 0;
+  int chunk = std::max(4, first_chunk);
+  CgCtl h;
+  for (;;) {
+    for (int k = 0; k < chunk; ++k) {
+      const int i = it + k;
+      int rc;
+      if (F32) {
+        rc = apply_op_f32(c, SW_OP_A, c->p32, c->q32, ctl, i);
+        if (rc) return rc;
+        launch_cg_update_f32(nn, i & 1, c->pinv32, c->d32, c->r32, c->z32, c->p32, c->q32, ctl, s);
+        launch_cg_dir_f32(nn, i & 1, iter_base + i, c->max_iter, c->z32, c->p32, ctl, s);
+      } else {
+        rc = apply_op_f64(c, SW_OP_A, c->p, c->q, ctl, i);
+        if (rc) return rc;
+        launch_cg_update_f64(nn, i & 1, c->pinv64, c->x, c->r, c->z, c->p, c->q, ctl, s);
+        launch_cg_dir_f64(nn, i & 1, iter_base + i, c->max_iter, c->z, c->p, ctl, s);
+      }
+    }
+    LAUNCHED();
+    it += chunk;
+    int rc = read_ctl(c, ctl, &h);
+    if (rc) return rc;
+    if (h.done) break;
+    chunk = 8;
+  }
+  *iters_out = h.iters - iter_base > 0 ? h.iters - iter_base : 0;
+  return SW_OK;
+}
+
+// true residual of x64: q = A x, r = b - q, rr_true into ctl64 (FP64).
+// q keeps A x unless zero_q is set.
+int true_residual(sw_case* c, CgCtl* hctl, bool zero_q) {
+  hipStream_t s = c->ctx->stream;
+  const int64_t nd = 3 * c->mesh->n_nodes;
+  launch_fill_f64(1, &c->ctl64->rr_true, 0.0, s);
+  int rc = apply_op_f64(c, SW_OP_A, c->x, c->q, nullptr, -1);
+  if (rc) return rc;
+  launch_true_residual(nd, c->b, c->q, c->r, c->ctl64, s);
+  if (zero_q) launch_fill_f64(nd, c->q, 0.0, s);
+  LAUNCHED();
+  return read_ctl(c, c->ctl64, hctl);
+}
+
+int solve_step(sw_case* c, int* iters, int* outer, double* relres, int* flags) {
+  hipStream_t s = c->ctx->stream;
+  const int64_t nn = c->mesh->n_nodes, nd = 3 * nn;
+  *iters = 0;
+  *outer = 0;
+  *flags = 0;
+  int rc = build_rhs(c, c->b);
+  if (rc) return rc;
+  launch_fill_f64(1, &c->ctl64->bb, 0.0, s);
+  launch_norm2(nd, c->b, &c->ctl64->bb, s);
+  launch_ctl_prepare(c->ctl64, c->rtol, 0, s);
+  // initial guess
+  const bool use_poly = (c->guess == SW_GUESS_POLY) && c->hist_count > 0;
+  if (use_poly) {
+    const int order = std::min(c->poly_order, c->hist_count - 1);
+    launch_guess_poly(nd, c->hist, c->hist_head, order, c->x, c->ctl64, s);
+  } else {
+    launch_fill_f64(nd, c->x, 0.0, s);
+  }
+  LAUNCHED();
+  CgCtl h;
+  if (c->precision == SW_FP64) {
+    if (use_poly) {
+      rc = apply_op_f64(c, SW_OP_A, c->x, c->q, nullptr, -1);
+      if (rc) return rc;
+      launch_cg_init_f64(nn, c->b, c->q, c->pinv64, c->r, c->z, c->p, c->q, c->ctl64, s);
+    } else {
+      launch_cg_init_f64(nn, c->b, nullptr, c->pinv64, c->r, c->z, c->p, nullptr, c->ctl64, s);
+    }
+    LAUNCHED();
+    for (;;) {
+      int it = 0;
+      rc = cg_loop<false>(c, c->ctl64, *iters, std::max(4, c->last_iters - *iters), &it);
+      if (rc) return rc;
+      *iters += it;
+      rc = true_residual(c, &h, false);
+      if (rc) return rc;
+      ++*outer;
+      bool stop = false;
+      if (!(h.rr_true == h.rr_true)) {
+        *flags |= SW_FLAG_NONFINITE;
+        stop = true;
+      } else if (h.rr_true <= c->rtol * c->rtol * h.bb) {
+        stop = true;
+      } else if (*iters >= c->max_iter) {
+        *flags |= SW_FLAG_NOCONV;
+        stop = true;
+      }
+      if (stop) {
+        launch_fill_f64(nd, c->q, 0.0, s);
+        LAUNCHED();
+        break;
+      }
+      // restart CG from the current iterate on the true residual b - A x
+      launch_ctl_prepare(c->ctl64, c->rtol, 0, s);
+      launch_cg_init_f64(nn, c->b, c->q, c->pinv64, c->r, c->z, c->p, c->q, c->ctl64, s);
+      LAUNCHED();
+    }
+  } else {
+    for (;;) {
+      rc = true_residual(c, &h, true);
+      if (rc) return rc;
+      ++*outer;
+      if (!(h.rr_true == h.rr_true)) {
+        *flags |= SW_FLAG_NONFINITE;
+        break;
+      }
+      if (h.rr_true <= c->rtol * c->rtol * h.bb) break;
+      if (*iters >= c->max_iter) {
+        *flags |= SW_FLAG_NOCONV;
+        break;
+      }
+      launch_to_f32_scaled(nd, c->r, c->r32, c->ctl64, s);
+      launch_fill_f64(sizeof(CgCtl) / 8, (double*)c->ctl32, 0.0, s);
+      launch_fill_f64(1, &c->ctl32->bb, 1.0, s);
+      launch_ctl_prepare(c->ctl32, c->inner_rtol, 0, s);
+      launch_fill_f32(nd, c->d32, 0.0f, s);
+      launch_cg_init_f32(nn, c->r32, nullptr, c->pinv32, c->r32, c->z32, c->p32, nullptr, c->ctl32, s);
+      LAUNCHED();
+      int it = 0;
+      rc = cg_loop<true>(c, c->ctl32, *iters, std::max(4, c->last_iters / 2), &it);
+      if (rc) return rc;
+      *iters += it;
+      launch_ir_update(nd, c->x, c->d32, c->ctl64, s);
+      LAUNCHED();
+    }
+  }
+  *relres = h.bb > 0.0 ? std::sqrt(h.rr_true / h.bb) : 0.0;
+  return SW_OK;
+}
+
+}  // namespace
+
+extern "C" int sw_case_step(sw_case* c, int32_t n) {
+  if (!c) return fail(SW_EINVAL, "NULL case");
+  if (n < 0) return fail(SW_EINVAL, "negative step count");
+  if (c->step + n > c->n_steps)
+    return fail(SW_ESTATE, "stepping to %lld exceeds the case capacity of %lld steps", (long long)(c->step + n),
+                (long long)c->n_steps);
+  HIPC(hipSetDevice(c->ctx->device));
+  hipStream_t s = c->ctx->stream;
+  const int64_t nd = 3 * c->mesh->n_nodes;
+  for (int k = 0; k < n; ++k) {
+    int iters, outer, flags;
+    double rel;
+    int rc = solve_step(c, &iters, &outer, &rel, &flags);
+    if (rc) return rc;
+    const int head = (c->hist_head + 1) & 3;
+    launch_newmark(nd, c->dt, c->x, c->u, c->v, c->a, c->hist + head * nd, s);
+    launch_record(c->n_rec, c->rec, c->v, c->wave + c->step * 3 * c->n_rec, s);
+    LAUNCHED();
+    c->hist_head = head;
+    c->hist_count = std::min(c->hist_count + 1, 4);
+    const int32_t it32 = iters;
+    HIPC(hipMemcpyAsync(c->log_it + c->step, &it32, 4, hipMemcpyHostToDevice, s));
+    HIPC(hipMemcpyAsync(c->log_rel + c->step, &rel, 8, hipMemcpyHostToDevice, s));
+    HIPC(hipStreamSynchronize(s));
+    c->step += 1;
+    c->last_iters = std::max(4, iters);
+    c->stats.steps += 1;
+    c->stats.cg_iters += iters;
+    c->stats.ir_outer += outer;
+    c->stats.max_true_rel_res = std::max(c->stats.max_true_rel_res, rel);
+    c->stats.flags |= flags;
+  }
+  return SW_OK;
+}
+
+extern "C" int sw_case_stats_get(const sw_case* c, sw_case_stats* out) {
+  if (!c || !out) return fail(SW_EINVAL, "NULL argument");
+  *out = c->stats;
+  return SW_OK;
+}
+
+extern "C" int sw_case_step_log(const sw_case* c, int64_t step0, int64_t n, int32_t* iters, double* rel) {
+  if (!c) return fail(SW_EINVAL, "NULL case");
+  if (step0 < 0 || n < 0 || step0 + n > c->step) return fail(SW_EINVAL, "log range outside the completed steps");
+  if (n == 0) return SW_OK;
+  HIPC(hipSetDevice(c->ctx->device));
+  hipStream_t s = c->ctx->stream;
+  if (iters) HIPC(hipMemcpyAsync(iters, c->log_it + step0, 4 * (size_t)n, hipMemcpyDeviceToHost, s));
+  if (rel) HIPC(hipMemcpyAsync(rel, c->log_rel + step0, 8 * (size_t)n, hipMemcpyDeviceToHost, s));
+  HIPC(hipStreamSynchronize(s));
+  return SW_OK;
+}
+
+extern "C" int sw_case_waveforms(const sw_case* c, int64_t step0, int64_t n, double* out) {
+  if (!c || !out) return fail(SW_EINVAL, "NULL argument");
+  if (step0 < 0 || n < 0 || step0 + n > c->n_steps) return fail(SW_EINVAL, "waveform range out of bounds");
+  if (n == 0 || c->n_rec == 0) return SW_OK;
+  HIPC(hipSetDevice(c->ctx->device));
+  HIPC(hipMemcpyAsync(out, c->wave + step0 * 3 * c->n_rec, 8 * 3 * (size_t)c->n_rec * n, hipMemcpyDeviceToHost,
+                      c->ctx->stream));
+  HIPC(hipStreamSynchronize(c->ctx->stream));
+  return SW_OK;
+}
+
+extern "C" int sw_case_waveform_device(const sw_case* c, const double** out) {
+  if (!c || !out) return fail(SW_EINVAL, "NULL argument");
+  *out = c->wave;
+  return SW_OK;
+}
+
+extern "C" int sw_case_apply(sw_case* c, int32_t op, const double* x, double* y) {
+  if (!c || !x || !y) return fail(SW_EINVAL, "NULL argument");
+  if (!(op == SW_OP_A || (op > 0 && op < 8))) return fail(SW_EINVAL, "bad operator mask %d", op);
+  HIPC(hipSetDevice(c->ctx->device));
+  launch_fill_f64(3 * c->mesh->n_nodes, y, 0.0, c->ctx->stream);
+  int rc = apply_op_f64(c, op, x, y, nullptr, -1);
+  if (rc) return rc;
+  HIPC(hipStreamSynchronize(c->ctx->stream));
+  return SW_OK;
+}
+
+extern "C" int sw_case_apply_f32(sw_case* c, int32_t op, const float* x, float* y) {
+  if (!c || !x || !y) return fail(SW_EINVAL, "NULL argument");
+  if (!(op == SW_OP_A || (op > 0 && op < 8))) return fail(SW_EINVAL, "bad operator mask %d", op);
+  HIPC(hipSetDevice(c->ctx->device));
+  launch_fill_f32(3 * c->mesh->n_nodes, y, 0.0f, c->ctx->stream);
+  int rc = apply_op_f32(c, op, x, y, nullptr, -1);
+  if (rc) return rc;
+  HIPC(hipStreamSynchronize(c->ctx->stream));
+  return SW_OK;
+}
+
+extern "C" int sw_case_rhs(sw_case* c, double* y) {
+  if (!c || !y) return fail(SW_EINVAL, "NULL argument");
+  if (c->step >= c->n_steps) return fail(SW_ESTATE, "no further step in the case capacity");
+  HIPC(hipSetDevice(c->ctx->device));
+  int rc = build_rhs(c, y);
+  if (rc) return rc;
+  HIPC(hipStreamSynchronize(c->ctx->stream));
+  return SW_OK;
+}
+
+extern "C" int sw_case_diag_blocks(sw_case* c, double* y) {
+  if (!c || !y) return fail(SW_EINVAL, "NULL argument");
+  HIPC(hipSetDevice(c->ctx->device));
+  HIPC(hipMemcpyAsync(y, c->diag6, 8 * 6 * (size_t)c->mesh->n_nodes, hipMemcpyDeviceToDevice, c->ctx->stream));
+  HIPC(hipStreamSynchronize(c->ctx->stream));
+  return SW_OK;
+}
+
+// ------------------------------------------------------------ misfit
+
+extern "C" int sw_misfit_workspace_bytes(int32_t n_rec, size_t* bytes) {
+  if (!bytes || n_rec <= 0) return fail(SW_EINVAL, "bad arguments");
+  *bytes = 8 * (2 * 3 * (size_t)n_rec + 2);
+  return SW_OK;
+}
+
+static int misfit_run(sw_ctx* ctx, int32_t n_rec, int64_t n_steps, const double* U, const double* obs, double* buf,
+                      double* err, int32_t* n_pairs) {
+  launch_misfit(n_rec, n_steps, U, obs, buf, buf + 2 * 3 * n_rec, ctx->stream);
+  LAUNCHED();
+  double h[2];
+  HIPC(hipMemcpyAsync(h, buf + 2 * 3 * n_rec, 16, hipMemcpyDeviceToHost, ctx->stream));
+  HIPC(hipStreamSynchronize(ctx->stream));
+  *err = h[0];
+  if (n_pairs) *n_pairs = (int32_t)h[1];
+  return SW_OK;
+}
+
+extern "C" int sw_misfit(sw_ctx* ctx, int32_t n_rec, int64_t n_steps, const double* U, const double* obs,
+                         void* dev_ws, size_t ws_bytes, double* err, int32_t* n_pairs) {
+  if (!ctx || !U || !obs || !err) return fail(SW_EINVAL, "NULL argument");
+  if (n_rec <= 0 || n_steps <= 0) return fail(SW_EINVAL, "n_rec and n_steps must be > 0");
+  if ((int64_t)n_rec * 3 > (1 << 30)) return fail(SW_EINVAL, "too many receivers");
+  size_t need = 0;
+  sw_misfit_workspace_bytes(n_rec, &need);
+  if (!dev_ws || ((uintptr_t)dev_ws & 7) || ws_bytes < need)
+    return fail(SW_ENOWS, "misfit workspace NULL, misaligned or smaller than %zu bytes", need);
+  HIPC(hipSetDevice(ctx->device));
+  return misfit_run(ctx, n_rec, n_steps, U, obs, (double*)dev_ws, err, n_pairs);
+}
+
+extern "C" int sw_case_misfit(sw_case* c, const double* obs, double* err, int32_t* n_pairs) {
+  if (!c || !obs || !err) return fail(SW_EINVAL, "NULL argument");
+  if (c->n_rec <= 0 || c->step <= 0) return fail(SW_ESTATE, "no recorded waveforms");
+  HIPC(hipSetDevice(c->ctx->device));
+  return misfit_run(c->ctx, c->n_rec, c->step, c->wave, obs, c->mis_buf, err, n_pairs);
+}
+
+// ------------------------------------------------------------ batch
+
+extern "C" int sw_batch_workspace_bytes(sw_case* const* cases, int32_t n, size_t* bytes) {
+  if (!cases || n <= 0 || !bytes) return fail(SW_EINVAL, "bad batch arguments");
+  *bytes = 256;
+  return SW_OK;
+}
+
+extern "C" int sw_batch_create(sw_ctx* ctx, sw_case* const* cases, int32_t n, void* ws, size_t ws_bytes,
+                               sw_batch** out) {
+  if (!ctx || !cases || n <= 0 || !out) return fail(SW_EINVAL, "bad batch arguments");
+  for (int i = 0; i < n; ++i)
+    if (!cases[i] || cases[i]->ctx->device != ctx->device) return fail(SW_EINVAL, "case %d invalid or on another device", i);
+  sw_batch* b = new sw_batch{ctx, std::vector<sw_case*>(cases, cases + n)};
+  *out = b;
+  return SW_OK;
+}
+
+extern "C" int sw_batch_step(sw_batch* b, int32_t n_steps) {
+  if (!b) return fail(SW_EINVAL, "NULL batch");
+  for (sw_case* c : b->cases)
+    if (c->step + n_steps > c->n_steps) return fail(SW_ESTATE, "a case would exceed its step capacity");
+  for (sw_case* c : b->cases) {
+    int rc = sw_case_step(c, n_steps);
+    if (rc) return rc;
+  }
+  return SW_OK;
+}
+
+extern "C" int sw_batch_destroy(sw_batch* b) {
+  delete b;
+  return SW_OK;
+}
