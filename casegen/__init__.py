@@ -241,7 +241,11 @@ def two_layer_materials(mesh: Mesh, depth_fn):
     """Material id per tet: 0 (soft) if the centroid lies above the
     interface (depth below surface < h(x, y)), else 1 (bedrock)."""
     c = tet_centroids(mesh)
-    d = depth_fn(c[:, 0], c[:, 1])
+    # evaluate the field once per distinct (x, y) centroid position
+    q = np.rint(c[:, :2] * 1e6).astype(np.int64)
+    key = (q[:, 0] - q[:, 0].min()) * (int(q[:, 1].max() - q[:, 1].min()) + 1) + (q[:, 1] - q[:, 1].min())
+    ukey, first, inv = np.unique(key, return_index=True, return_inverse=True)
+    d = depth_fn(c[first, 0], c[first, 1])[inv.ravel()]
     return np.where(-c[:, 2] < d, 0, 1).astype(np.uint8)
 
 

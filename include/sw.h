@@ -111,6 +111,27 @@ SW_API const char* sw_version(void);
 SW_API int sw_ctx_create(int device, void* hip_stream, sw_ctx** out);
 SW_API int sw_ctx_destroy(sw_ctx* ctx);
 
+/* Kernel classes timed by the optional profiler: the matrix-free operator
+ * (tile kernel) and the two CG vector kernels, per precision, as launched
+ * inside the CG iterations of sw_case_step. */
+enum {
+  SW_PROF_TILE_F64 = 0, SW_PROF_TILE_F32 = 1,
+  SW_PROF_UPDATE_F64 = 2, SW_PROF_UPDATE_F32 = 3,
+  SW_PROF_DIR_F64 = 4, SW_PROF_DIR_F32 = 5,
+  SW_PROF_KINDS = 6
+};
+/* enable != 0: bracket every launch of those kernels with HIP events on the
+ * context stream (a few microseconds of overhead per launch) and reset the
+ * totals; 0: stop.  Synchronises the stream. */
+SW_API int sw_ctx_profile(sw_ctx* ctx, int32_t enable);
+/* Total device time (ms) and launch count of one kernel class since the last
+ * sw_ctx_profile call, and (optional, may be NULL) the mean duration and
+ * count of its full launches: those lasting at least half the longest, which
+ * leaves out launches that returned at once because the solve had already
+ * converged.  Synchronises the stream. */
+SW_API int sw_ctx_profile_read(sw_ctx* ctx, int32_t kind, double* total_ms, int64_t* count, double* full_mean_ms,
+                               int64_t* full_count);
+
 /* ----------------------------------------------------------------- mesh */
 
 typedef struct {

@@ -59,6 +59,20 @@ class Context:
         L.check(self.lib.sw_ctx_create(device, C.c_void_p(stream.cuda_stream), C.byref(h)))
         self.h = h
 
+    def profile(self, enable=True):
+        """Start (reset) or stop per-kernel HIP-event timing of the CG kernels."""
+        L.check(self.lib.sw_ctx_profile(self.h, 1 if enable else 0))
+
+    def profile_read(self, kind):
+        """(total ms, launches, mean ms of full launches, full launches) of one
+        kernel class: tile_f64, tile_f32, update_f64, update_f32, dir_f64,
+        dir_f32.  Full launches are those lasting at least half the longest."""
+        t, fm = C.c_double(), C.c_double()
+        n, fn = C.c_int64(), C.c_int64()
+        L.check(self.lib.sw_ctx_profile_read(self.h, L.PROF_KINDS[kind], C.byref(t), C.byref(n), C.byref(fm),
+                                             C.byref(fn)))
+        return t.value, n.value, fm.value, fn.value
+
     def __del__(self):
         if getattr(self, "h", None):
             self.lib.sw_ctx_destroy(self.h)

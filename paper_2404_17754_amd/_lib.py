@@ -13,6 +13,7 @@ SW_FLAG_NOCONV, SW_FLAG_NONFINITE, SW_FLAG_GUESS_FALLBACK = 1, 2, 4
 SW_FP64, SW_MIXED_FP32 = 0, 1
 SW_GUESS_ZERO, SW_GUESS_POLY, SW_GUESS_MLP = 0, 1, 2
 SW_OP_M, SW_OP_K, SW_OP_CABS, SW_OP_A = 1, 2, 4, 8
+PROF_KINDS = {"tile_f64": 0, "tile_f32": 1, "update_f64": 2, "update_f32": 3, "dir_f64": 4, "dir_f32": 5}
 
 ERRNAMES = {SW_EINVAL: "SW_EINVAL", SW_ENOWS: "SW_ENOWS", SW_EMESH: "SW_EMESH", SW_ENOCONV: "SW_ENOCONV",
             SW_EHIP: "SW_EHIP", SW_ESTATE: "SW_ESTATE"}
@@ -52,6 +53,8 @@ SIGNATURES = {
     "sw_version": (),
     "sw_ctx_create": (C.c_int, VP, PP),
     "sw_ctx_destroy": (VP,),
+    "sw_ctx_profile": (VP, I32),
+    "sw_ctx_profile_read": (VP, I32, C.POINTER(F64), C.POINTER(I64), C.POINTER(F64), C.POINTER(I64)),
     "sw_mesh_workspace_bytes": (C.POINTER(MeshDesc), C.POINTER(SZ)),
     "sw_mesh_create": (VP, C.POINTER(MeshDesc), VP, SZ, PP),
     "sw_mesh_destroy": (VP,),

@@ -15,8 +15,8 @@ CSRC = os.path.join(PKG, "csrc")
 ROOT = os.path.dirname(PKG)
 LIB = os.path.join(PKG, "libsw.so")
 
-SOURCES = ["sw_kernels.hip", "sw_api.cpp"]
-HEADERS = ["sw_elem.h", "sw_internal.h"]
+SOURCES = ["sw_tile.hip", "sw_kernels.hip", "sw_mesh.cpp", "sw_api.cpp"]
+HEADERS = ["sw_elem.h", "sw_internal.h", "sw_device.h", "sw_layout.h"]
 
 HIPCC_FLAGS = [
     "-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",

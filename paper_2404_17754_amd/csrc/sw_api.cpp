@@ -20,8 +20,9 @@
 #include <string>
 #include <vector>
 
-#include "../../include/sw.h"
+#include "sw.h"
 #include "sw_internal.h"
+#include "sw_layout.h"
 
 using namespace sw;
 
@@ -77,15 +78,67 @@ inline int64_t pad64(int64_t n) { return (n + 63) / 64 * 64; }
 
 // ------------------------------------------------------------ objects
 
+// Optional per-kernel timing with HIP events on the context stream: each
+// profiled launch is bracketed by two events; elapsed times are collected at
+// the next host synchronisation point.
+struct KernelProfiler {
+  static constexpr int kPool = 512;
+  bool on = false;
+  std::vector<hipEvent_t> ev;
+  std::vector<int> kind;  // per event pair
+  int next = 0;           // next free event
+  double total_ms[SW_PROF_KINDS] = {};
+  int64_t count[SW_PROF_KINDS] = {};
+  std::vector<float> each[SW_PROF_KINDS];  // every launch's duration (ms)
+};
+
 struct sw_ctx {
   int device;
   hipStream_t stream;
+  KernelProfiler prof;
 };
+
+namespace {
+
+int prof_flush(sw_ctx* ctx) {
+  KernelProfiler& P = ctx->prof;
+  for (int i = 0; i + 1 < P.next; i += 2) {
+    float ms = 0.0f;
+    HIPC(hipEventSynchronize(P.ev[i + 1]));
+    HIPC(hipEventElapsedTime(&ms, P.ev[i], P.ev[i + 1]));
+    P.total_ms[P.kind[i / 2]] += ms;
+    P.count[P.kind[i / 2]] += 1;
+    P.each[P.kind[i / 2]].push_back(ms);
+  }
+  P.next = 0;
+  return SW_OK;
+}
+
+// returns the event index of the start marker, or -1 when not profiling
+int prof_begin(sw_ctx* ctx, int kind) {
+  KernelProfiler& P = ctx->prof;
+  if (!P.on) return -1;
+  if (P.next + 2 > KernelProfiler::kPool && prof_flush(ctx) != SW_OK) return -1;
+  const int i = P.next;
+  P.kind[i / 2] = kind;
+  P.next += 2;
+  if (hipEventRecord(P.ev[i], ctx->stream) != hipSuccess) return -1;
+  return i;
+}
+
+void prof_end(sw_ctx* ctx, int i) {
+  if (i >= 0) (void)hipEventRecord(ctx->prof.ev[i + 1], ctx->stream);
+}
+
+}  // namespace
 
 struct sw_mesh {
   sw_ctx* ctx;
   MeshDev dev;
   int64_t n_nodes, n_tets, n_faces;
+  std::vector<int32_t> elem_order;  // internal element -> user element
+  std::vector<int32_t> node_u2i;    // user node -> internal node
+  std::vector<int32_t> node_i2u;
 };
 
 struct sw_case {
@@ -96,10 +149,10 @@ struct sw_case {
   int32_t max_iter, precision, guess, poly_order, n_mat, n_rec;
   int64_t n_steps;
   double cM, cK, cC;
-  // device
+  // device (vectors in internal node order)
   MatDev* mats;
-  uint8_t* tet_mat;
-  int32_t* rec;
+  uint8_t* emat;  // material per internal element
+  int32_t* rec;   // internal node ids
   double* vin;
   double *u, *v, *a, *b, *x, *r, *z, *p, *q;
   double* hist;  // [4][n_dof]
@@ -112,7 +165,6 @@ struct sw_case {
   CgCtl *ctl64, *ctl32;
   int32_t* bad;
   double* mis_buf;
-  double* mis_out;
   // host state
   int64_t step = 0;
   int hist_head = 3, hist_count = 0;
@@ -137,33 +189,58 @@ extern "C" int sw_ctx_create(int device, void* hip_stream, sw_ctx** out) {
 }
 
 extern "C" int sw_ctx_destroy(sw_ctx* ctx) {
+  if (ctx)
+    for (hipEvent_t e : ctx->prof.ev) (void)hipEventDestroy(e);
   delete ctx;
   return SW_OK;
 }
 
-// ------------------------------------------------------------ mesh
-
-static size_t mesh_layout(const sw_mesh_desc* d, Carver& cv, MeshDev* md) {
-  const int64_t ts = pad64(d->n_tets), fs = pad64(std::max<int64_t>(d->n_faces, 1));
-  auto conn = cv.take<int32_t>(10 * ts);
-  auto xyz = cv.take<double>(3 * d->n_nodes);
-  auto fconn = cv.take<int32_t>(6 * fs);
-  auto ftet = cv.take<int32_t>(fs);
-  auto frole = cv.take<uint8_t>(fs);
-  if (md) {
-    md->n_nodes = d->n_nodes;
-    md->n_tets = d->n_tets;
-    md->n_faces = d->n_faces;
-    md->tet_stride = ts;
-    md->face_stride = fs;
-    md->conn = conn;
-    md->xyz = xyz;
-    md->fconn = fconn;
-    md->face_tet = ftet;
-    md->face_role = frole;
+extern "C" int sw_ctx_profile(sw_ctx* ctx, int32_t enable) {
+  if (!ctx) return fail(SW_EINVAL, "NULL context");
+  HIPC(hipSetDevice(ctx->device));
+  KernelProfiler& P = ctx->prof;
+  if (enable && P.ev.empty()) {
+    P.ev.resize(KernelProfiler::kPool);
+    P.kind.assign(KernelProfiler::kPool / 2, 0);
+    for (auto& e : P.ev) HIPC(hipEventCreate(&e));
   }
-  return cv.off;
+  HIPC(hipStreamSynchronize(ctx->stream));
+  int rc = prof_flush(ctx);
+  if (rc) return rc;
+  for (int k = 0; k < SW_PROF_KINDS; ++k) {
+    P.total_ms[k] = 0.0;
+    P.count[k] = 0;
+    P.each[k].clear();
+  }
+  P.on = enable != 0;
+  return SW_OK;
 }
+
+extern "C" int sw_ctx_profile_read(sw_ctx* ctx, int32_t kind, double* total_ms, int64_t* count,
+                                   double* full_mean_ms, int64_t* full_count) {
+  if (!ctx || !total_ms || !count) return fail(SW_EINVAL, "NULL argument");
+  if (kind < 0 || kind >= SW_PROF_KINDS) return fail(SW_EINVAL, "unknown kernel kind %d", kind);
+  HIPC(hipStreamSynchronize(ctx->stream));
+  int rc = prof_flush(ctx);
+  if (rc) return rc;
+  *total_ms = ctx->prof.total_ms[kind];
+  *count = ctx->prof.count[kind];
+  const std::vector<float>& e = ctx->prof.each[kind];
+  float mx = 0.0f;
+  for (float v : e) mx = std::max(mx, v);
+  double sum = 0.0;
+  int64_t n = 0;
+  for (float v : e)
+    if (v >= 0.5f * mx) {
+      sum += v;
+      ++n;
+    }
+  if (full_mean_ms) *full_mean_ms = n ? sum / (double)n : 0.0;
+  if (full_count) *full_count = n;
+  return SW_OK;
+}
+
+// ------------------------------------------------------------ mesh
 
 static int validate_mesh(const sw_mesh_desc* d) {
   if (!d) return fail(SW_EINVAL, "mesh desc is NULL");
@@ -227,11 +304,94 @@ static int validate_mesh(const sw_mesh_desc* d) {
   return SW_OK;
 }
 
+
+namespace {
+
+// The tiled layout of the last mesh sized by sw_mesh_workspace_bytes, so the
+// create call that normally follows does not rebuild it.
+struct LayoutCache {
+  const void* xyz = nullptr;
+  const void* tet10 = nullptr;
+  const void* tri6 = nullptr;
+  int64_t n_nodes = -1, n_tets = -1, n_faces = -1;
+  HostLayout L;
+  bool matches(const sw_mesh_desc* d) const {
+    return xyz == d->xyz && tet10 == d->tet10 && tri6 == d->tri6 && n_nodes == d->n_nodes && n_tets == d->n_tets &&
+           n_faces == d->n_faces;
+  }
+};
+thread_local LayoutCache g_layout;
+
+const HostLayout& layout_for(const sw_mesh_desc* d) {
+  if (!g_layout.matches(d)) {
+    build_layout(d->n_nodes, d->n_tets, d->n_faces, d->xyz, d->tet10, d->tri6, d->face_tet, d->face_role,
+                 g_layout.L);
+    g_layout.xyz = d->xyz;
+    g_layout.tet10 = d->tet10;
+    g_layout.tri6 = d->tri6;
+    g_layout.n_nodes = d->n_nodes;
+    g_layout.n_tets = d->n_tets;
+    g_layout.n_faces = d->n_faces;
+  }
+  return g_layout.L;
+}
+
+size_t mesh_layout(const HostLayout& L, Carver& cv, MeshDev* md) {
+  const int32_t nT = L.n_tiles;
+  auto conn_loc = cv.take<uint16_t>(10 * L.tet_stride);
+  auto teo = cv.take<int32_t>(nT + 1);
+  auto tno = cv.take<int32_t>(nT + 1);
+  auto tn = cv.take<int32_t>(std::max<size_t>(L.tile_nodes.size(), 1));
+  auto tib = cv.take<int32_t>(nT);
+  auto tni = cv.take<int32_t>(nT);
+  auto tfo = cv.take<int32_t>(nT + 1);
+  auto xyz = cv.take<double>(3 * L.n_nodes);
+  auto fconn = cv.take<int32_t>(6 * L.face_stride);
+  auto fconn_loc = cv.take<uint16_t>(6 * L.face_stride);
+  auto fel = cv.take<int32_t>(L.face_stride);
+  auto frole = cv.take<uint8_t>(L.face_stride);
+  auto u2i = cv.take<int32_t>(L.n_nodes);
+  auto i2u = cv.take<int32_t>(L.n_nodes);
+  if (md) {
+    md->n_nodes = L.n_nodes;
+    md->n_tets = L.n_tets;
+    md->n_faces = L.n_faces;
+    md->n_tiles = nT;
+    md->max_tile_nodes = L.max_tile_nodes;
+    md->tet_stride = L.tet_stride;
+    md->face_stride = L.face_stride;
+    md->conn_loc = conn_loc;
+    md->tile_elem_off = teo;
+    md->tile_node_off = tno;
+    md->tile_nodes = tn;
+    md->tile_int_base = tib;
+    md->tile_nint = tni;
+    md->tile_face_off = tfo;
+    md->xyz = xyz;
+    md->fconn = fconn;
+    md->fconn_loc = fconn_loc;
+    md->face_elem = fel;
+    md->face_role = frole;
+    md->node_u2i = u2i;
+    md->node_i2u = i2u;
+  }
+  return cv.off;
+}
+
+template <typename T>
+hipError_t up(const T* dst, const std::vector<T>& src, hipStream_t s) {
+  if (src.empty()) return hipSuccess;
+  return hipMemcpyAsync((void*)dst, src.data(), src.size() * sizeof(T), hipMemcpyHostToDevice, s);
+}
+
+}  // namespace
+
 extern "C" int sw_mesh_workspace_bytes(const sw_mesh_desc* d, size_t* bytes) {
   if (!d || !bytes) return fail(SW_EINVAL, "NULL argument");
-  if (d->n_nodes <= 0 || d->n_tets <= 0 || d->n_faces < 0) return fail(SW_EINVAL, "bad mesh sizes");
+  int rc = validate_mesh(d);
+  if (rc) return rc;
   Carver cv(nullptr);
-  *bytes = mesh_layout(d, cv, nullptr);
+  *bytes = mesh_layout(layout_for(d), cv, nullptr);
   return SW_OK;
 }
 
@@ -239,33 +399,33 @@ extern "C" int sw_mesh_create(sw_ctx* ctx, const sw_mesh_desc* d, void* ws, size
   if (!ctx || !out) return fail(SW_EINVAL, "NULL argument");
   int rc = validate_mesh(d);
   if (rc) return rc;
+  const HostLayout& L = layout_for(d);
+  if (L.max_tile_nodes > TILE_MAX_NODES) return fail(SW_EMESH, "tile exceeds the LDS node capacity");
   Carver dry(nullptr);
-  const size_t need = mesh_layout(d, dry, nullptr);
+  const size_t need = mesh_layout(L, dry, nullptr);
   if (!ws || ((uintptr_t)ws & 255)) return fail(SW_ENOWS, "mesh workspace NULL or not 256-byte aligned");
   if (ws_bytes < need) return fail(SW_ENOWS, "mesh workspace %zu bytes < %zu needed", ws_bytes, need);
   HIPC(hipSetDevice(ctx->device));
   Carver cv(ws);
   MeshDev md;
-  mesh_layout(d, cv, &md);
-  // element-coalesced connectivity: conn[k][e]
-  std::vector<int32_t> conn(10 * md.tet_stride, 0);
-  for (int64_t e = 0; e < d->n_tets; ++e)
-    for (int k = 0; k < 10; ++k) conn[k * md.tet_stride + e] = d->tet10[10 * e + k];
-  std::vector<int32_t> fconn(6 * md.face_stride, 0), ftet(md.face_stride, 0);
-  std::vector<uint8_t> frole(md.face_stride, 0);
-  for (int64_t f = 0; f < d->n_faces; ++f) {
-    for (int k = 0; k < 6; ++k) fconn[k * md.face_stride + f] = d->tri6[6 * f + k];
-    ftet[f] = d->face_tet[f];
-    frole[f] = d->face_role[f];
-  }
+  mesh_layout(L, cv, &md);
   hipStream_t s = ctx->stream;
-  HIPC(hipMemcpyAsync((void*)md.conn, conn.data(), conn.size() * 4, hipMemcpyHostToDevice, s));
-  HIPC(hipMemcpyAsync((void*)md.xyz, d->xyz, 3 * d->n_nodes * 8, hipMemcpyHostToDevice, s));
-  HIPC(hipMemcpyAsync((void*)md.fconn, fconn.data(), fconn.size() * 4, hipMemcpyHostToDevice, s));
-  HIPC(hipMemcpyAsync((void*)md.face_tet, ftet.data(), ftet.size() * 4, hipMemcpyHostToDevice, s));
-  HIPC(hipMemcpyAsync((void*)md.face_role, frole.data(), frole.size(), hipMemcpyHostToDevice, s));
+  HIPC(up(md.conn_loc, L.conn_loc, s));
+  HIPC(up(md.tile_elem_off, L.tile_elem_off, s));
+  HIPC(up(md.tile_node_off, L.tile_node_off, s));
+  HIPC(up(md.tile_nodes, L.tile_nodes, s));
+  HIPC(up(md.tile_int_base, L.tile_int_base, s));
+  HIPC(up(md.tile_nint, L.tile_nint, s));
+  HIPC(up(md.tile_face_off, L.tile_face_off, s));
+  HIPC(up(md.xyz, L.xyz, s));
+  HIPC(up(md.fconn, L.fconn, s));
+  HIPC(up(md.fconn_loc, L.fconn_loc, s));
+  HIPC(up(md.face_elem, L.face_elem, s));
+  HIPC(up(md.face_role, L.face_role, s));
+  HIPC(up(md.node_u2i, L.node_u2i, s));
+  HIPC(up(md.node_i2u, L.node_i2u, s));
   HIPC(hipStreamSynchronize(s));
-  sw_mesh* m = new sw_mesh{ctx, md, d->n_nodes, d->n_tets, d->n_faces};
+  sw_mesh* m = new sw_mesh{ctx, md, d->n_nodes, d->n_tets, d->n_faces, L.elem_order, L.node_u2i, L.node_i2u};
   *out = m;
   return SW_OK;
 }
@@ -281,7 +441,7 @@ static size_t case_layout(const sw_mesh* m, const sw_case_desc* d, Carver& cv, s
   const int64_t nn = m->n_nodes, nd = 3 * nn;
   const bool mixed = d->precision == SW_MIXED_FP32;
   auto mats = cv.take<MatDev>(d->n_mat);
-  auto tm = cv.take<uint8_t>(m->n_tets);
+  auto em = cv.take<uint8_t>(m->n_tets);
   auto rec = cv.take<int32_t>(std::max(d->n_rec, 1));
   auto vin = cv.take<double>(3 * (d->n_steps + 1));
   double* vec[9];
@@ -298,11 +458,10 @@ static size_t case_layout(const sw_mesh* m, const sw_case_desc* d, Carver& cv, s
   auto log_rel = cv.take<double>(d->n_steps);
   auto ctl = cv.take<CgCtl>(2);
   auto bad = cv.take<int32_t>(1);
-  auto mis_buf = cv.take<double>(2 * 3 * std::max(d->n_rec, 1));
-  auto mis_out = cv.take<double>(2);
+  auto mis_buf = cv.take<double>(2 * 3 * std::max(d->n_rec, 1) + 2);
   if (c) {
     c->mats = mats;
-    c->tet_mat = tm;
+    c->emat = em;
     c->rec = rec;
     c->vin = vin;
     c->u = vec[0];
@@ -330,7 +489,6 @@ static size_t case_layout(const sw_mesh* m, const sw_case_desc* d, Carver& cv, s
     c->ctl32 = ctl ? ctl + 1 : nullptr;
     c->bad = bad;
     c->mis_buf = mis_buf;
-    c->mis_out = mis_out;
   }
   return cv.off;
 }
@@ -365,6 +523,7 @@ static int validate_case(const sw_mesh* m, const sw_case_desc* d) {
   return SW_OK;
 }
 
+
 extern "C" int sw_case_workspace_bytes(const sw_mesh* m, const sw_case_desc* d, size_t* bytes) {
   if (!m || !d || !bytes) return fail(SW_EINVAL, "NULL argument");
   if (d->n_mat < 1 || d->n_rec < 0 || d->n_steps < 1) return fail(SW_EINVAL, "bad case sizes");
@@ -373,43 +532,85 @@ extern "C" int sw_case_workspace_bytes(const sw_mesh* m, const sw_case_desc* d, 
   return SW_OK;
 }
 
-static int apply_op_f64(sw_case* c, int op, const double* x, double* y, CgCtl* ctl, int iter) {
-  const MeshDev& md = c->mesh->dev;
-  hipStream_t s = c->ctx->stream;
-  double sM, sK, sC;
+namespace {
+
+void op_scales(const sw_case* c, int op, double* sM, double* sK, double* sC) {
   if (op == SW_OP_A) {
-    sM = c->cM;
-    sK = c->cK;
-    sC = c->cC;
+    *sM = c->cM;
+    *sK = c->cK;
+    *sC = c->cC;
   } else {
-    sM = (op & SW_OP_M) ? 1.0 : 0.0;
-    sK = (op & SW_OP_K) ? 1.0 : 0.0;
-    sC = (op & SW_OP_CABS) ? 1.0 : 0.0;
+    *sM = (op & SW_OP_M) ? 1.0 : 0.0;
+    *sK = (op & SW_OP_K) ? 1.0 : 0.0;
+    *sC = (op & SW_OP_CABS) ? 1.0 : 0.0;
   }
-  if (sM != 0.0 || sK != 0.0) launch_ebe_apply_f64(md, c->tet_mat, c->mats, sM, sK, x, y, ctl, iter, s);
-  if (sC != 0.0) launch_face_apply_f64(md, c->tet_mat, c->mats, sC, x, y, ctl, s);
+}
+
+// y = op x (internal order).  y's shared-node entries must be zero on entry
+// (interior entries are overwritten).
+int apply_f64(sw_case* c, int op, const double* x, double* y, CgCtl* ctl, int iter) {
+  TileArgs<double> A{};
+  op_scales(c, op, &A.sM, &A.sK, &A.sC);
+  A.x1 = x;
+  A.a1 = 1.0;
+  A.xf = x;
+  A.y = y;
+  launch_tile_f64(c->mesh->dev, c->emat, c->mats, A, ctl, iter, c->ctx->stream);
   LAUNCHED();
   return SW_OK;
 }
 
-static int apply_op_f32(sw_case* c, int op, const float* x, float* y, CgCtl* ctl, int iter) {
-  const MeshDev& md = c->mesh->dev;
-  hipStream_t s = c->ctx->stream;
+int apply_f32(sw_case* c, int op, const float* x, float* y, CgCtl* ctl, int iter) {
+  TileArgs<float> A{};
   double sM, sK, sC;
-  if (op == SW_OP_A) {
-    sM = c->cM;
-    sK = c->cK;
-    sC = c->cC;
-  } else {
-    sM = (op & SW_OP_M) ? 1.0 : 0.0;
-    sK = (op & SW_OP_K) ? 1.0 : 0.0;
-    sC = (op & SW_OP_CABS) ? 1.0 : 0.0;
-  }
-  if (sM != 0.0 || sK != 0.0) launch_ebe_apply_f32(md, c->tet_mat, c->mats, sM, sK, x, y, ctl, iter, s);
-  if (sC != 0.0) launch_face_apply_f32(md, c->tet_mat, c->mats, sC, x, y, ctl, s);
+  op_scales(c, op, &sM, &sK, &sC);
+  A.sM = (float)sM;
+  A.sK = (float)sK;
+  A.sC = (float)sC;
+  A.x1 = x;
+  A.a1 = 1.0f;
+  A.xf = x;
+  A.y = y;
+  launch_tile_f32(c->mesh->dev, c->emat, c->mats, A, ctl, iter, c->ctx->stream);
   LAUNCHED();
   return SW_OK;
 }
+
+// Right-hand side of step c->step -> c->step + 1 (internal order) into y:
+// y = M (a + (4/dt + alpha) v) + C_abs v + F  then  y += -K (u - beta v).
+int build_rhs(sw_case* c, double* y) {
+  hipStream_t s = c->ctx->stream;
+  const int64_t nd = 3 * c->mesh->n_nodes;
+  launch_fill_f64(nd, y, 0.0, s);
+  TileArgs<double> A{};
+  A.sM = 1.0;
+  A.sK = 0.0;
+  A.sC = 1.0;
+  A.x1 = c->a;
+  A.a1 = 1.0;
+  A.x2 = c->v;
+  A.a2 = 4.0 / c->dt + c->alpha;
+  A.xf = c->v;
+  A.vin = c->vin + 3 * (c->step + 1);
+  A.y = y;
+  A.accumulate = 0;
+  launch_tile_f64(c->mesh->dev, c->emat, c->mats, A, nullptr, -1, s);
+  TileArgs<double> B{};
+  B.sM = 0.0;
+  B.sK = -1.0;
+  B.sC = 0.0;
+  B.x1 = c->u;
+  B.a1 = 1.0;
+  B.x2 = c->v;
+  B.a2 = -c->beta;
+  B.y = y;
+  B.accumulate = 1;
+  launch_tile_f64(c->mesh->dev, c->emat, c->mats, B, nullptr, -1, s);
+  LAUNCHED();
+  return SW_OK;
+}
+
+}  // namespace
 
 extern "C" int sw_case_create(sw_ctx* ctx, sw_mesh* m, const sw_case_desc* d, void* ws, size_t ws_bytes,
                               sw_case** out) {
@@ -451,19 +652,23 @@ extern "C" int sw_case_create(sw_ctx* ctx, sw_mesh* m, const sw_case_desc* d, vo
     mats[i].zp = rho * vp;
     mats[i].zs = rho * vs;
   }
+  std::vector<uint8_t> em(m->n_tets);
+  for (int64_t i = 0; i < m->n_tets; ++i) em[i] = d->tet_mat[m->elem_order[i]];
+  std::vector<int32_t> rec(std::max(d->n_rec, 1), 0);
+  for (int i = 0; i < d->n_rec; ++i) rec[i] = m->node_u2i[d->rec_node[i]];
   const int64_t nn = m->n_nodes, nd = 3 * nn;
   auto cleanup = [&](int code) {
     delete c;
     return code;
   };
-#define HIPX(expr)                                                                                  \
-  do {                                                                                              \
-    hipError_t _e = (expr);                                                                         \
+#define HIPX(expr)                                                                                       \
+  do {                                                                                                   \
+    hipError_t _e = (expr);                                                                              \
     if (_e != hipSuccess) return cleanup(fail(SW_EHIP, "%s failed: %s", #expr, hipGetErrorString(_e))); \
   } while (0)
   HIPX(hipMemcpyAsync(c->mats, mats.data(), mats.size() * sizeof(MatDev), hipMemcpyHostToDevice, s));
-  HIPX(hipMemcpyAsync(c->tet_mat, d->tet_mat, m->n_tets, hipMemcpyHostToDevice, s));
-  if (d->n_rec > 0) HIPX(hipMemcpyAsync(c->rec, d->rec_node, 4 * (size_t)d->n_rec, hipMemcpyHostToDevice, s));
+  HIPX(hipMemcpyAsync(c->emat, em.data(), em.size(), hipMemcpyHostToDevice, s));
+  HIPX(hipMemcpyAsync(c->rec, rec.data(), 4 * rec.size(), hipMemcpyHostToDevice, s));
   HIPX(hipMemcpyAsync(c->vin, d->v_in, 8 * 3 * (size_t)(d->n_steps + 1), hipMemcpyHostToDevice, s));
   double* zero_vecs[] = {c->u, c->v, c->a, c->b, c->x, c->r, c->z, c->p, c->q};
   for (double* zv : zero_vecs) launch_fill_f64(nd, zv, 0.0, s);
@@ -474,12 +679,12 @@ extern "C" int sw_case_create(sw_ctx* ctx, sw_mesh* m, const sw_case_desc* d, vo
   }
   launch_fill_f64(std::max<int64_t>(c->n_steps * 3 * c->n_rec, 1), c->wave, 0.0, s);
   launch_fill_f64((int64_t)(2 * sizeof(CgCtl) / 8), (double*)c->ctl64, 0.0, s);
-  HIPX(hipMemsetAsync(c->log_it, 0, 4 * (size_t)c->n_steps, s));
   launch_fill_f64(c->n_steps, c->log_rel, 0.0, s);
+  HIPX(hipMemsetAsync(c->log_it, 0, 4 * (size_t)c->n_steps, s));
   // preconditioner: inverse 3x3 diagonal blocks of A
   launch_fill_f64(6 * nn, c->diag6, 0.0, s);
   HIPX(hipMemsetAsync(c->bad, 0, 4, s));
-  launch_diag_blocks(m->dev, c->tet_mat, c->mats, c->cM, c->cK, c->cC, c->diag6, s);
+  launch_tile_diag(m->dev, c->emat, c->mats, c->cM, c->cK, c->cC, c->diag6, s);
   launch_invert_blocks(nn, c->diag6, c->pinv64, c->pinv32, c->bad, s);
   HIPX(hipGetLastError());
   int32_t bad = 0;
@@ -500,12 +705,21 @@ extern "C" int sw_case_set_state(sw_case* c, const double* u, const double* v, c
   if (!c) return fail(SW_EINVAL, "NULL case");
   if (step < 0 || step > c->n_steps) return fail(SW_EINVAL, "step %lld out of range", (long long)step);
   HIPC(hipSetDevice(c->ctx->device));
-  const size_t nb = 8 * 3 * (size_t)c->mesh->n_nodes;
+  const int64_t nn = c->mesh->n_nodes;
   hipStream_t s = c->ctx->stream;
-  if (u) HIPC(hipMemcpyAsync(c->u, u, nb, hipMemcpyHostToDevice, s));
-  if (v) HIPC(hipMemcpyAsync(c->v, v, nb, hipMemcpyHostToDevice, s));
-  if (a) HIPC(hipMemcpyAsync(c->a, a, nb, hipMemcpyHostToDevice, s));
-  launch_fill_f64(4 * 3 * c->mesh->n_nodes, c->hist, 0.0, s);
+  std::vector<double> tmp(3 * nn);
+  const double* src[3] = {u, v, a};
+  double* dst[3] = {c->u, c->v, c->a};
+  for (int k = 0; k < 3; ++k) {
+    if (!src[k]) continue;
+    for (int64_t i = 0; i < nn; ++i) {
+      const int64_t j = c->mesh->node_u2i[i];
+      for (int d = 0; d < 3; ++d) tmp[3 * j + d] = src[k][3 * i + d];
+    }
+    HIPC(hipMemcpyAsync(dst[k], tmp.data(), 8 * tmp.size(), hipMemcpyHostToDevice, s));
+    HIPC(hipStreamSynchronize(s));
+  }
+  launch_fill_f64(4 * 3 * nn, c->hist, 0.0, s);
   LAUNCHED();
   HIPC(hipStreamSynchronize(s));
   c->step = step;
@@ -517,12 +731,20 @@ extern "C" int sw_case_set_state(sw_case* c, const double* u, const double* v, c
 extern "C" int sw_case_get_state(const sw_case* c, double* u, double* v, double* a, int64_t* step) {
   if (!c) return fail(SW_EINVAL, "NULL case");
   HIPC(hipSetDevice(c->ctx->device));
-  const size_t nb = 8 * 3 * (size_t)c->mesh->n_nodes;
+  const int64_t nn = c->mesh->n_nodes;
   hipStream_t s = c->ctx->stream;
-  if (u) HIPC(hipMemcpyAsync(u, c->u, nb, hipMemcpyDeviceToHost, s));
-  if (v) HIPC(hipMemcpyAsync(v, c->v, nb, hipMemcpyDeviceToHost, s));
-  if (a) HIPC(hipMemcpyAsync(a, c->a, nb, hipMemcpyDeviceToHost, s));
-  HIPC(hipStreamSynchronize(s));
+  std::vector<double> tmp(3 * nn);
+  double* dst[3] = {u, v, a};
+  const double* src[3] = {c->u, c->v, c->a};
+  for (int k = 0; k < 3; ++k) {
+    if (!dst[k]) continue;
+    HIPC(hipMemcpyAsync(tmp.data(), src[k], 8 * tmp.size(), hipMemcpyDeviceToHost, s));
+    HIPC(hipStreamSynchronize(s));
+    for (int64_t i = 0; i < nn; ++i) {
+      const int64_t j = c->mesh->node_u2i[i];
+      for (int d = 0; d < 3; ++d) dst[k][3 * i + d] = tmp[3 * j + d];
+    }
+  }
   if (step) *step = c->step;
   return SW_OK;
 }
@@ -531,47 +753,49 @@ extern "C" int sw_case_get_state(const sw_case* c, double* u, double* v, double*
 
 namespace {
 
-// Right-hand side of step c->step -> c->step + 1 into y (cleared first).
-int build_rhs(sw_case* c, double* y) {
-  const MeshDev& md = c->mesh->dev;
-  hipStream_t s = c->ctx->stream;
-  const int64_t nd = 3 * c->mesh->n_nodes;
-  launch_fill_f64(nd, y, 0.0, s);
-  launch_ebe_rhs(md, c->tet_mat, c->mats, 4.0 / c->dt + c->alpha, c->beta, c->u, c->v, c->a, y, s);
-  launch_face_rhs(md, c->tet_mat, c->mats, c->v, c->vin + 3 * (c->step + 1), y, s);
-  LAUNCHED();
-  return SW_OK;
-}
-
 int read_ctl(sw_case* c, CgCtl* dev, CgCtl* host) {
   HIPC(hipMemcpyAsync(host, dev, sizeof(CgCtl), hipMemcpyDeviceToHost, c->ctx->stream));
   HIPC(hipStreamSynchronize(c->ctx->stream));
-  return SW_OK;
+  return c->ctx->prof.on ? prof_flush(c->ctx) : SW_OK;
 }
 
-// Runs CG iterations of the solve in `ctl` until its done flag is set.
-// iter_base: iterations already spent in this step (for the cap).
+// Runs CG iterations of the solve in `ctl` until its done flag is set.  The
+// first chunk is sized from the previous solve's count; later ones are short
+// so that few launches are spent after convergence.
 template <bool F32>
 int cg_loop(sw_case* c, CgCtl* ctl, int iter_base, int first_chunk, int* iters_out) {
   const int64_t nn = c->mesh->n_nodes;
   hipStream_t s = c->ctx->stream;
   int it = 0;
-  int chunk = std::max(4, first_chunk);
+  int chunk = std::max(1, first_chunk);
   CgCtl h;
   for (;;) {
     for (int k = 0; k < chunk; ++k) {
       const int i = it + k;
       int rc;
+      sw_ctx* cx = c->ctx;
       if (F32) {
-        rc = apply_op_f32(c, SW_OP_A, c->p32, c->q32, ctl, i);
+        int ev = prof_begin(cx, SW_PROF_TILE_F32);
+        rc = apply_f32(c, SW_OP_A, c->p32, c->q32, ctl, i);
+        prof_end(cx, ev);
         if (rc) return rc;
+        ev = prof_begin(cx, SW_PROF_UPDATE_F32);
         launch_cg_update_f32(nn, i & 1, c->pinv32, c->d32, c->r32, c->z32, c->p32, c->q32, ctl, s);
+        prof_end(cx, ev);
+        ev = prof_begin(cx, SW_PROF_DIR_F32);
         launch_cg_dir_f32(nn, i & 1, iter_base + i, c->max_iter, c->z32, c->p32, ctl, s);
+        prof_end(cx, ev);
       } else {
-        rc = apply_op_f64(c, SW_OP_A, c->p, c->q, ctl, i);
+        int ev = prof_begin(cx, SW_PROF_TILE_F64);
+        rc = apply_f64(c, SW_OP_A, c->p, c->q, ctl, i);
+        prof_end(cx, ev);
         if (rc) return rc;
+        ev = prof_begin(cx, SW_PROF_UPDATE_F64);
         launch_cg_update_f64(nn, i & 1, c->pinv64, c->x, c->r, c->z, c->p, c->q, ctl, s);
+        prof_end(cx, ev);
+        ev = prof_begin(cx, SW_PROF_DIR_F64);
         launch_cg_dir_f64(nn, i & 1, iter_base + i, c->max_iter, c->z, c->p, ctl, s);
+        prof_end(cx, ev);
       }
     }
     LAUNCHED();
@@ -579,19 +803,19 @@ int cg_loop(sw_case* c, CgCtl* ctl, int iter_base, int first_chunk, int* iters_o
     int rc = read_ctl(c, ctl, &h);
     if (rc) return rc;
     if (h.done) break;
-    chunk = 8;
+    chunk = 2;
   }
   *iters_out = h.iters - iter_base > 0 ? h.iters - iter_base : 0;
   return SW_OK;
 }
 
-// true residual of x64: q = A x, r = b - q, rr_true into ctl64 (FP64).
-// q keeps A x unless zero_q is set.
+// FP64 true residual of x: q = A x, r = b - q, rr_true into ctl64.  q keeps
+// A x unless zero_q is set.
 int true_residual(sw_case* c, CgCtl* hctl, bool zero_q) {
   hipStream_t s = c->ctx->stream;
   const int64_t nd = 3 * c->mesh->n_nodes;
   launch_fill_f64(1, &c->ctl64->rr_true, 0.0, s);
-  int rc = apply_op_f64(c, SW_OP_A, c->x, c->q, nullptr, -1);
+  int rc = apply_f64(c, SW_OP_A, c->x, c->q, nullptr, -1);
   if (rc) return rc;
   launch_true_residual(nd, c->b, c->q, c->r, c->ctl64, s);
   if (zero_q) launch_fill_f64(nd, c->q, 0.0, s);
@@ -609,8 +833,7 @@ int solve_step(sw_case* c, int* iters, int* outer, double* relres, int* flags) {
   if (rc) return rc;
   launch_fill_f64(1, &c->ctl64->bb, 0.0, s);
   launch_norm2(nd, c->b, &c->ctl64->bb, s);
-  launch_ctl_prepare(c->ctl64, c->rtol, 0, s);
-  // initial guess
+  launch_ctl_prepare(c->ctl64, c->rtol, s);
   const bool use_poly = (c->guess == SW_GUESS_POLY) && c->hist_count > 0;
   if (use_poly) {
     const int order = std::min(c->poly_order, c->hist_count - 1);
@@ -622,7 +845,7 @@ int solve_step(sw_case* c, int* iters, int* outer, double* relres, int* flags) {
   CgCtl h;
   if (c->precision == SW_FP64) {
     if (use_poly) {
-      rc = apply_op_f64(c, SW_OP_A, c->x, c->q, nullptr, -1);
+      rc = apply_f64(c, SW_OP_A, c->x, c->q, nullptr, -1);
       if (rc) return rc;
       launch_cg_init_f64(nn, c->b, c->q, c->pinv64, c->r, c->z, c->p, c->q, c->ctl64, s);
     } else {
@@ -631,7 +854,7 @@ int solve_step(sw_case* c, int* iters, int* outer, double* relres, int* flags) {
     LAUNCHED();
     for (;;) {
       int it = 0;
-      rc = cg_loop<false>(c, c->ctl64, *iters, std::max(4, c->last_iters - *iters), &it);
+      rc = cg_loop<false>(c, c->ctl64, *iters, c->last_iters - *iters - 1, &it);
       if (rc) return rc;
       *iters += it;
       rc = true_residual(c, &h, false);
@@ -653,11 +876,12 @@ int solve_step(sw_case* c, int* iters, int* outer, double* relres, int* flags) {
         break;
       }
       // restart CG from the current iterate on the true residual b - A x
-      launch_ctl_prepare(c->ctl64, c->rtol, 0, s);
+      launch_ctl_prepare(c->ctl64, c->rtol, s);
       launch_cg_init_f64(nn, c->b, c->q, c->pinv64, c->r, c->z, c->p, c->q, c->ctl64, s);
       LAUNCHED();
     }
   } else {
+    int inner_est = std::max(1, c->last_iters / 2);
     for (;;) {
       rc = true_residual(c, &h, true);
       if (rc) return rc;
@@ -674,14 +898,15 @@ int solve_step(sw_case* c, int* iters, int* outer, double* relres, int* flags) {
       launch_to_f32_scaled(nd, c->r, c->r32, c->ctl64, s);
       launch_fill_f64(sizeof(CgCtl) / 8, (double*)c->ctl32, 0.0, s);
       launch_fill_f64(1, &c->ctl32->bb, 1.0, s);
-      launch_ctl_prepare(c->ctl32, c->inner_rtol, 0, s);
+      launch_ctl_prepare(c->ctl32, c->inner_rtol, s);
       launch_fill_f32(nd, c->d32, 0.0f, s);
       launch_cg_init_f32(nn, c->r32, nullptr, c->pinv32, c->r32, c->z32, c->p32, nullptr, c->ctl32, s);
       LAUNCHED();
       int it = 0;
-      rc = cg_loop<true>(c, c->ctl32, *iters, std::max(4, c->last_iters / 2), &it);
+      rc = cg_loop<true>(c, c->ctl32, *iters, inner_est - 1, &it);
       if (rc) return rc;
       *iters += it;
+      inner_est = std::max(1, it);
       launch_ir_update(nd, c->x, c->d32, c->ctl64, s);
       LAUNCHED();
     }
@@ -717,7 +942,7 @@ extern "C" int sw_case_step(sw_case* c, int32_t n) {
     HIPC(hipMemcpyAsync(c->log_rel + c->step, &rel, 8, hipMemcpyHostToDevice, s));
     HIPC(hipStreamSynchronize(s));
     c->step += 1;
-    c->last_iters = std::max(4, iters);
+    c->last_iters = std::max(2, iters);
     c->stats.steps += 1;
     c->stats.cg_iters += iters;
     c->stats.ir_outer += outer;
@@ -762,14 +987,22 @@ extern "C" int sw_case_waveform_device(const sw_case* c, const double** out) {
   return SW_OK;
 }
 
+// The user-order entry points below borrow the case's CG work vectors
+// (p, q, r, z), which hold no state between steps.
 extern "C" int sw_case_apply(sw_case* c, int32_t op, const double* x, double* y) {
   if (!c || !x || !y) return fail(SW_EINVAL, "NULL argument");
   if (!(op == SW_OP_A || (op > 0 && op < 8))) return fail(SW_EINVAL, "bad operator mask %d", op);
   HIPC(hipSetDevice(c->ctx->device));
-  launch_fill_f64(3 * c->mesh->n_nodes, y, 0.0, c->ctx->stream);
-  int rc = apply_op_f64(c, op, x, y, nullptr, -1);
+  const int64_t nn = c->mesh->n_nodes;
+  hipStream_t s = c->ctx->stream;
+  launch_permute_f64(nn, 3, x, c->mesh->dev.node_i2u, c->p, s);
+  launch_fill_f64(3 * nn, c->q, 0.0, s);
+  int rc = apply_f64(c, op, c->p, c->q, nullptr, -1);
   if (rc) return rc;
-  HIPC(hipStreamSynchronize(c->ctx->stream));
+  launch_permute_f64(nn, 3, c->q, c->mesh->dev.node_u2i, y, s);
+  launch_fill_f64(3 * nn, c->q, 0.0, s);
+  LAUNCHED();
+  HIPC(hipStreamSynchronize(s));
   return SW_OK;
 }
 
@@ -777,10 +1010,17 @@ extern "C" int sw_case_apply_f32(sw_case* c, int32_t op, const float* x, float* 
   if (!c || !x || !y) return fail(SW_EINVAL, "NULL argument");
   if (!(op == SW_OP_A || (op > 0 && op < 8))) return fail(SW_EINVAL, "bad operator mask %d", op);
   HIPC(hipSetDevice(c->ctx->device));
-  launch_fill_f32(3 * c->mesh->n_nodes, y, 0.0f, c->ctx->stream);
-  int rc = apply_op_f32(c, op, x, y, nullptr, -1);
+  const int64_t nn = c->mesh->n_nodes;
+  hipStream_t s = c->ctx->stream;
+  float* xi = (float*)c->r;  // FP64 vectors hold twice the floats needed
+  float* yi = (float*)c->z;
+  launch_permute_f32(nn, 3, x, c->mesh->dev.node_i2u, xi, s);
+  launch_fill_f32(3 * nn, yi, 0.0f, s);
+  int rc = apply_f32(c, op, xi, yi, nullptr, -1);
   if (rc) return rc;
-  HIPC(hipStreamSynchronize(c->ctx->stream));
+  launch_permute_f32(nn, 3, yi, c->mesh->dev.node_u2i, y, s);
+  LAUNCHED();
+  HIPC(hipStreamSynchronize(s));
   return SW_OK;
 }
 
@@ -788,8 +1028,10 @@ extern "C" int sw_case_rhs(sw_case* c, double* y) {
   if (!c || !y) return fail(SW_EINVAL, "NULL argument");
   if (c->step >= c->n_steps) return fail(SW_ESTATE, "no further step in the case capacity");
   HIPC(hipSetDevice(c->ctx->device));
-  int rc = build_rhs(c, y);
+  int rc = build_rhs(c, c->r);
   if (rc) return rc;
+  launch_permute_f64(c->mesh->n_nodes, 3, c->r, c->mesh->dev.node_u2i, y, c->ctx->stream);
+  LAUNCHED();
   HIPC(hipStreamSynchronize(c->ctx->stream));
   return SW_OK;
 }
@@ -797,7 +1039,8 @@ extern "C" int sw_case_rhs(sw_case* c, double* y) {
 extern "C" int sw_case_diag_blocks(sw_case* c, double* y) {
   if (!c || !y) return fail(SW_EINVAL, "NULL argument");
   HIPC(hipSetDevice(c->ctx->device));
-  HIPC(hipMemcpyAsync(y, c->diag6, 8 * 6 * (size_t)c->mesh->n_nodes, hipMemcpyDeviceToDevice, c->ctx->stream));
+  launch_permute_f64(c->mesh->n_nodes, 6, c->diag6, c->mesh->dev.node_u2i, y, c->ctx->stream);
+  LAUNCHED();
   HIPC(hipStreamSynchronize(c->ctx->stream));
   return SW_OK;
 }

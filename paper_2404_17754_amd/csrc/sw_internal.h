@@ -12,15 +12,18 @@ struct MatDev {
   double lam, mu, rho, zp, zs;  // Lame constants, density, rho*Vp, rho*Vs
 };
 
-// Device-resident control block of one CG solve (one per case, FP64 scalars
-// whatever the vector precision).  Kernels accumulate the dot products into
-// it and decide convergence from it, so a chunk of iterations runs without
-// the host.
+// Device-resident control block of one CG solve (FP64 scalars whatever the
+// vector precision).  Kernels accumulate the dot products into it and decide
+// convergence from it, so a chunk of iterations runs without the host.  Each
+// dot product is spread over NSLOT partial sums (workgroup w adds into slot
+// w mod NSLOT) so that thousands of workgroups do not serialise on one
+// address; readers add the slots up.
+constexpr int NSLOT = 32;
 struct CgCtl {
-  double pAp;      // p . A p (element energies)
-  double rz[2];    // r . z, ring indexed by iteration parity
-  double rr[2];    // r . r, same ring
-  double bb;       // ||b||^2 of the FP64 right-hand side
+  double pAp[NSLOT];     // p . A p (element energies)
+  double rz[2][NSLOT];   // r . z, ring indexed by iteration parity
+  double rr[2][NSLOT];   // r . r, same ring
+  double bb;       // ||b||^2 of the right-hand side
   double tol2;     // stop when rr <= tol2
   double rr_true;  // ||b - A x||^2 recomputed in FP64
   double scale;    // mixed precision: residual scaling of the inner system
@@ -29,46 +32,57 @@ struct CgCtl {
   int32_t pad[2];
 };
 
-// Mesh in device memory.
+// Tiled mesh in device memory (internal element and node numbering; see
+// sw_layout.h).
 struct MeshDev {
   int64_t n_nodes, n_tets, n_faces;
-  int64_t tet_stride;        // padded n_tets: conn[a * tet_stride + e]
-  const int32_t* conn;       // [10][tet_stride]
-  const double* xyz;         // [n_nodes][3]
-  const int32_t* fconn;      // [6][face_stride]
-  int64_t face_stride;
-  const int32_t* face_tet;   // [n_faces]
-  const uint8_t* face_role;  // [n_faces]
+  int32_t n_tiles, max_tile_nodes;
+  int64_t tet_stride, face_stride;
+  const uint16_t* conn_loc;      // [10][tet_stride]
+  const int32_t* tile_elem_off;  // [n_tiles + 1]
+  const int32_t* tile_node_off;  // [n_tiles + 1]
+  const int32_t* tile_nodes;
+  const int32_t* tile_int_base;
+  const int32_t* tile_nint;
+  const int32_t* tile_face_off;  // [n_tiles + 1]
+  const double* xyz;             // [n_nodes][3]
+  const int32_t* fconn;          // [6][face_stride]
+  const uint16_t* fconn_loc;     // [6][face_stride]
+  const int32_t* face_elem;      // [n_faces]
+  const uint8_t* face_role;      // [n_faces]
+  const int32_t* node_u2i;       // [n_nodes]
+  const int32_t* node_i2u;       // [n_nodes]
 };
 
-// ---- launch wrappers implemented in sw_kernels.hip -----------------------
+// One tiled operator pass:
+//   y (=|+=) sM M xe + sK K xe + sC C_abs xf + F(vin)
+// with xe = a1 x1 + a2 x2 (x2 optional) gathered into LDS per tile, xf read
+// by the face work-items, F the base input force when vin != nullptr.
+template <typename T>
+struct TileArgs {
+  T sM, sK, sC;
+  const T* x1;
+  const T* x2;
+  T a1, a2;
+  const T* xf;
+  const double* vin;   // 3 values or nullptr
+  T* y;
+  int accumulate;      // interior nodes: 0 overwrite, 1 add
+};
 
-enum EbeMode { EBE_APPLY = 0, EBE_RHS = 1 };
-
-// y += sM M x + sK K x.  iter >= 0: CG iteration `iter` of the solve in ctl
-// (early exit when done, p.Ap accumulated into ctl); iter < 0: plain apply.
-void launch_ebe_apply_f64(const MeshDev& m, const uint8_t* tet_mat, const MatDev* mats, double sM, double sK,
-                          const double* x, double* y, CgCtl* ctl, int iter, hipStream_t s);
-void launch_ebe_apply_f32(const MeshDev& m, const uint8_t* tet_mat, const MatDev* mats, double sM, double sK,
-                          const float* x, float* y, CgCtl* ctl, int iter, hipStream_t s);
-// y += M (a + c1 v) - K (u - bR v)
-void launch_ebe_rhs(const MeshDev& m, const uint8_t* tet_mat, const MatDev* mats, double c1, double bR,
-                    const double* u, const double* v, const double* a, double* y, hipStream_t s);
-// y += s C_abs x (+ energy)
-void launch_face_apply_f64(const MeshDev& m, const uint8_t* tet_mat, const MatDev* mats, double sc,
-                           const double* x, double* y, CgCtl* ctl, hipStream_t s);
-void launch_face_apply_f32(const MeshDev& m, const uint8_t* tet_mat, const MatDev* mats, double sc,
-                           const float* x, float* y, CgCtl* ctl, hipStream_t s);
-// y += C_abs v + F(v_in) on base faces
-void launch_face_rhs(const MeshDev& m, const uint8_t* tet_mat, const MatDev* mats, const double* v,
-                     const double* vin3, double* y, hipStream_t s);
-
-void launch_diag_blocks(const MeshDev& m, const uint8_t* tet_mat, const MatDev* mats, double cM, double cK,
-                        double cC, double* diag6, hipStream_t s);
+// Launches (sw_kernels.hip).  iter >= 0: CG iteration `iter` of the solve in
+// ctl (early exit when done, p.Ap accumulated into ctl); iter < 0: plain.
+void launch_tile_f64(const MeshDev& m, const uint8_t* emat, const MatDev* mats, const TileArgs<double>& a,
+                     CgCtl* ctl, int iter, hipStream_t s);
+void launch_tile_f32(const MeshDev& m, const uint8_t* emat, const MatDev* mats, const TileArgs<float>& a,
+                     CgCtl* ctl, int iter, hipStream_t s);
+// Diagonal 3x3 blocks (6 values per node) of cM M + cK K + cC C_abs.
+void launch_tile_diag(const MeshDev& m, const uint8_t* emat, const MatDev* mats, double cM, double cK, double cC,
+                      double* diag6, hipStream_t s);
 void launch_invert_blocks(int64_t n_nodes, const double* diag6, double* pinv64, float* pinv32, int* bad,
                           hipStream_t s);
 
-// CG vector kernels, T = double or float vectors; pinv in matching precision
+// CG vector kernels (node-parallel), T = double or float vectors
 void launch_cg_init_f64(int64_t n_nodes, const double* b, const double* q, const double* pinv, double* r, double* z,
                         double* p, double* qz, CgCtl* ctl, hipStream_t s);
 void launch_cg_init_f32(int64_t n_nodes, const float* b, const float* q, const float* pinv, float* r, float* z,
@@ -82,29 +96,31 @@ void launch_cg_dir_f64(int64_t n_nodes, int par, int iter_abs, int max_iter, con
 void launch_cg_dir_f32(int64_t n_nodes, int par, int iter_abs, int max_iter, const float* z, float* p,
                        CgCtl* ctl, hipStream_t s);
 
-// ctl setup: bb = ||b||^2 must already be in ctl; sets tol2 = rtol^2 bb and clears the rest
-void launch_ctl_prepare(CgCtl* ctl, double rtol, int clear_bb, hipStream_t s);
+// ctl setup: bb must already be in ctl; sets tol2 = rtol^2 bb, clears the rest
+void launch_ctl_prepare(CgCtl* ctl, double rtol, hipStream_t s);
 void launch_norm2(int64_t n, const double* x, double* out, hipStream_t s);
 
-// mixed precision glue
-// r64 = b - q64, rr_true -> ctl; also r32 = r64 / ||r64|| once the norm is known (second kernel)
+// r = b - q, rr_true -> ctl
 void launch_true_residual(int64_t n, const double* b, const double* q, double* r, CgCtl* ctl, hipStream_t s);
+// r32 = r64 / ||r64|| (||r64|| from ctl->rr_true, kept in ctl->scale)
 void launch_to_f32_scaled(int64_t n, const double* r64, float* r32, CgCtl* ctl, hipStream_t s);
+// x64 += ctl->scale * d32
 void launch_ir_update(int64_t n, double* x64, const float* d32, const CgCtl* ctl, hipStream_t s);
 
-// initial guess: x = sum_j coef[j] hist[(head - j) mod 4]; zero if ctl->bb == 0
+// x = sum_j coef[j] hist[(head - j) mod 4]; zero if ctl->bb == 0
 void launch_guess_poly(int64_t n, const double* hist, int head, int order, double* x, const CgCtl* ctl,
                        hipStream_t s);
 
-// Newmark update, history push, receiver record, step log
 void launch_newmark(int64_t n, double dt, const double* du, double* u, double* v, double* a, double* hist_slot,
                     hipStream_t s);
 void launch_record(int n_rec, const int32_t* rec, const double* v, double* wave_row, hipStream_t s);
-void launch_step_log(const CgCtl* ctl, int32_t* iters_out, double* relres_out, int32_t* iter_total, hipStream_t s);
 
-// misfit: per-pair sums then the mean
 void launch_misfit(int n_rec, int64_t n_steps, const double* U, const double* obs, double* pair_buf,
                    double* out2, hipStream_t s);
+
+// dst[i*w + k] = src[map[i]*w + k], i < n, k < w (w <= 6)
+void launch_permute_f64(int64_t n, int w, const double* src, const int32_t* map, double* dst, hipStream_t s);
+void launch_permute_f32(int64_t n, int w, const float* src, const int32_t* map, float* dst, hipStream_t s);
 
 void launch_fill_f64(int64_t n, double* x, double val, hipStream_t s);
 void launch_fill_f32(int64_t n, float* x, float val, hipStream_t s);

@@ -1,322 +1,18 @@
-// HIP kernels (gfx950) of the implicit wave-propagation step: matrix-free
-// element-by-element operator, boundary faces, 3x3 block-Jacobi
-// preconditioner, fused CG vector updates with wavefront reductions, Newmark
+// Node-parallel HIP kernels (gfx950) of the implicit wave-propagation step:
+// fused CG vector updates with the 3x3 block-Jacobi preconditioner, dot
+// products, mixed-precision refinement glue, initial guesses, the Newmark
 // update, receiver recording and the ERR misfit of Eq. (eqerr).
 //
-// Every vector is node-major [node][3].  One work-item handles one tet, one
-// face or one node; partial dot products are reduced across the 64-wide
-// wavefront with shuffles, across the workgroup through LDS, and across the
-// grid with one FP64 atomic per workgroup into a device control block.
+// Every vector is node-major [node][3] in the mesh's internal node order.
+// Partial dot products are reduced across the 64-wide wavefront with
+// shuffles, across the workgroup through LDS, and across the grid with one
+// FP64 atomic per workgroup into a device control block.
 #include <hip/hip_runtime.h>
 
-#include "sw_elem.h"
+#include "sw_device.h"
 #include "sw_internal.h"
 
 namespace sw {
-
-constexpr int TPB = 256;
-
-__device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-  return v;
-}
-
-// Sum of v over the workgroup, returned on thread 0 (TPB threads).
-__device__ __forceinline__ double block_sum(double v, double* sh) {
-  v = wave_sum(v);
-  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-  if (lane == 0) sh[wid] = v;
-  __syncthreads();
-  double t = 0.0;
-  if (threadIdx.x == 0) {
-#pragma unroll
-    for (int i = 0; i < TPB / 64; ++i) t += sh[i];
-  }
-  return t;
-}
-
-__device__ __forceinline__ void block_sum2(double& a, double& b, double* sh) {
-  a = wave_sum(a);
-  b = wave_sum(b);
-  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-  if (lane == 0) {
-    sh[wid] = a;
-    sh[TPB / 64 + wid] = b;
-  }
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    a = 0.0;
-    b = 0.0;
-#pragma unroll
-    for (int i = 0; i < TPB / 64; ++i) {
-      a += sh[i];
-      b += sh[TPB / 64 + i];
-    }
-  }
-}
-
-__device__ __forceinline__ void atomic_add(double* p, double v) { unsafeAtomicAdd(p, v); }
-__device__ __forceinline__ void atomic_add(float* p, float v) { unsafeAtomicAdd(p, v); }
-
-static inline unsigned nblocks(int64_t n) { return (unsigned)((n + TPB - 1) / TPB); }
-
-// ------------------------------------------------------------ EBE operator
-
-// Iteration-mode protocol (par >= 0): the kernel returns at once when the
-// solve is done; on the first iteration it also ends a solve whose initial
-// residual already meets the tolerance; workgroup 0 clears the scalar slots
-// that the next update kernel accumulates into.  par < 0: plain application.
-template <typename T, int MODE>
-__global__ __launch_bounds__(TPB) void k_ebe(MeshDev m, const uint8_t* __restrict__ tet_mat,
-                                             const MatDev* __restrict__ mats, T sM, T sK,
-                                             const T* __restrict__ x, T* __restrict__ y,
-                                             const double* __restrict__ u, const double* __restrict__ v,
-                                             const double* __restrict__ a, double c1, double bR, CgCtl* ctl,
-                                             int iter) {
-  __shared__ double sh[2 * TPB / 64];
-  const int par = iter & 1, first_iter = iter == 0;
-  if (iter >= 0) {
-    if (ctl->done) return;
-    if (first_iter && ctl->rr[0] <= ctl->tol2) {
-      if (blockIdx.x == 0 && threadIdx.x == 0) ctl->done = 1;
-      return;
-    }
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
-      ctl->rz[par ^ 1] = 0.0;
-      ctl->rr[par ^ 1] = 0.0;
-    }
-  }
-  const int64_t e = (int64_t)blockIdx.x * TPB + threadIdx.x;
-  double energy = 0.0;
-  if (e < m.n_tets) {
-    int nd[10];
-#pragma unroll
-    for (int k = 0; k < 10; ++k) nd[k] = m.conn[k * m.tet_stride + e];
-    double X[4][3];
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-#pragma unroll
-      for (int d = 0; d < 3; ++d) X[k][d] = m.xyz[3 * (int64_t)nd[k] + d];
-    }
-    Geo<T> G;
-    tet_geometry<T>(X, G);
-    const MatDev mt = mats[tet_mat[e]];
-    T out[10][3];
-#pragma unroll
-    for (int k = 0; k < 10; ++k) out[k][0] = out[k][1] = out[k][2] = (T)0;
-    if (MODE == EBE_APPLY) {
-      T w[10][3];
-#pragma unroll
-      for (int k = 0; k < 10; ++k) {
-#pragma unroll
-        for (int c = 0; c < 3; ++c) w[k][c] = x[3 * (int64_t)nd[k] + c];
-      }
-      stiffness_apply<T>(G, (T)mt.lam, (T)mt.mu, sK, w, out);
-      mass_apply<T>((T)mt.rho * G.vol, sM, w, out);
-      if (ctl != nullptr) {
-#pragma unroll
-        for (int k = 0; k < 10; ++k) {
-#pragma unroll
-          for (int c = 0; c < 3; ++c) energy += (double)w[k][c] * (double)out[k][c];
-        }
-      }
-    } else {
-      T w1[10][3], w2[10][3];
-#pragma unroll
-      for (int k = 0; k < 10; ++k) {
-#pragma unroll
-        for (int c = 0; c < 3; ++c) {
-          const int64_t i = 3 * (int64_t)nd[k] + c;
-          const double vv = v[i];
-          w1[k][c] = (T)(a[i] + c1 * vv);
-          w2[k][c] = (T)(u[i] - bR * vv);
-        }
-      }
-      stiffness_apply<T>(G, (T)mt.lam, (T)mt.mu, (T)-1, w2, out);
-      mass_apply<T>((T)mt.rho * G.vol, (T)1, w1, out);
-    }
-#pragma unroll
-    for (int k = 0; k < 10; ++k) {
-#pragma unroll
-      for (int c = 0; c < 3; ++c) atomic_add(&y[3 * (int64_t)nd[k] + c], out[k][c]);
-    }
-  }
-  if (ctl != nullptr && MODE == EBE_APPLY) {
-    double t = block_sum(energy, sh);
-    if (threadIdx.x == 0) atomic_add(&ctl->pAp, t);
-  }
-}
-
-void launch_ebe_apply_f64(const MeshDev& m, const uint8_t* tet_mat, const MatDev* mats, double sM, double sK,
-                          const double* x, double* y, CgCtl* ctl, int iter, hipStream_t s) {
-  hipLaunchKernelGGL((k_ebe<double, EBE_APPLY>), dim3(nblocks(m.n_tets)), dim3(TPB), 0, s, m, tet_mat, mats, sM, sK,
-                     x, y, nullptr, nullptr, nullptr, 0.0, 0.0, ctl, iter);
-}
-void launch_ebe_apply_f32(const MeshDev& m, const uint8_t* tet_mat, const MatDev* mats, double sM, double sK,
-                          const float* x, float* y, CgCtl* ctl, int iter, hipStream_t s) {
-  hipLaunchKernelGGL((k_ebe<float, EBE_APPLY>), dim3(nblocks(m.n_tets)), dim3(TPB), 0, s, m, tet_mat, mats,
-                     (float)sM, (float)sK, x, y, nullptr, nullptr, nullptr, 0.0, 0.0, ctl, iter);
-}
-void launch_ebe_rhs(const MeshDev& m, const uint8_t* tet_mat, const MatDev* mats, double c1, double bR,
-                    const double* u, const double* v, const double* a, double* y, hipStream_t s) {
-  hipLaunchKernelGGL((k_ebe<double, EBE_RHS>), dim3(nblocks(m.n_tets)), dim3(TPB), 0, s, m, tet_mat, mats, 1.0, -1.0,
-                     (const double*)nullptr, y, u, v, a, c1, bR, (CgCtl*)nullptr, -1);
-}
-
-// ------------------------------------------------------------------ faces
-
-template <typename T, int MODE>
-__global__ __launch_bounds__(TPB) void k_face(MeshDev m, const uint8_t* __restrict__ tet_mat,
-                                              const MatDev* __restrict__ mats, T sc, const T* __restrict__ x,
-                                              T* __restrict__ y, CgCtl* ctl, const double* __restrict__ vin3) {
-  __shared__ double sh[2 * TPB / 64];
-  if (ctl != nullptr && ctl->done) return;
-  const int64_t f = (int64_t)blockIdx.x * TPB + threadIdx.x;
-  double energy = 0.0;
-  if (f < m.n_faces) {
-    int nd[6];
-#pragma unroll
-    for (int k = 0; k < 6; ++k) nd[k] = m.fconn[k * m.face_stride + f];
-    double P[3][3];
-#pragma unroll
-    for (int k = 0; k < 3; ++k) {
-#pragma unroll
-      for (int d = 0; d < 3; ++d) P[k][d] = m.xyz[3 * (int64_t)nd[k] + d];
-    }
-    const FaceGeo g = face_geometry(P);
-    const MatDev mt = mats[tet_mat[m.face_tet[f]]];
-    T w[6][3], out[6][3];
-#pragma unroll
-    for (int k = 0; k < 6; ++k) {
-#pragma unroll
-      for (int c = 0; c < 3; ++c) {
-        w[k][c] = x[3 * (int64_t)nd[k] + c];
-        out[k][c] = (T)0;
-      }
-    }
-    const T n[3] = {(T)g.n[0], (T)g.n[1], (T)g.n[2]};
-    face_dashpot_apply<T>(n, (T)g.area, (T)mt.zp, (T)mt.zs, sc, w, out);
-    if (MODE == EBE_RHS && m.face_role[f] == 2) {
-      // incident wave: traction 2 Z v_in, consistent load A/3 on edge nodes
-      const double vi[3] = {vin3[0], vin3[1], vin3[2]};
-      const double nv = g.n[0] * vi[0] + g.n[1] * vi[1] + g.n[2] * vi[2];
-      const double w3 = g.area / 3.0;
-#pragma unroll
-      for (int c = 0; c < 3; ++c) {
-        const double t = 2.0 * (mt.zs * vi[c] + (mt.zp - mt.zs) * nv * g.n[c]);
-        out[3][c] += (T)(w3 * t);
-        out[4][c] += (T)(w3 * t);
-        out[5][c] += (T)(w3 * t);
-      }
-    }
-#pragma unroll
-    for (int k = 0; k < 6; ++k) {
-#pragma unroll
-      for (int c = 0; c < 3; ++c) {
-        atomic_add(&y[3 * (int64_t)nd[k] + c], out[k][c]);
-        energy += (double)w[k][c] * (double)out[k][c];
-      }
-    }
-  }
-  if (ctl != nullptr) {
-    double t = block_sum(energy, sh);
-    if (threadIdx.x == 0) atomic_add(&ctl->pAp, t);
-  }
-}
-
-void launch_face_apply_f64(const MeshDev& m, const uint8_t* tet_mat, const MatDev* mats, double sc,
-                           const double* x, double* y, CgCtl* ctl, hipStream_t s) {
-  if (m.n_faces == 0) return;
-  hipLaunchKernelGGL((k_face<double, EBE_APPLY>), dim3(nblocks(m.n_faces)), dim3(TPB), 0, s, m, tet_mat, mats, sc, x,
-                     y, ctl, (const double*)nullptr);
-}
-void launch_face_apply_f32(const MeshDev& m, const uint8_t* tet_mat, const MatDev* mats, double sc,
-                           const float* x, float* y, CgCtl* ctl, hipStream_t s) {
-  if (m.n_faces == 0) return;
-  hipLaunchKernelGGL((k_face<float, EBE_APPLY>), dim3(nblocks(m.n_faces)), dim3(TPB), 0, s, m, tet_mat, mats,
-                     (float)sc, x, y, ctl, (const double*)nullptr);
-}
-void launch_face_rhs(const MeshDev& m, const uint8_t* tet_mat, const MatDev* mats, const double* v,
-                     const double* vin3, double* y, hipStream_t s) {
-  if (m.n_faces == 0) return;
-  hipLaunchKernelGGL((k_face<double, EBE_RHS>), dim3(nblocks(m.n_faces)), dim3(TPB), 0, s, m, tet_mat, mats, 1.0, v,
-                     y, (CgCtl*)nullptr, vin3);
-}
-
-// --------------------------------------------------------- block Jacobi
-
-__global__ __launch_bounds__(TPB) void k_diag_elem(MeshDev m, const uint8_t* __restrict__ tet_mat,
-                                                   const MatDev* __restrict__ mats, double cM, double cK,
-                                                   double* __restrict__ diag6) {
-  const int64_t e = (int64_t)blockIdx.x * TPB + threadIdx.x;
-  if (e >= m.n_tets) return;
-  int nd[10];
-  for (int k = 0; k < 10; ++k) nd[k] = m.conn[k * m.tet_stride + e];
-  double X[4][3];
-  for (int k = 0; k < 4; ++k)
-    for (int d = 0; d < 3; ++d) X[k][d] = m.xyz[3 * (int64_t)nd[k] + d];
-  Geo<double> G;
-  tet_geometry<double>(X, G);
-  const MatDev mt = mats[tet_mat[e]];
-  double out[10][6];
-  diag_blocks<double>(G, mt.lam, mt.mu, mt.rho, cM, cK, out);
-  for (int k = 0; k < 10; ++k)
-    for (int j = 0; j < 6; ++j) atomic_add(&diag6[6 * (int64_t)nd[k] + j], out[k][j]);
-}
-
-__global__ __launch_bounds__(TPB) void k_diag_face(MeshDev m, const uint8_t* __restrict__ tet_mat,
-                                                   const MatDev* __restrict__ mats, double cC,
-                                                   double* __restrict__ diag6) {
-  const int64_t f = (int64_t)blockIdx.x * TPB + threadIdx.x;
-  if (f >= m.n_faces) return;
-  int nd[6];
-  for (int k = 0; k < 6; ++k) nd[k] = m.fconn[k * m.face_stride + f];
-  double P[3][3];
-  for (int k = 0; k < 3; ++k)
-    for (int d = 0; d < 3; ++d) P[k][d] = m.xyz[3 * (int64_t)nd[k] + d];
-  const FaceGeo g = face_geometry(P);
-  const MatDev mt = mats[tet_mat[m.face_tet[f]]];
-  const double dz = mt.zp - mt.zs;
-  const double Z[6] = {mt.zs + dz * g.n[0] * g.n[0], mt.zs + dz * g.n[1] * g.n[1], mt.zs + dz * g.n[2] * g.n[2],
-                       dz * g.n[1] * g.n[2],         dz * g.n[0] * g.n[2],         dz * g.n[0] * g.n[1]};
-  for (int k = 0; k < 6; ++k) {
-    const double s = cC * g.area / 180.0 * (k < 3 ? 6.0 : 32.0);
-    for (int j = 0; j < 6; ++j) atomic_add(&diag6[6 * (int64_t)nd[k] + j], s * Z[j]);
-  }
-}
-
-__global__ __launch_bounds__(TPB) void k_invert(int64_t n, const double* __restrict__ d6, double* __restrict__ p64,
-                                                float* __restrict__ p32, int* bad) {
-  const int64_t i = (int64_t)blockIdx.x * TPB + threadIdx.x;
-  if (i >= n) return;
-  const double a = d6[6 * i + 0], b = d6[6 * i + 1], c = d6[6 * i + 2];
-  const double yz = d6[6 * i + 3], xz = d6[6 * i + 4], xy = d6[6 * i + 5];
-  // inverse of [[a xy xz][xy b yz][xz yz c]] by cofactors
-  const double c00 = b * c - yz * yz, c11 = a * c - xz * xz, c22 = a * b - xy * xy;
-  const double c12 = -(a * yz - xy * xz), c02 = xy * yz - b * xz, c01 = -(xy * c - yz * xz);
-  const double det = a * c00 + xy * c01 + xz * c02;
-  if (!(det > 0.0) || !(a > 0.0)) {
-    *bad = 1;
-  }
-  const double id = 1.0 / det;
-  const double r[6] = {c00 * id, c11 * id, c22 * id, c12 * id, c02 * id, c01 * id};
-  for (int k = 0; k < 6; ++k) {
-    p64[6 * i + k] = r[k];
-    p32[6 * i + k] = (float)r[k];
-  }
-}
-
-void launch_diag_blocks(const MeshDev& m, const uint8_t* tet_mat, const MatDev* mats, double cM, double cK,
-                        double cC, double* diag6, hipStream_t s) {
-  hipLaunchKernelGGL(k_diag_elem, dim3(nblocks(m.n_tets)), dim3(TPB), 0, s, m, tet_mat, mats, cM, cK, diag6);
-  if (m.n_faces)
-    hipLaunchKernelGGL(k_diag_face, dim3(nblocks(m.n_faces)), dim3(TPB), 0, s, m, tet_mat, mats, cC, diag6);
-}
-void launch_invert_blocks(int64_t n_nodes, const double* diag6, double* pinv64, float* pinv32, int* bad,
-                          hipStream_t s) {
-  hipLaunchKernelGGL(k_invert, dim3(nblocks(n_nodes)), dim3(TPB), 0, s, n_nodes, diag6, pinv64, pinv32, bad);
-}
 
 // --------------------------------------------------------- CG vector ops
 
@@ -329,15 +25,21 @@ __device__ __forceinline__ void bj_apply(const T* __restrict__ P, int64_t i, con
   z[2] = xz * r[0] + yz * r[1] + c * r[2];
 }
 
+// Grid for the node-parallel kernels: grid-stride loops over a capped grid
+// (enough workgroups to fill 256 CUs several times over).
+static inline unsigned vgrid(int64_t n) {
+  unsigned g = nblocks(n);
+  return g > 2048 ? 2048 : (g == 0 ? 1 : g);
+}
+
 // r = b - q, z = P r, p = z, q = 0; rz[0], rr[0]
 template <typename T>
 __global__ __launch_bounds__(TPB) void k_cg_init(int64_t n, const T* __restrict__ b, const T* __restrict__ q,
                                                  const T* __restrict__ P, T* __restrict__ r, T* __restrict__ z,
                                                  T* __restrict__ p, T* __restrict__ qz, CgCtl* ctl) {
   __shared__ double sh[2 * TPB / 64];
-  const int64_t i = (int64_t)blockIdx.x * TPB + threadIdx.x;
   double rz = 0.0, rr = 0.0;
-  if (i < n) {
+  for (int64_t i = (int64_t)blockIdx.x * TPB + threadIdx.x; i < n; i += (int64_t)gridDim.x * TPB) {
     T rv[3], zv[3];
 #pragma unroll
     for (int c = 0; c < 3; ++c) rv[c] = b[3 * i + c] - (q ? q[3 * i + c] : (T)0);
@@ -354,8 +56,8 @@ __global__ __launch_bounds__(TPB) void k_cg_init(int64_t n, const T* __restrict_
   }
   block_sum2(rz, rr, sh);
   if (threadIdx.x == 0) {
-    atomic_add(&ctl->rz[0], rz);
-    atomic_add(&ctl->rr[0], rr);
+    atomic_add(&ctl->rz[0][blockIdx.x % NSLOT], rz);
+    atomic_add(&ctl->rr[0][blockIdx.x % NSLOT], rr);
   }
 }
 
@@ -367,10 +69,9 @@ __global__ __launch_bounds__(TPB) void k_cg_update(int64_t n, int par, const T* 
                                                    T* __restrict__ q, CgCtl* ctl) {
   __shared__ double sh[2 * TPB / 64];
   if (ctl->done) return;
-  const T alpha = (T)(ctl->rz[par] / ctl->pAp);
-  const int64_t i = (int64_t)blockIdx.x * TPB + threadIdx.x;
+  const T alpha = (T)(slot_sum<NSLOT>(ctl->rz[par]) / slot_sum<NSLOT>(ctl->pAp));
   double rz = 0.0, rr = 0.0;
-  if (i < n) {
+  for (int64_t i = (int64_t)blockIdx.x * TPB + threadIdx.x; i < n; i += (int64_t)gridDim.x * TPB) {
     T rv[3], zv[3];
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
@@ -390,8 +91,8 @@ __global__ __launch_bounds__(TPB) void k_cg_update(int64_t n, int par, const T* 
   }
   block_sum2(rz, rr, sh);
   if (threadIdx.x == 0) {
-    atomic_add(&ctl->rz[par ^ 1], rz);
-    atomic_add(&ctl->rr[par ^ 1], rr);
+    atomic_add(&ctl->rz[par ^ 1][blockIdx.x % NSLOT], rz);
+    atomic_add(&ctl->rr[par ^ 1][blockIdx.x % NSLOT], rr);
   }
 }
 
@@ -400,17 +101,18 @@ template <typename T>
 __global__ __launch_bounds__(TPB) void k_cg_dir(int64_t n, int par, int iter_abs, int max_iter,
                                                 const T* __restrict__ z, T* __restrict__ p, CgCtl* ctl) {
   if (ctl->done) return;
-  const double rr = ctl->rr[par ^ 1];
+  const double rr = slot_sum<NSLOT>(ctl->rr[par ^ 1]);
   const bool stop = !(rr > ctl->tol2) || (iter_abs + 1 >= max_iter);  // NaN stops too
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
-    ctl->iters = iter_abs + 1;
-    if (stop) ctl->done = 1;
-    ctl->pAp = 0.0;
+  const T beta = (T)(slot_sum<NSLOT>(ctl->rz[par ^ 1]) / slot_sum<NSLOT>(ctl->rz[par]));
+  if (blockIdx.x == 0) {
+    if (threadIdx.x == 0) {
+      ctl->iters = iter_abs + 1;
+      if (stop) ctl->done = 1;
+    }
+    if (threadIdx.x < NSLOT) ctl->pAp[threadIdx.x] = 0.0;
   }
   if (stop) return;
-  const T beta = (T)(ctl->rz[par ^ 1] / ctl->rz[par]);
-  const int64_t i = (int64_t)blockIdx.x * TPB + threadIdx.x;
-  if (i < n) {
+  for (int64_t i = (int64_t)blockIdx.x * TPB + threadIdx.x; i < n; i += (int64_t)gridDim.x * TPB) {
 #pragma unroll
     for (int c = 0; c < 3; ++c) p[3 * i + c] = z[3 * i + c] + beta * p[3 * i + c];
   }
@@ -418,44 +120,47 @@ __global__ __launch_bounds__(TPB) void k_cg_dir(int64_t n, int par, int iter_abs
 
 void launch_cg_init_f64(int64_t n, const double* b, const double* q, const double* P, double* r, double* z, double* p,
                         double* qz, CgCtl* ctl, hipStream_t s) {
-  hipLaunchKernelGGL(k_cg_init<double>, dim3(nblocks(n)), dim3(TPB), 0, s, n, b, q, P, r, z, p, qz, ctl);
+  hipLaunchKernelGGL(k_cg_init<double>, dim3(vgrid(n)), dim3(TPB), 0, s, n, b, q, P, r, z, p, qz, ctl);
 }
 void launch_cg_init_f32(int64_t n, const float* b, const float* q, const float* P, float* r, float* z, float* p,
                         float* qz, CgCtl* ctl, hipStream_t s) {
-  hipLaunchKernelGGL(k_cg_init<float>, dim3(nblocks(n)), dim3(TPB), 0, s, n, b, q, P, r, z, p, qz, ctl);
+  hipLaunchKernelGGL(k_cg_init<float>, dim3(vgrid(n)), dim3(TPB), 0, s, n, b, q, P, r, z, p, qz, ctl);
 }
 void launch_cg_update_f64(int64_t n, int par, const double* P, double* x, double* r, double* z, const double* p,
                           double* q, CgCtl* ctl, hipStream_t s) {
-  hipLaunchKernelGGL(k_cg_update<double>, dim3(nblocks(n)), dim3(TPB), 0, s, n, par, P, x, r, z, p, q, ctl);
+  hipLaunchKernelGGL(k_cg_update<double>, dim3(vgrid(n)), dim3(TPB), 0, s, n, par, P, x, r, z, p, q, ctl);
 }
 void launch_cg_update_f32(int64_t n, int par, const float* P, float* x, float* r, float* z, const float* p, float* q,
                           CgCtl* ctl, hipStream_t s) {
-  hipLaunchKernelGGL(k_cg_update<float>, dim3(nblocks(n)), dim3(TPB), 0, s, n, par, P, x, r, z, p, q, ctl);
+  hipLaunchKernelGGL(k_cg_update<float>, dim3(vgrid(n)), dim3(TPB), 0, s, n, par, P, x, r, z, p, q, ctl);
 }
 void launch_cg_dir_f64(int64_t n, int par, int iter_abs, int max_iter, const double* z, double* p, CgCtl* ctl,
                        hipStream_t s) {
-  hipLaunchKernelGGL(k_cg_dir<double>, dim3(nblocks(n)), dim3(TPB), 0, s, n, par, iter_abs, max_iter, z, p, ctl);
+  hipLaunchKernelGGL(k_cg_dir<double>, dim3(vgrid(n)), dim3(TPB), 0, s, n, par, iter_abs, max_iter, z, p, ctl);
 }
 void launch_cg_dir_f32(int64_t n, int par, int iter_abs, int max_iter, const float* z, float* p, CgCtl* ctl,
                        hipStream_t s) {
-  hipLaunchKernelGGL(k_cg_dir<float>, dim3(nblocks(n)), dim3(TPB), 0, s, n, par, iter_abs, max_iter, z, p, ctl);
+  hipLaunchKernelGGL(k_cg_dir<float>, dim3(vgrid(n)), dim3(TPB), 0, s, n, par, iter_abs, max_iter, z, p, ctl);
 }
 
 // ------------------------------------------------------------ scalars
 
-__global__ void k_ctl_prepare(CgCtl* ctl, double rtol, int clear_bb) {
-  if (threadIdx.x != 0) return;
-  if (clear_bb) ctl->bb = 0.0;
-  ctl->tol2 = rtol * rtol * ctl->bb;
-  ctl->pAp = 0.0;
-  ctl->rz[0] = ctl->rz[1] = 0.0;
-  ctl->rr[0] = ctl->rr[1] = 0.0;
-  ctl->rr_true = 0.0;
-  ctl->done = 0;
-  ctl->iters = 0;
+__global__ void k_ctl_prepare(CgCtl* ctl, double rtol) {
+  const int i = threadIdx.x;
+  if (i < NSLOT) {
+    ctl->pAp[i] = 0.0;
+    ctl->rz[0][i] = ctl->rz[1][i] = 0.0;
+    ctl->rr[0][i] = ctl->rr[1][i] = 0.0;
+  }
+  if (i == 0) {
+    ctl->tol2 = rtol * rtol * ctl->bb;
+    ctl->rr_true = 0.0;
+    ctl->done = 0;
+    ctl->iters = 0;
+  }
 }
-void launch_ctl_prepare(CgCtl* ctl, double rtol, int clear_bb, hipStream_t s) {
-  hipLaunchKernelGGL(k_ctl_prepare, dim3(1), dim3(64), 0, s, ctl, rtol, clear_bb);
+void launch_ctl_prepare(CgCtl* ctl, double rtol, hipStream_t s) {
+  hipLaunchKernelGGL(k_ctl_prepare, dim3(1), dim3(64), 0, s, ctl, rtol);
 }
 
 __global__ __launch_bounds__(TPB) void k_norm2(int64_t n, const double* __restrict__ x, double* out) {
@@ -574,16 +279,6 @@ void launch_record(int n_rec, const int32_t* rec, const double* v, double* row, 
   hipLaunchKernelGGL(k_record, dim3((3 * n_rec + 255) / 256), dim3(256), 0, s, n_rec, rec, v, row);
 }
 
-__global__ void k_step_log(const CgCtl* ctl, int32_t* it, double* rel, int32_t* total) {
-  if (threadIdx.x != 0) return;
-  *it = ctl->iters;
-  *rel = ctl->bb > 0.0 ? sqrt(ctl->rr_true / ctl->bb) : 0.0;
-  if (total) *total += ctl->iters;
-}
-void launch_step_log(const CgCtl* ctl, int32_t* it, double* rel, int32_t* total, hipStream_t s) {
-  hipLaunchKernelGGL(k_step_log, dim3(1), dim3(64), 0, s, ctl, it, rel, total);
-}
-
 // --------------------------------------------------------------- misfit
 
 // pair_buf[2 * pair] = sum_t (U - obs)^2, pair_buf[2 * pair + 1] = sum_t obs^2
@@ -663,6 +358,27 @@ void launch_fill_f32(int64_t n, float* x, float val, hipStream_t s) {
   unsigned g = nblocks(n);
   if (g > 16384) g = 16384;
   hipLaunchKernelGGL(k_fill<float>, dim3(g), dim3(TPB), 0, s, n, x, val);
+}
+
+// ---------------------------------------------------------- permutation
+
+template <typename T>
+__global__ __launch_bounds__(TPB) void k_permute(int64_t n, int w, const T* __restrict__ src,
+                                                 const int32_t* __restrict__ map, T* __restrict__ dst) {
+  for (int64_t k = (int64_t)blockIdx.x * TPB + threadIdx.x; k < n * w; k += (int64_t)gridDim.x * TPB) {
+    const int64_t i = k / w;
+    dst[k] = src[(int64_t)map[i] * w + (k - i * w)];
+  }
+}
+void launch_permute_f64(int64_t n, int w, const double* src, const int32_t* map, double* dst, hipStream_t s) {
+  unsigned g = nblocks(n * w);
+  if (g > 16384) g = 16384;
+  hipLaunchKernelGGL(k_permute<double>, dim3(g), dim3(TPB), 0, s, n, w, src, map, dst);
+}
+void launch_permute_f32(int64_t n, int w, const float* src, const int32_t* map, float* dst, hipStream_t s) {
+  unsigned g = nblocks(n * w);
+  if (g > 16384) g = 16384;
+  hipLaunchKernelGGL(k_permute<float>, dim3(g), dim3(TPB), 0, s, n, w, src, map, dst);
 }
 
 }  // namespace sw

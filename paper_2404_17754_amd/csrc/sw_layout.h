@@ -1,0 +1,41 @@
+// Host-side tiled mesh layout (built by sw_mesh.cpp, uploaded by sw_api.cpp).
+#pragma once
+
+#include <cstdint>
+#include <vector>
+
+namespace sw {
+
+// A tile's node values and accumulators live in LDS: FP64 needs 48 bytes per
+// node (input + accumulator, 3 components each) plus a 4-byte node id, so 1536
+// nodes take 78 KB and
+// two tiles fit in the 160 KB LDS of a gfx950 compute unit.
+constexpr int TILE_MAX_NODES = 1536;
+constexpr int TILE_MAX_ELEMS = 1024;
+
+struct HostLayout {
+  int64_t n_nodes = 0, n_tets = 0, n_faces = 0;
+  int32_t n_tiles = 0;
+  int32_t max_tile_nodes = 0;
+  int64_t tet_stride = 0, face_stride = 0;
+  std::vector<int32_t> elem_order;     // internal element i = user element elem_order[i]
+  std::vector<int32_t> elem_u2i;       // user element -> internal
+  std::vector<int32_t> node_u2i, node_i2u;
+  std::vector<int32_t> tile_elem_off;  // [n_tiles + 1]
+  std::vector<int32_t> tile_node_off;  // [n_tiles + 1]
+  std::vector<int32_t> tile_nodes;     // internal node ids, per tile: interior then shared
+  std::vector<int32_t> tile_int_base;  // first interior node id of each tile
+  std::vector<int32_t> tile_nint;      // interior node count of each tile
+  std::vector<int32_t> tile_face_off;  // [n_tiles + 1]
+  std::vector<uint16_t> conn_loc;      // [10][tet_stride] tile-local node index
+  std::vector<double> xyz;             // [n_nodes][3] internal order
+  std::vector<int32_t> fconn;          // [6][face_stride] internal node ids
+  std::vector<uint16_t> fconn_loc;     // [6][face_stride] tile-local node index
+  std::vector<int32_t> face_elem;      // internal element owning each face
+  std::vector<uint8_t> face_role;
+};
+
+void build_layout(int64_t n_nodes, int64_t n_tets, int64_t n_faces, const double* xyz, const int32_t* tet10,
+                  const int32_t* tri6, const int32_t* face_tet, const uint8_t* face_role, HostLayout& L);
+
+}  // namespace sw
