@@ -346,6 +346,7 @@ size_t mesh_layout(const HostLayout& L, Carver& cv, MeshDev* md) {
   auto tni = cv.take<int32_t>(nT);
   auto tfo = cv.take<int32_t>(nT + 1);
   auto xyz = cv.take<double>(3 * L.n_nodes);
+  auto geo32 = cv.take<float>(10 * L.tet_stride);
   auto fconn = cv.take<int32_t>(6 * L.face_stride);
   auto fconn_loc = cv.take<uint16_t>(6 * L.face_stride);
   auto fel = cv.take<int32_t>(L.face_stride);
@@ -368,6 +369,7 @@ size_t mesh_layout(const HostLayout& L, Carver& cv, MeshDev* md) {
     md->tile_nint = tni;
     md->tile_face_off = tfo;
     md->xyz = xyz;
+    md->geo32 = geo32;
     md->fconn = fconn;
     md->fconn_loc = fconn_loc;
     md->face_elem = fel;
@@ -424,6 +426,8 @@ extern "C" int sw_mesh_create(sw_ctx* ctx, const sw_mesh_desc* d, void* ws, size
   HIPC(up(md.face_role, L.face_role, s));
   HIPC(up(md.node_u2i, L.node_u2i, s));
   HIPC(up(md.node_i2u, L.node_i2u, s));
+  launch_geom32(md, (float*)md.geo32, s);
+  HIPC(hipGetLastError());
   HIPC(hipStreamSynchronize(s));
   sw_mesh* m = new sw_mesh{ctx, md, d->n_nodes, d->n_tets, d->n_faces, L.elem_order, L.node_u2i, L.node_i2u};
   *out = m;

@@ -29,6 +29,22 @@ __device__ __forceinline__ double block_sum(double v, double* sh) {
   return t;
 }
 
+// Sum of v over an NT-thread workgroup (sh holds NT / 64 doubles), valid on
+// thread 0.
+template <int NT>
+__device__ __forceinline__ double block_sum_n(double v, double* sh) {
+  v = wave_sum(v);
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  if (lane == 0) sh[wid] = v;
+  __syncthreads();
+  double t = 0.0;
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int i = 0; i < NT / 64; ++i) t += sh[i];
+  }
+  return t;
+}
+
 // Two sums at once (sh holds 2 * TPB / 64 doubles), valid on thread 0.
 __device__ __forceinline__ void block_sum2(double& a, double& b, double* sh) {
   a = wave_sum(a);

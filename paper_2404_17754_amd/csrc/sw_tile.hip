@@ -12,19 +12,32 @@
 #include "sw_device.h"
 #include "sw_elem.h"
 #include "sw_internal.h"
+#include "sw_layout.h"
 
 namespace sw {
 
-// Per-element inputs fetched from global memory (tile-local connectivity,
-// vertex coordinates through the LDS node-id list, material id).
-struct ElemIn {
+// Per-element inputs fetched from global memory: tile-local connectivity,
+// material id, and the geometry.  FP64 recomputes the barycentric gradients
+// from the FP64 vertex coordinates (through the LDS node-id list); FP32
+// streams the precomputed FP32 gradients and volume (coalesced, no
+// dependent gather).
+template <typename T>
+struct ElemIn;
+template <>
+struct ElemIn<double> {
   int ln[10];
   double X[4][3];
   int mid;
 };
+template <>
+struct ElemIn<float> {
+  int ln[10];
+  float geo[10];
+  int mid;
+};
 
 __device__ __forceinline__ void load_elem(const MeshDev& m, const int32_t* gid, const uint8_t* __restrict__ emat,
-                                          int e, ElemIn& o) {
+                                          int e, ElemIn<double>& o) {
 #pragma unroll
   for (int k = 0; k < 10; ++k) o.ln[k] = m.conn_loc[k * m.tet_stride + e];
 #pragma unroll
@@ -36,8 +49,30 @@ __device__ __forceinline__ void load_elem(const MeshDev& m, const int32_t* gid, 
   o.mid = emat[e];
 }
 
-template <typename T>
-__global__ __launch_bounds__(TPB) void k_tile(MeshDev m, const uint8_t* __restrict__ emat,
+__device__ __forceinline__ void load_elem(const MeshDev& m, const int32_t*, const uint8_t* __restrict__ emat, int e,
+                                          ElemIn<float>& o) {
+#pragma unroll
+  for (int k = 0; k < 10; ++k) o.ln[k] = m.conn_loc[k * m.tet_stride + e];
+#pragma unroll
+  for (int k = 0; k < 10; ++k) o.geo[k] = m.geo32[k * m.tet_stride + e];
+  o.mid = emat[e];
+}
+
+__device__ __forceinline__ void elem_geometry(const ElemIn<double>& in, Geo<double>& G) { tet_geometry<double>(in.X, G); }
+
+__device__ __forceinline__ void elem_geometry(const ElemIn<float>& in, Geo<float>& G) {
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    G.g[1][d] = in.geo[d];
+    G.g[2][d] = in.geo[3 + d];
+    G.g[3][d] = in.geo[6 + d];
+    G.g[0][d] = -(in.geo[d] + in.geo[3 + d] + in.geo[6 + d]);
+  }
+  G.vol = in.geo[9];
+}
+
+template <typename T, int NT>
+__global__ __launch_bounds__(NT) void k_tile(MeshDev m, const uint8_t* __restrict__ emat,
                                               const MatDev* __restrict__ mats, TileArgs<T> A, CgCtl* ctl, int iter) {
   // LDS: FP64 accumulators (LDS FP64 atomics are much faster than FP32 ones
   // on this target), then the tile's input values in T
@@ -45,7 +80,7 @@ __global__ __launch_bounds__(TPB) void k_tile(MeshDev m, const uint8_t* __restri
   double* ys = reinterpret_cast<double*>(smem_raw);
   int32_t* gid = reinterpret_cast<int32_t*>(ys + 3 * m.max_tile_nodes);
   T* xs = reinterpret_cast<T*>(gid + m.max_tile_nodes + (m.max_tile_nodes & 1));
-  __shared__ double sh[2 * TPB / 64];
+  __shared__ double sh[NT / 64];
   // CG-iteration protocol: exit when the solve is done; on the first
   // iteration end a solve whose initial residual meets the tolerance; block
   // 0 clears the scalar slots the next update kernel accumulates into.
@@ -68,10 +103,10 @@ __global__ __launch_bounds__(TPB) void k_tile(MeshDev m, const uint8_t* __restri
   const int64_t ib3 = 3 * (int64_t)m.tile_int_base[t];
 
   // node ids of the tile into LDS
-  for (int j = threadIdx.x; j < nt; j += TPB) gid[j] = m.tile_nodes[n0 + j];
+  for (int j = threadIdx.x; j < nt; j += NT) gid[j] = m.tile_nodes[n0 + j];
   __syncthreads();
   // gather xe = a1 x1 + a2 x2 for the tile's nodes; clear the accumulator
-  for (int k = threadIdx.x; k < 3 * nt; k += TPB) {
+  for (int k = threadIdx.x; k < 3 * nt; k += NT) {
     int64_t gi;
     if (k < 3 * nint) {
       gi = ib3 + k;
@@ -91,18 +126,27 @@ __global__ __launch_bounds__(TPB) void k_tile(MeshDev m, const uint8_t* __restri
     const int e1 = m.tile_elem_off[t + 1];
     // software pipeline: the next element's connectivity, coordinates and
     // material are loaded before the current element is computed
-    ElemIn nx;
-    int e = m.tile_elem_off[t] + threadIdx.x;
-    if (e < e1) load_elem(m, gid, emat, e, nx);
+    // Work-item i takes the tile's element (i * S) mod n with S coprime to n:
+    // neighbouring lanes then work on elements S apart along the Morton
+    // order, which rarely share a node, so the LDS atomics of one
+    // instruction seldom hit the same address.
+    const int eb = m.tile_elem_off[t];
+    const int n_e = e1 - eb;
+    // (n_e <= 1024 < 7 * 11 * 13 * 17, so one of these primes is coprime)
+    const int S = (n_e % 7) ? 7 : ((n_e % 11) ? 11 : ((n_e % 13) ? 13 : 17));
+    auto elem_of = [&](int i) { return eb + (int)(((int64_t)i * S) % n_e); };
+    ElemIn<T> nx;
+    int i = threadIdx.x;
+    if (i < n_e) load_elem(m, gid, emat, elem_of(i), nx);
     // (FP64: the prefetch registers would halve the occupancy, so no pipeline)
     constexpr bool kPrefetch = sizeof(T) == 4;
-    for (; e < e1; e += TPB) {
-      if (!kPrefetch && e != m.tile_elem_off[t] + (int)threadIdx.x) load_elem(m, gid, emat, e, nx);
-      const ElemIn cur = nx;
-      if (kPrefetch && e + TPB < e1) load_elem(m, gid, emat, e + TPB, nx);
+    for (; i < n_e; i += NT) {
+      if (!kPrefetch && i != (int)threadIdx.x) load_elem(m, gid, emat, elem_of(i), nx);
+      const ElemIn<T> cur = nx;
+      if (kPrefetch && i + NT < n_e) load_elem(m, gid, emat, elem_of(i + NT), nx);
       const int* ln = cur.ln;
       Geo<T> G;
-      tet_geometry<T>(cur.X, G);
+      elem_geometry(cur, G);
       const MatDev mt = mats[cur.mid];
       T w[10][3], out[10][3];
 #pragma unroll
@@ -115,19 +159,21 @@ __global__ __launch_bounds__(TPB) void k_tile(MeshDev m, const uint8_t* __restri
       }
       if (A.sK != (T)0) stiffness_apply<T>(G, (T)mt.lam, (T)mt.mu, A.sK, w, out);
       if (A.sM != (T)0) mass_apply<T>((T)mt.rho * G.vol, A.sM, w, out);
+      T eloc = (T)0;
 #pragma unroll
       for (int k = 0; k < 10; ++k) {
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
           atomicAdd(&ys[3 * ln[k] + c], (double)out[k][c]);
-          energy += (double)w[k][c] * (double)out[k][c];
+          eloc += w[k][c] * out[k][c];
         }
       }
+      energy += (double)eloc;
     }
   }
   if (A.sC != (T)0 || A.vin != nullptr) {
     const int f1 = m.tile_face_off[t + 1];
-    for (int f = m.tile_face_off[t] + threadIdx.x; f < f1; f += TPB) {
+    for (int f = m.tile_face_off[t] + threadIdx.x; f < f1; f += NT) {
       int ln[6];
       int64_t gn[6];
 #pragma unroll
@@ -184,19 +230,19 @@ __global__ __launch_bounds__(TPB) void k_tile(MeshDev m, const uint8_t* __restri
 
   // interior nodes: one contiguous range, plain stores
   T* __restrict__ y = A.y;
-  for (int k = threadIdx.x; k < 3 * nint; k += TPB) {
+  for (int k = threadIdx.x; k < 3 * nint; k += NT) {
     if (A.accumulate)
       y[ib3 + k] += (T)ys[k];
     else
       y[ib3 + k] = (T)ys[k];
   }
   // shared nodes: address-sorted global atomics
-  for (int k = 3 * nint + threadIdx.x; k < 3 * nt; k += TPB) {
+  for (int k = 3 * nint + threadIdx.x; k < 3 * nt; k += NT) {
     const int j = k / 3;
     atomic_add(&y[3 * (int64_t)gid[j] + (k - 3 * j)], (T)ys[k]);
   }
   if (iter >= 0) {
-    const double s = block_sum(energy, sh);
+    const double s = block_sum_n<NT>(energy, sh);
     if (threadIdx.x == 0) atomic_add(&ctl->pAp[blockIdx.x % NSLOT], s);
   }
 }
@@ -206,7 +252,9 @@ static void launch_tile(const MeshDev& m, const uint8_t* emat, const MatDev* mat
                         int iter, hipStream_t s) {
   const size_t nmax = m.max_tile_nodes;
   const size_t lds = 3 * nmax * sizeof(double) + (nmax + (nmax & 1)) * sizeof(int32_t) + 3 * nmax * sizeof(T);
-  hipLaunchKernelGGL(k_tile<T>, dim3(m.n_tiles), dim3(TPB), lds, s, m, emat, mats, a, ctl, iter);
+  // 4 waves per workgroup (6 measured slower for FP32)
+  constexpr int NT = 256;
+  hipLaunchKernelGGL((k_tile<T, NT>), dim3(m.n_tiles), dim3(NT), lds, s, m, emat, mats, a, ctl, iter);
 }
 
 void launch_tile_f64(const MeshDev& m, const uint8_t* emat, const MatDev* mats, const TileArgs<double>& a,
@@ -216,6 +264,38 @@ void launch_tile_f64(const MeshDev& m, const uint8_t* emat, const MatDev* mats, 
 void launch_tile_f32(const MeshDev& m, const uint8_t* emat, const MatDev* mats, const TileArgs<float>& a,
                      CgCtl* ctl, int iter, hipStream_t s) {
   launch_tile<float>(m, emat, mats, a, ctl, iter, s);
+}
+
+// ------------------------------------------------------------ geometry
+
+// FP32 barycentric gradients (rows of the inverse Jacobian, L1..L3) and the
+// volume of every element, from the FP64 coordinates: geo32[k][e], k < 10.
+__global__ __launch_bounds__(TPB) void k_geom32(MeshDev m, float* __restrict__ geo32) {
+  __shared__ int32_t gid[TILE_MAX_NODES];
+  const int t = blockIdx.x;
+  const int n0 = m.tile_node_off[t];
+  const int nt = m.tile_node_off[t + 1] - n0;
+  for (int j = threadIdx.x; j < nt; j += TPB) gid[j] = m.tile_nodes[n0 + j];
+  __syncthreads();
+  for (int e = m.tile_elem_off[t] + threadIdx.x; e < m.tile_elem_off[t + 1]; e += TPB) {
+    double X[4][3];
+    for (int k = 0; k < 4; ++k) {
+      const int64_t g = gid[m.conn_loc[k * m.tet_stride + e]];
+      for (int d = 0; d < 3; ++d) X[k][d] = m.xyz[3 * g + d];
+    }
+    Geo<double> G;
+    tet_geometry<double>(X, G);
+    for (int d = 0; d < 3; ++d) {
+      geo32[(0 + d) * m.tet_stride + e] = (float)G.g[1][d];
+      geo32[(3 + d) * m.tet_stride + e] = (float)G.g[2][d];
+      geo32[(6 + d) * m.tet_stride + e] = (float)G.g[3][d];
+    }
+    geo32[9 * m.tet_stride + e] = (float)G.vol;
+  }
+}
+
+void launch_geom32(const MeshDev& m, float* geo32, hipStream_t s) {
+  hipLaunchKernelGGL(k_geom32, dim3(m.n_tiles), dim3(TPB), 0, s, m, geo32);
 }
 
 // ------------------------------------------------------------ diagonal
