@@ -215,6 +215,9 @@ SW_API int sw_case_apply(sw_case* c, int32_t op, const double* x_dev, double* y_
 SW_API int sw_case_apply_f32(sw_case* c, int32_t op, const float* x_dev, float* y_dev);
 /* Right-hand side b of the next step (from the current state) into y_dev. */
 SW_API int sw_case_rhs(sw_case* c, double* y_dev);
+/* Initial guess that the next step would start from (from the current
+ * increment history and the case's guess kind) into y_dev. */
+SW_API int sw_case_guess(sw_case* c, double* y_dev);
 /* Diagonal 3x3 blocks of A, 6 doubles per node (xx yy zz yz xz xy), into y_dev. */
 SW_API int sw_case_diag_blocks(sw_case* c, double* y_dev);
 
@@ -230,6 +233,58 @@ SW_API int sw_misfit(sw_ctx* ctx, int32_t n_rec, int64_t n_steps, const double* 
 /* ERR of the case's recorded waveforms (steps 1..current) against obs_dev
  * (same layout, at least as many steps), using the case's own scratch. */
 SW_API int sw_case_misfit(sw_case* c, const double* obs_dev, double* err, int32_t* n_pairs);
+
+/* ------------------------------------------------------ learned guess */
+
+/* Per-DOF network predicting each step's initial guess (the paper has no
+ * network; this is the learned part added to its CG solve).  For DOF (node
+ * n, component c) before the step that computes du^m:
+ *   d_k   = du^{m-1-k}(n, c), k = 0..3            (last four increments)
+ *   nb_k  = element-neighbour mean of du^{m-1-k}  (mean over the elements
+ *           containing n of the element's mean of component c)
+ *   s     = max_k(|d_k|, |nb_k|)
+ *   x     = (d_0..d_3, nb_0..nb_3) / s, Vs/500, rho/2000  (node means)
+ *   y     = w3 . ReLU(W2 ReLU(W1 x + b1) + b2) + b3
+ *   guess = 3 d_0 - 3 d_1 + d_2 + s y                 (0 when s = 0)
+ * Parameters (SW_MLP_NPARAM floats, FP32, host order): W1[64][10], b1[64],
+ * W2[64][64], b2[64], w3[64], b3.  Inference runs in FP16 on the matrix
+ * cores with FP32 accumulation.  Training rows (12 floats): the ten
+ * features x, the target t = (du^m - quadratic extrapolation) / s and the
+ * weight s^2; the loss is sum w (y - t)^2 / sum w, minimised with Adam
+ * (beta 0.9 / 0.999, eps 1e-8) on FP32 weights. */
+#define SW_MLP_NPARAM 4929
+#define SW_MLP_ROW 12
+SW_API int sw_mlp_workspace_bytes(size_t* bytes);
+/* params: host, SW_MLP_NPARAM floats (copied).  Non-finite values are
+ * accepted: a guess that is not finite or whose residual exceeds that of the
+ * zero guess is replaced by quadratic extrapolation (SW_FLAG_GUESS_FALLBACK). */
+SW_API int sw_mlp_create(sw_ctx* ctx, const float* params, void* dev_ws, size_t ws_bytes, sw_mlp** out);
+SW_API int sw_mlp_destroy(sw_mlp* mlp);
+SW_API int sw_mlp_get_params(sw_mlp* mlp, float* params_host);
+/* y_dev[i] = network output for the features X_dev[i][0..9] (device, FP32),
+ * computed by the same matrix-core path as the guess.  Synchronous. */
+SW_API int sw_mlp_forward(sw_mlp* mlp, const float* X_dev, float* y_dev, int64_t n);
+/* Gradient of the loss over the n rows of S_dev (device, n x 12) into
+ * grad_host (SW_MLP_NPARAM doubles) and the loss into *loss (FP32 kernels).
+ * Synchronous. */
+SW_API int sw_mlp_gradient(sw_mlp* mlp, const float* S_dev, int64_t n, double* grad_host, double* loss);
+/* `steps` Adam steps on minibatches of `batch` rows drawn with replacement
+ * from the n rows of S_dev by a counter-based generator keyed on `seed`;
+ * loss_host (optional, `steps` floats) receives each minibatch's loss.
+ * Synchronous. */
+SW_API int sw_mlp_train(sw_mlp* mlp, const float* S_dev, int64_t n, int32_t steps, int32_t batch, float lr,
+                        uint64_t seed, float* loss_host);
+/* Use (or with NULL stop using) the network for a case created with
+ * guess SW_GUESS_MLP; the network stays owned by the caller. */
+SW_API int sw_case_attach_mlp(sw_case* c, sw_mlp* mlp);
+/* Record training rows while the case marches: after each step's solve,
+ * per_step DOFs drawn by a counter-based generator keyed on (seed, step)
+ * give one row each into the device ring buffer dev_buf (capacity rows of
+ * SW_MLP_ROW floats).  Needs a case created with a non-zero guess; rows are
+ * recorded once four past increments exist.  NULL stops recording. */
+SW_API int sw_case_set_sampler(sw_case* c, float* dev_buf, int64_t capacity, int32_t per_step, uint64_t seed);
+/* Rows recorded so far (at most the capacity). */
+SW_API int sw_case_samples(const sw_case* c, int64_t* rows);
 
 /* ----------------------------------------------------------------- batch */
 

@@ -215,11 +215,37 @@ class Case:
         L.check(self.ctx.lib.sw_case_rhs(self.h, C.c_void_p(y.data_ptr())))
         return y
 
+    def guess(self):
+        """Initial guess the next step would start from (device, user order)."""
+        torch = _torch()
+        y = torch.empty(self.n_dof, dtype=torch.float64, device=self.ctx.device)
+        L.check(self.ctx.lib.sw_case_guess(self.h, C.c_void_p(y.data_ptr())))
+        return y
+
     def diag_blocks(self):
         torch = _torch()
         y = torch.empty(self.mesh.n_nodes * 6, dtype=torch.float64, device=self.ctx.device)
         L.check(self.ctx.lib.sw_case_diag_blocks(self.h, C.c_void_p(y.data_ptr())))
         return y.view(-1, 6)
+
+    # -- learned guess
+    def attach_mlp(self, mlp):
+        L.check(self.ctx.lib.sw_case_attach_mlp(self.h, mlp.h if mlp is not None else C.c_void_p(0)))
+        self._mlp = mlp
+
+    def set_sampler(self, capacity, per_step, seed=0):
+        """Record training rows into a new device buffer; returns it."""
+        torch = _torch()
+        buf = torch.zeros((int(capacity), L.MLP_ROW), dtype=torch.float32, device=self.ctx.device)
+        L.check(self.ctx.lib.sw_case_set_sampler(self.h, C.c_void_p(buf.data_ptr()), int(capacity), int(per_step),
+                                                 int(seed)))
+        self._samp = buf
+        return buf
+
+    def samples(self):
+        n = C.c_int64()
+        L.check(self.ctx.lib.sw_case_samples(self.h, C.byref(n)))
+        return self._samp[: n.value]
 
     def misfit(self, obs):
         """ERR of the recorded waveforms against obs (device tensor)."""
@@ -232,6 +258,66 @@ class Case:
         n = C.c_int32()
         L.check(self.ctx.lib.sw_case_misfit(self.h, C.c_void_p(obs.data_ptr()), C.byref(e), C.byref(n)))
         return e.value, n.value
+
+
+class Mlp:
+    """Initial-guess network (see sw_mlp_* in include/sw.h).  params: 4929
+    floats packed W1[64][10], b1, W2[64][64], b2, w3, b3."""
+
+    def __init__(self, ctx: Context, params):
+        self.ctx = ctx
+        p = np.ascontiguousarray(params, np.float32).ravel()
+        if p.size != L.MLP_NPARAM:
+            raise ValueError(f"expected {L.MLP_NPARAM} parameters, got {p.size}")
+        nb = C.c_size_t()
+        L.check(ctx.lib.sw_mlp_workspace_bytes(C.byref(nb)))
+        self.ws = _workspace(nb.value, ctx.device)
+        h = C.c_void_p()
+        L.check(ctx.lib.sw_mlp_create(ctx.h, _ptr(p), C.c_void_p(self.ws.data_ptr()), nb.value, C.byref(h)))
+        self.h = h
+
+    def __del__(self):
+        if getattr(self, "h", None):
+            self.ctx.lib.sw_mlp_destroy(self.h)
+            self.h = None
+
+    def params(self):
+        out = np.zeros(L.MLP_NPARAM, np.float32)
+        L.check(self.ctx.lib.sw_mlp_get_params(self.h, _ptr(out)))
+        return out
+
+    def forward(self, X):
+        torch = _torch()
+        X = X.to(self.ctx.device, torch.float32).contiguous()
+        if X.dim() != 2 or X.shape[1] != 10:
+            raise ValueError("X must be (n, 10)")
+        y = torch.empty(X.shape[0], dtype=torch.float32, device=self.ctx.device)
+        L.check(self.ctx.lib.sw_mlp_forward(self.h, C.c_void_p(X.data_ptr()), C.c_void_p(y.data_ptr()),
+                                            X.shape[0]))
+        return y
+
+    @staticmethod
+    def _rows(S, device):
+        torch = _torch()
+        S = S.to(device, torch.float32).contiguous()
+        if S.dim() != 2 or S.shape[1] != L.MLP_ROW:
+            raise ValueError(f"sample rows must be (n, {L.MLP_ROW})")
+        return S
+
+    def gradient(self, S):
+        S = self._rows(S, self.ctx.device)
+        g = np.zeros(L.MLP_NPARAM)
+        loss = C.c_double()
+        L.check(self.ctx.lib.sw_mlp_gradient(self.h, C.c_void_p(S.data_ptr()), S.shape[0], _ptr(g),
+                                             C.byref(loss)))
+        return g, loss.value
+
+    def train(self, S, steps, batch=4096, lr=1e-3, seed=0):
+        S = self._rows(S, self.ctx.device)
+        losses = np.zeros(steps, np.float32)
+        L.check(self.ctx.lib.sw_mlp_train(self.h, C.c_void_p(S.data_ptr()), S.shape[0], int(steps), int(batch),
+                                          float(lr), int(seed), _ptr(losses)))
+        return losses
 
 
 def misfit(ctx: Context, U, obs):

@@ -13,6 +13,7 @@ SW_FLAG_NOCONV, SW_FLAG_NONFINITE, SW_FLAG_GUESS_FALLBACK = 1, 2, 4
 SW_FP64, SW_MIXED_FP32 = 0, 1
 SW_GUESS_ZERO, SW_GUESS_POLY, SW_GUESS_MLP = 0, 1, 2
 SW_OP_M, SW_OP_K, SW_OP_CABS, SW_OP_A = 1, 2, 4, 8
+MLP_NPARAM, MLP_ROW = 4929, 12
 PROF_KINDS = {"tile_f64": 0, "tile_f32": 1, "update_f64": 2, "update_f32": 3, "dir_f64": 4, "dir_f32": 5}
 
 ERRNAMES = {SW_EINVAL: "SW_EINVAL", SW_ENOWS: "SW_ENOWS", SW_EMESH: "SW_EMESH", SW_ENOCONV: "SW_ENOCONV",
@@ -71,10 +72,21 @@ SIGNATURES = {
     "sw_case_apply": (VP, I32, VP, VP),
     "sw_case_apply_f32": (VP, I32, VP, VP),
     "sw_case_rhs": (VP, VP),
+    "sw_case_guess": (VP, VP),
     "sw_case_diag_blocks": (VP, VP),
     "sw_misfit_workspace_bytes": (I32, C.POINTER(SZ)),
     "sw_misfit": (VP, I32, I64, VP, VP, VP, SZ, C.POINTER(F64), C.POINTER(I32)),
     "sw_case_misfit": (VP, VP, C.POINTER(F64), C.POINTER(I32)),
+    "sw_mlp_workspace_bytes": (C.POINTER(SZ),),
+    "sw_mlp_create": (VP, VP, VP, SZ, PP),
+    "sw_mlp_destroy": (VP,),
+    "sw_mlp_get_params": (VP, VP),
+    "sw_mlp_forward": (VP, VP, VP, I64),
+    "sw_mlp_gradient": (VP, VP, I64, VP, C.POINTER(F64)),
+    "sw_mlp_train": (VP, VP, I64, I32, I32, C.c_float, C.c_uint64, VP),
+    "sw_case_attach_mlp": (VP, VP),
+    "sw_case_set_sampler": (VP, VP, I64, I32, C.c_uint64),
+    "sw_case_samples": (VP, C.POINTER(I64)),
     "sw_batch_workspace_bytes": (C.POINTER(VP), I32, C.POINTER(SZ)),
     "sw_batch_create": (VP, C.POINTER(VP), I32, VP, SZ, PP),
     "sw_batch_step": (VP, I32),

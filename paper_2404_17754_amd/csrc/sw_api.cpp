@@ -165,11 +165,29 @@ struct sw_case {
   CgCtl *ctl64, *ctl32;
   int32_t* bad;
   double* mis_buf;
+  // learned guess: neighbour means of past increments, node material, network
+  float* nbh = nullptr;       // [4][n_dof] ring (allocated when the guess is not zero)
+  float* node_mat = nullptr;  // [n_nodes][2] (Vs, rho)
+  int nb_head = 3, nb_count = 0;
+  sw_mlp* mlp = nullptr;
+  // training-sample collection
+  float* samp = nullptr;
+  int64_t samp_cap = 0, samp_rows = 0;
+  int32_t samp_per_step = 0;
+  uint64_t samp_seed = 0;
   // host state
   int64_t step = 0;
   int hist_head = 3, hist_count = 0;
   int last_iters = 16;
   sw_case_stats stats{};
+};
+
+struct sw_mlp {
+  sw_ctx* ctx;
+  float *theta, *m, *v;  // FP32 master weights, Adam moments
+  double* grad;          // un-normalised gradient accumulator
+  double* loss2;         // sum w e^2, sum w
+  int64_t adam_step = 0;
 };
 
 struct sw_batch {
@@ -353,6 +371,7 @@ size_t mesh_layout(const HostLayout& L, Carver& cv, MeshDev* md) {
   auto frole = cv.take<uint8_t>(L.face_stride);
   auto u2i = cv.take<int32_t>(L.n_nodes);
   auto i2u = cv.take<int32_t>(L.n_nodes);
+  auto inv_val = cv.take<float>(L.n_nodes);
   if (md) {
     md->n_nodes = L.n_nodes;
     md->n_tets = L.n_tets;
@@ -376,6 +395,7 @@ size_t mesh_layout(const HostLayout& L, Carver& cv, MeshDev* md) {
     md->face_role = frole;
     md->node_u2i = u2i;
     md->node_i2u = i2u;
+    md->inv_valence = inv_val;
   }
   return cv.off;
 }
@@ -426,6 +446,7 @@ extern "C" int sw_mesh_create(sw_ctx* ctx, const sw_mesh_desc* d, void* ws, size
   HIPC(up(md.face_role, L.face_role, s));
   HIPC(up(md.node_u2i, L.node_u2i, s));
   HIPC(up(md.node_i2u, L.node_i2u, s));
+  HIPC(up(md.inv_valence, L.inv_valence, s));
   launch_geom32(md, (float*)md.geo32, s);
   HIPC(hipGetLastError());
   HIPC(hipStreamSynchronize(s));
@@ -463,6 +484,12 @@ static size_t case_layout(const sw_mesh* m, const sw_case_desc* d, Carver& cv, s
   auto ctl = cv.take<CgCtl>(2);
   auto bad = cv.take<int32_t>(1);
   auto mis_buf = cv.take<double>(2 * 3 * std::max(d->n_rec, 1) + 2);
+  float* nbh = nullptr;
+  float* node_mat = nullptr;
+  if (d->guess != SW_GUESS_ZERO) {
+    nbh = cv.take<float>(4 * nd);
+    node_mat = cv.take<float>(2 * nn);
+  }
   if (c) {
     c->mats = mats;
     c->emat = em;
@@ -493,6 +520,8 @@ static size_t case_layout(const sw_mesh* m, const sw_case_desc* d, Carver& cv, s
     c->ctl32 = ctl ? ctl + 1 : nullptr;
     c->bad = bad;
     c->mis_buf = mis_buf;
+    c->nbh = nbh;
+    c->node_mat = node_mat;
   }
   return cv.off;
 }
@@ -506,7 +535,6 @@ static int validate_case(const sw_mesh* m, const sw_case_desc* d) {
   if (d->precision != SW_FP64 && d->precision != SW_MIXED_FP32) return fail(SW_EINVAL, "unknown precision %d", d->precision);
   if (d->guess != SW_GUESS_ZERO && d->guess != SW_GUESS_POLY && d->guess != SW_GUESS_MLP)
     return fail(SW_EINVAL, "unknown guess kind %d", d->guess);
-  if (d->guess == SW_GUESS_MLP) return fail(SW_EINVAL, "SW_GUESS_MLP needs an attached network");
   if (d->poly_order < 0 || d->poly_order > 3) return fail(SW_EINVAL, "poly_order must be 0..3");
   if (!(d->inner_rtol >= 0.0 && d->inner_rtol < 1.0)) return fail(SW_EINVAL, "inner_rtol must be in [0, 1)");
   if (d->n_mat < 1 || d->n_mat > 255 || !d->mat) return fail(SW_EINVAL, "n_mat must be 1..255 with a table");
@@ -695,6 +723,13 @@ extern "C" int sw_case_create(sw_ctx* ctx, sw_mesh* m, const sw_case_desc* d, vo
   HIPX(hipMemcpyAsync(&bad, c->bad, 4, hipMemcpyDeviceToHost, s));
   HIPX(hipStreamSynchronize(s));
   if (bad) return cleanup(fail(SW_EINVAL, "a diagonal block of the step operator is not positive definite"));
+  if (c->nbh) {
+    launch_fill_f32(4 * nd, c->nbh, 0.0f, s);
+    launch_fill_f32(2 * nn, c->node_mat, 0.0f, s);
+    launch_node_material(m->dev, c->emat, c->mats, c->node_mat, s);
+    HIPX(hipGetLastError());
+    HIPX(hipStreamSynchronize(s));
+  }
 #undef HIPX
   *out = c;
   return SW_OK;
@@ -729,6 +764,8 @@ extern "C" int sw_case_set_state(sw_case* c, const double* u, const double* v, c
   c->step = step;
   c->hist_count = 0;
   c->hist_head = 3;
+  c->nb_count = 0;
+  c->nb_head = 3;
   return SW_OK;
 }
 
@@ -827,6 +864,35 @@ int true_residual(sw_case* c, CgCtl* hctl, bool zero_q) {
   return read_ctl(c, c->ctl64, hctl);
 }
 
+MlpFeat mlp_features(const sw_case* c) {
+  MlpFeat F;
+  F.n_dof = 3 * c->mesh->n_nodes;
+  F.hist = c->hist;
+  F.head = c->hist_head;
+  F.nbh = c->nbh;
+  F.nb_head = c->nb_head;
+  F.node_mat = c->node_mat;
+  return F;
+}
+
+enum { GUESS_NONE = 0, GUESS_EXTRAP = 1, GUESS_NET = 2 };
+
+// Writes the initial guess of kind g into c->x.
+int set_guess(sw_case* c, int g) {
+  hipStream_t s = c->ctx->stream;
+  const int64_t nd = 3 * c->mesh->n_nodes;
+  if (g == GUESS_NET) {
+    launch_mlp_guess(mlp_features(c), c->mlp->theta, c->x, c->ctl64, s);
+  } else if (g == GUESS_EXTRAP) {
+    const int order = std::min(c->poly_order, c->hist_count - 1);
+    launch_guess_poly(nd, c->hist, c->hist_head, order, c->x, c->ctl64, s);
+  } else {
+    launch_fill_f64(nd, c->x, 0.0, s);
+  }
+  LAUNCHED();
+  return SW_OK;
+}
+
 int solve_step(sw_case* c, int* iters, int* outer, double* relres, int* flags) {
   hipStream_t s = c->ctx->stream;
   const int64_t nn = c->mesh->n_nodes, nd = 3 * nn;
@@ -838,24 +904,39 @@ int solve_step(sw_case* c, int* iters, int* outer, double* relres, int* flags) {
   launch_fill_f64(1, &c->ctl64->bb, 0.0, s);
   launch_norm2(nd, c->b, &c->ctl64->bb, s);
   launch_ctl_prepare(c->ctl64, c->rtol, s);
-  const bool use_poly = (c->guess == SW_GUESS_POLY) && c->hist_count > 0;
-  if (use_poly) {
-    const int order = std::min(c->poly_order, c->hist_count - 1);
-    launch_guess_poly(nd, c->hist, c->hist_head, order, c->x, c->ctl64, s);
-  } else {
-    launch_fill_f64(nd, c->x, 0.0, s);
-  }
-  LAUNCHED();
+  // guess: the network needs four past increments and their neighbour means;
+  // extrapolation needs one; otherwise zero
+  int g = GUESS_NONE;
+  if (c->guess == SW_GUESS_MLP && c->mlp && c->hist_count >= 4 && c->nb_count >= 4)
+    g = GUESS_NET;
+  else if (c->guess != SW_GUESS_ZERO && c->hist_count > 0)
+    g = GUESS_EXTRAP;
+  rc = set_guess(c, g);
+  if (rc) return rc;
   CgCtl h;
   if (c->precision == SW_FP64) {
-    if (use_poly) {
-      rc = apply_f64(c, SW_OP_A, c->x, c->q, nullptr, -1);
+    for (int attempt = 0;; ++attempt) {
+      if (g != GUESS_NONE) {
+        rc = apply_f64(c, SW_OP_A, c->x, c->q, nullptr, -1);
+        if (rc) return rc;
+        launch_cg_init_f64(nn, c->b, c->q, c->pinv64, c->r, c->z, c->p, c->q, c->ctl64, s);
+      } else {
+        launch_cg_init_f64(nn, c->b, nullptr, c->pinv64, c->r, c->z, c->p, nullptr, c->ctl64, s);
+      }
+      LAUNCHED();
+      if (g != GUESS_NET || attempt > 0) break;
+      // reject a learned guess whose residual exceeds that of the zero guess
+      rc = read_ctl(c, c->ctl64, &h);
       if (rc) return rc;
-      launch_cg_init_f64(nn, c->b, c->q, c->pinv64, c->r, c->z, c->p, c->q, c->ctl64, s);
-    } else {
-      launch_cg_init_f64(nn, c->b, nullptr, c->pinv64, c->r, c->z, c->p, nullptr, c->ctl64, s);
+      double rr0 = 0.0;
+      for (int k = 0; k < NSLOT; ++k) rr0 += h.rr[0][k];
+      if (rr0 <= h.bb) break;
+      *flags |= SW_FLAG_GUESS_FALLBACK;
+      g = GUESS_EXTRAP;
+      launch_ctl_prepare(c->ctl64, c->rtol, s);
+      rc = set_guess(c, g);
+      if (rc) return rc;
     }
-    LAUNCHED();
     for (;;) {
       int it = 0;
       rc = cg_loop<false>(c, c->ctl64, *iters, c->last_iters - *iters - 1, &it);
@@ -886,10 +967,20 @@ int solve_step(sw_case* c, int* iters, int* outer, double* relres, int* flags) {
     }
   } else {
     int inner_est = std::max(1, c->last_iters / 2);
+    bool first = true;
     for (;;) {
       rc = true_residual(c, &h, true);
       if (rc) return rc;
       ++*outer;
+      if (first && g == GUESS_NET && !(h.rr_true <= h.bb)) {
+        // reject a learned guess whose residual exceeds that of the zero guess
+        *flags |= SW_FLAG_GUESS_FALLBACK;
+        g = GUESS_EXTRAP;
+        rc = set_guess(c, g);
+        if (rc) return rc;
+        continue;
+      }
+      first = false;
       if (!(h.rr_true == h.rr_true)) {
         *flags |= SW_FLAG_NONFINITE;
         break;
@@ -899,10 +990,14 @@ int solve_step(sw_case* c, int* iters, int* outer, double* relres, int* flags) {
         *flags |= SW_FLAG_NOCONV;
         break;
       }
+      // inner tolerance: the fixed inner_rtol, or less work when the target
+      // needs only a smaller reduction of the current residual
+      const double need = c->rtol * std::sqrt(h.bb / h.rr_true);
+      const double tol = std::min(0.5, std::max(c->inner_rtol, 0.3 * need));
       launch_to_f32_scaled(nd, c->r, c->r32, c->ctl64, s);
       launch_fill_f64(sizeof(CgCtl) / 8, (double*)c->ctl32, 0.0, s);
       launch_fill_f64(1, &c->ctl32->bb, 1.0, s);
-      launch_ctl_prepare(c->ctl32, c->inner_rtol, s);
+      launch_ctl_prepare(c->ctl32, tol, s);
       launch_fill_f32(nd, c->d32, 0.0f, s);
       launch_cg_init_f32(nn, c->r32, nullptr, c->pinv32, c->r32, c->z32, c->p32, nullptr, c->ctl32, s);
       LAUNCHED();
@@ -927,6 +1022,7 @@ extern "C" int sw_case_step(sw_case* c, int32_t n) {
   if (c->step + n > c->n_steps)
     return fail(SW_ESTATE, "stepping to %lld exceeds the case capacity of %lld steps", (long long)(c->step + n),
                 (long long)c->n_steps);
+  if (c->guess == SW_GUESS_MLP && !c->mlp) return fail(SW_ESTATE, "SW_GUESS_MLP needs sw_case_attach_mlp first");
   HIPC(hipSetDevice(c->ctx->device));
   hipStream_t s = c->ctx->stream;
   const int64_t nd = 3 * c->mesh->n_nodes;
@@ -935,12 +1031,25 @@ extern "C" int sw_case_step(sw_case* c, int32_t n) {
     double rel;
     int rc = solve_step(c, &iters, &outer, &rel, &flags);
     if (rc) return rc;
+    if (c->samp && c->hist_count >= 4 && c->nb_count >= 4) {
+      launch_mlp_collect(mlp_features(c), c->x, c->samp_per_step, c->samp_seed, c->step, c->samp_rows, c->samp_cap,
+                         c->samp, s);
+      c->samp_rows += c->samp_per_step;
+    }
     const int head = (c->hist_head + 1) & 3;
     launch_newmark(nd, c->dt, c->x, c->u, c->v, c->a, c->hist + head * nd, s);
     launch_record(c->n_rec, c->rec, c->v, c->wave + c->step * 3 * c->n_rec, s);
     LAUNCHED();
     c->hist_head = head;
     c->hist_count = std::min(c->hist_count + 1, 4);
+    if (c->nbh && (c->guess == SW_GUESS_MLP || c->samp)) {
+      const int nh = (c->nb_head + 1) & 3;
+      launch_fill_f32(nd, c->nbh + nh * nd, 0.0f, s);
+      launch_neighbour_mean(c->mesh->dev, c->hist + head * nd, c->nbh + nh * nd, s);
+      LAUNCHED();
+      c->nb_head = nh;
+      c->nb_count = std::min(c->nb_count + 1, 4);
+    }
     const int32_t it32 = iters;
     HIPC(hipMemcpyAsync(c->log_it + c->step, &it32, 4, hipMemcpyHostToDevice, s));
     HIPC(hipMemcpyAsync(c->log_rel + c->step, &rel, 8, hipMemcpyHostToDevice, s));
@@ -1040,6 +1149,30 @@ extern "C" int sw_case_rhs(sw_case* c, double* y) {
   return SW_OK;
 }
 
+extern "C" int sw_case_guess(sw_case* c, double* y) {
+  if (!c || !y) return fail(SW_EINVAL, "NULL argument");
+  if (c->step >= c->n_steps) return fail(SW_ESTATE, "no further step in the case capacity");
+  if (c->guess == SW_GUESS_MLP && !c->mlp) return fail(SW_ESTATE, "SW_GUESS_MLP needs sw_case_attach_mlp first");
+  HIPC(hipSetDevice(c->ctx->device));
+  hipStream_t s = c->ctx->stream;
+  const int64_t nd = 3 * c->mesh->n_nodes;
+  int rc = build_rhs(c, c->b);
+  if (rc) return rc;
+  launch_fill_f64(1, &c->ctl64->bb, 0.0, s);
+  launch_norm2(nd, c->b, &c->ctl64->bb, s);
+  int g = GUESS_NONE;
+  if (c->guess == SW_GUESS_MLP && c->hist_count >= 4 && c->nb_count >= 4)
+    g = GUESS_NET;
+  else if (c->guess != SW_GUESS_ZERO && c->hist_count > 0)
+    g = GUESS_EXTRAP;
+  rc = set_guess(c, g);
+  if (rc) return rc;
+  launch_permute_f64(c->mesh->n_nodes, 3, c->x, c->mesh->dev.node_u2i, y, s);
+  LAUNCHED();
+  HIPC(hipStreamSynchronize(s));
+  return SW_OK;
+}
+
 extern "C" int sw_case_diag_blocks(sw_case* c, double* y) {
   if (!c || !y) return fail(SW_EINVAL, "NULL argument");
   HIPC(hipSetDevice(c->ctx->device));
@@ -1087,6 +1220,152 @@ extern "C" int sw_case_misfit(sw_case* c, const double* obs, double* err, int32_
   if (c->n_rec <= 0 || c->step <= 0) return fail(SW_ESTATE, "no recorded waveforms");
   HIPC(hipSetDevice(c->ctx->device));
   return misfit_run(c->ctx, c->n_rec, c->step, c->wave, obs, c->mis_buf, err, n_pairs);
+}
+
+// ------------------------------------------------------------ network
+
+static size_t mlp_layout(Carver& cv, sw_mlp* o) {
+  auto th = cv.take<float>(MLP_NP);
+  auto m = cv.take<float>(MLP_NP);
+  auto v = cv.take<float>(MLP_NP);
+  auto g = cv.take<double>(MLP_NP);
+  auto l2 = cv.take<double>(4);
+  if (o) {
+    o->theta = th;
+    o->m = m;
+    o->v = v;
+    o->grad = g;
+    o->loss2 = l2;
+  }
+  return cv.off;
+}
+
+extern "C" int sw_mlp_workspace_bytes(size_t* bytes) {
+  if (!bytes) return fail(SW_EINVAL, "NULL argument");
+  Carver cv(nullptr);
+  *bytes = mlp_layout(cv, nullptr);
+  return SW_OK;
+}
+
+extern "C" int sw_mlp_create(sw_ctx* ctx, const float* params, void* ws, size_t ws_bytes, sw_mlp** out) {
+  if (!ctx || !params || !out) return fail(SW_EINVAL, "NULL argument");
+  Carver dry(nullptr);
+  const size_t need = mlp_layout(dry, nullptr);
+  if (!ws || ((uintptr_t)ws & 255)) return fail(SW_ENOWS, "network workspace NULL or not 256-byte aligned");
+  if (ws_bytes < need) return fail(SW_ENOWS, "network workspace %zu bytes < %zu needed", ws_bytes, need);
+  HIPC(hipSetDevice(ctx->device));
+  sw_mlp* o = new sw_mlp();
+  o->ctx = ctx;
+  Carver cv(ws);
+  mlp_layout(cv, o);
+  hipStream_t s = ctx->stream;
+  hipError_t e = hipMemcpyAsync(o->theta, params, 4 * (size_t)MLP_NP, hipMemcpyHostToDevice, s);
+  if (e != hipSuccess) {
+    delete o;
+    return fail(SW_EHIP, "parameter upload failed: %s", hipGetErrorString(e));
+  }
+  launch_fill_f32(MLP_NP, o->m, 0.0f, s);
+  launch_fill_f32(MLP_NP, o->v, 0.0f, s);
+  launch_fill_f64(MLP_NP, o->grad, 0.0, s);
+  launch_fill_f64(4, o->loss2, 0.0, s);
+  e = hipStreamSynchronize(s);
+  if (e != hipSuccess) {
+    delete o;
+    return fail(SW_EHIP, "network set-up failed: %s", hipGetErrorString(e));
+  }
+  *out = o;
+  return SW_OK;
+}
+
+extern "C" int sw_mlp_destroy(sw_mlp* o) {
+  delete o;
+  return SW_OK;
+}
+
+extern "C" int sw_mlp_get_params(sw_mlp* o, float* out) {
+  if (!o || !out) return fail(SW_EINVAL, "NULL argument");
+  HIPC(hipSetDevice(o->ctx->device));
+  HIPC(hipMemcpyAsync(out, o->theta, 4 * (size_t)MLP_NP, hipMemcpyDeviceToHost, o->ctx->stream));
+  HIPC(hipStreamSynchronize(o->ctx->stream));
+  return SW_OK;
+}
+
+extern "C" int sw_mlp_forward(sw_mlp* o, const float* X, float* y, int64_t n) {
+  if (!o || (n > 0 && (!X || !y)) || n < 0) return fail(SW_EINVAL, "bad arguments");
+  HIPC(hipSetDevice(o->ctx->device));
+  launch_mlp_forward(n, X, o->theta, y, o->ctx->stream);
+  LAUNCHED();
+  HIPC(hipStreamSynchronize(o->ctx->stream));
+  return SW_OK;
+}
+
+extern "C" int sw_mlp_gradient(sw_mlp* o, const float* S, int64_t n, double* grad, double* loss) {
+  if (!o || !S || n <= 0 || !grad) return fail(SW_EINVAL, "bad arguments");
+  HIPC(hipSetDevice(o->ctx->device));
+  hipStream_t s = o->ctx->stream;
+  launch_fill_f64(MLP_NP, o->grad, 0.0, s);
+  launch_fill_f64(4, o->loss2, 0.0, s);
+  launch_mlp_grad(S, n, 0, 0, 0, o->theta, o->grad, o->loss2, s);
+  LAUNCHED();
+  double l2[2];
+  HIPC(hipMemcpyAsync(grad, o->grad, 8 * (size_t)MLP_NP, hipMemcpyDeviceToHost, s));
+  HIPC(hipMemcpyAsync(l2, o->loss2, 16, hipMemcpyDeviceToHost, s));
+  launch_fill_f64(MLP_NP, o->grad, 0.0, s);
+  HIPC(hipStreamSynchronize(s));
+  if (l2[1] > 0.0)
+    for (int j = 0; j < MLP_NP; ++j) grad[j] /= l2[1];
+  if (loss) *loss = l2[1] > 0.0 ? l2[0] / l2[1] : 0.0;
+  return SW_OK;
+}
+
+extern "C" int sw_mlp_train(sw_mlp* o, const float* S, int64_t n, int32_t steps, int32_t batch, float lr,
+                            uint64_t seed, float* loss) {
+  if (!o || !S || n <= 0 || steps < 0 || batch <= 0 || !(lr > 0.0f)) return fail(SW_EINVAL, "bad arguments");
+  HIPC(hipSetDevice(o->ctx->device));
+  hipStream_t s = o->ctx->stream;
+  for (int k = 0; k < steps; ++k) {
+    launch_fill_f64(4, o->loss2, 0.0, s);
+    launch_mlp_grad(S, n, batch, seed, o->adam_step, o->theta, o->grad, o->loss2, s);
+    o->adam_step += 1;
+    launch_mlp_adam(o->theta, o->m, o->v, o->grad, o->loss2, o->adam_step, lr, s);
+    LAUNCHED();
+    if (loss) {
+      double l2[2];
+      HIPC(hipMemcpyAsync(l2, o->loss2, 16, hipMemcpyDeviceToHost, s));
+      HIPC(hipStreamSynchronize(s));
+      loss[k] = l2[1] > 0.0 ? (float)(l2[0] / l2[1]) : 0.0f;
+    }
+  }
+  HIPC(hipStreamSynchronize(s));
+  return SW_OK;
+}
+
+extern "C" int sw_case_attach_mlp(sw_case* c, sw_mlp* o) {
+  if (!c) return fail(SW_EINVAL, "NULL case");
+  if (o && o->ctx->device != c->ctx->device) return fail(SW_EINVAL, "network on another device");
+  if (o && !c->nbh) return fail(SW_ESTATE, "the case was created with the zero guess (no feature buffers)");
+  c->mlp = o;
+  return SW_OK;
+}
+
+extern "C" int sw_case_set_sampler(sw_case* c, float* buf, int64_t capacity, int32_t per_step, uint64_t seed) {
+  if (!c) return fail(SW_EINVAL, "NULL case");
+  if (buf && (capacity <= 0 || per_step <= 0 || per_step > capacity)) return fail(SW_EINVAL, "bad sampler sizes");
+  if (buf && !c->nbh) return fail(SW_ESTATE, "the case was created with the zero guess (no feature buffers)");
+  if (buf && c->nb_count < 4 && c->step > 0 && c->guess != SW_GUESS_MLP)
+    c->nb_count = 0;  // neighbour means start accumulating now
+  c->samp = buf;
+  c->samp_cap = capacity;
+  c->samp_per_step = per_step;
+  c->samp_seed = seed;
+  c->samp_rows = 0;
+  return SW_OK;
+}
+
+extern "C" int sw_case_samples(const sw_case* c, int64_t* rows) {
+  if (!c || !rows) return fail(SW_EINVAL, "NULL argument");
+  *rows = std::min(c->samp_rows, c->samp_cap);
+  return SW_OK;
 }
 
 // ------------------------------------------------------------ batch

@@ -53,6 +53,7 @@ struct MeshDev {
   const uint8_t* face_role;      // [n_faces]
   const int32_t* node_u2i;       // [n_nodes]
   const int32_t* node_i2u;       // [n_nodes]
+  const float* inv_valence;      // [n_nodes] 1 / number of elements containing the node
 };
 
 // One tiled operator pass:
@@ -124,6 +125,37 @@ void launch_misfit(int n_rec, int64_t n_steps, const double* U, const double* ob
 // dst[i*w + k] = src[map[i]*w + k], i < n, k < w (w <= 6)
 void launch_permute_f64(int64_t n, int w, const double* src, const int32_t* map, double* dst, hipStream_t s);
 void launch_permute_f32(int64_t n, int w, const float* src, const int32_t* map, float* dst, hipStream_t s);
+
+// ---- learned initial guess (sw_mlp.hip) ---------------------------------
+
+// Network 10 -> 64 -> 64 -> 1, parameters packed W1[64][10], b1, W2[64][64],
+// b2, w3, b3; training rows hold 10 features, the target and the weight.
+constexpr int MLP_IN = 10, MLP_H = 64, MLP_NP = 4929, MLP_ROW = 12;
+constexpr int MLP_OFF_W1 = 0, MLP_OFF_B1 = 640, MLP_OFF_W2 = 704, MLP_OFF_B2 = 4800, MLP_OFF_W3 = 4864,
+              MLP_OFF_B3 = 4928;
+
+// Where the features of the guess live (all in internal node order).
+struct MlpFeat {
+  int64_t n_dof;
+  const double* hist;     // [4][n_dof] increments, ring
+  int head;               // slot of the newest increment
+  const float* nbh;       // [4][n_dof] element-neighbour means, ring
+  int nb_head;
+  const float* node_mat;  // [n_nodes][2]: Vs, rho (element means)
+};
+
+void launch_mlp_forward(int64_t n, const float* X, const float* theta, float* y, hipStream_t s);
+void launch_mlp_guess(const MlpFeat& F, const float* theta, double* x, const CgCtl* ctl, hipStream_t s);
+void launch_mlp_collect(const MlpFeat& F, const double* du, int count, uint64_t seed, int64_t step, int64_t row0,
+                        int64_t capacity, float* out, hipStream_t s);
+void launch_mlp_grad(const float* S, int64_t n, int64_t nb, uint64_t seed, int64_t batch, const float* theta,
+                     double* grad, double* loss2, hipStream_t s);
+void launch_mlp_adam(float* theta, float* m, float* v, double* grad, const double* loss2, int64_t step, float lr,
+                     hipStream_t s);
+// out[node][3] = element-neighbour mean of the FP64 node field in (out cleared first)
+void launch_neighbour_mean(const MeshDev& m, const double* in, float* out, hipStream_t s);
+// out[node][2] = (Vs, rho) averaged over the node's elements (out cleared first)
+void launch_node_material(const MeshDev& m, const uint8_t* emat, const MatDev* mats, float* out, hipStream_t s);
 
 void launch_fill_f64(int64_t n, double* x, double val, hipStream_t s);
 void launch_fill_f32(int64_t n, float* x, float val, hipStream_t s);

@@ -33,6 +33,7 @@ struct HostLayout {
   std::vector<uint16_t> fconn_loc;     // [6][face_stride] tile-local node index
   std::vector<int32_t> face_elem;      // internal element owning each face
   std::vector<uint8_t> face_role;
+  std::vector<float> inv_valence;      // [n_nodes] 1 / elements containing the node (0 if none)
 };
 
 void build_layout(int64_t n_nodes, int64_t n_tets, int64_t n_faces, const double* xyz, const int32_t* tet10,

@@ -174,6 +174,14 @@ void build_layout(int64_t n_nodes, int64_t n_tets, int64_t n_faces, const double
   L.xyz.resize(3 * (size_t)n_nodes);
   for (int64_t i = 0; i < n_nodes; ++i)
     for (int d = 0; d < 3; ++d) L.xyz[3 * i + d] = xyz[3 * (int64_t)L.node_i2u[i] + d];
+  // --- element count per node (for element-to-node averages)
+  {
+    std::vector<int32_t> cnt(n_nodes, 0);
+    for (int64_t e = 0; e < n_tets; ++e)
+      for (int k = 0; k < 10; ++k) cnt[L.node_u2i[tet10[10 * e + k]]] += 1;
+    L.inv_valence.resize(n_nodes);
+    for (int64_t i = 0; i < n_nodes; ++i) L.inv_valence[i] = cnt[i] > 0 ? 1.0f / (float)cnt[i] : 0.0f;
+  }
   // --- faces grouped by the tile of their owner; local and global node ids
   std::vector<int32_t> forder(n_faces);
   std::iota(forder.begin(), forder.end(), 0);
