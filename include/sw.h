@@ -288,9 +288,26 @@ SW_API int sw_case_samples(const sw_case* c, int64_t* rows);
 
 /* ----------------------------------------------------------------- batch */
 
-/* A batch marches several cases together.  Cases that share a mesh, a
- * precision and a guess kind are fused into lane groups whose kernels read
- * the mesh once per operator application for all lanes. */
+/* A batch marches many candidate models together: the repeated analyses of
+ * the paper (Section 3: one analysis per candidate model and input
+ * direction).  Each case is a lane; every phase of a time step (right-hand
+ * side, true residual, each FP32 CG iteration, Newmark update, recording)
+ * is one kernel launch over all lanes, whatever their meshes, and the
+ * element-by-element pass hands the lanes of one mesh tile to the same XCD
+ * so that the tile's mesh data is read once per pass for all of them.
+ * Each lane keeps its own convergence control: a lane whose solve has
+ * converged returns from the launches at once, and its result is the same
+ * (to rounding) as stepping the case alone.
+ *
+ * cases: n distinct cases of one context, all SW_MIXED_FP32 (SW_EINVAL
+ * otherwise); any meshes, guesses, step counts.  The batch borrows them: a
+ * case must outlive the batch and must not be stepped alone while a batch
+ * step runs.  dev_ws: caller-owned device memory of at least the bytes
+ * sw_batch_workspace_bytes gives (lane tables and work list), borrowed until
+ * sw_batch_destroy.  sw_batch_step advances every case n_steps steps
+ * (SW_ESTATE if one would pass its capacity or lacks its network) and
+ * synchronises the context stream; statistics, logs and waveforms are read
+ * per case. */
 SW_API int sw_batch_workspace_bytes(sw_case* const* cases, int32_t n, size_t* bytes);
 SW_API int sw_batch_create(sw_ctx* ctx, sw_case* const* cases, int32_t n, void* dev_ws, size_t ws_bytes,
                     sw_batch** out);

@@ -190,9 +190,30 @@ struct sw_mlp {
   int64_t adam_step = 0;
 };
 
+// Cases marched together.  Lane l is cases[l]; every phase of a step is one
+// launch over all lanes (see the lane kernels), the host keeps each lane's
+// refinement decisions.
 struct sw_batch {
   sw_ctx* ctx;
   std::vector<sw_case*> cases;
+  int n = 0;
+  int64_t max_nodes = 0;
+  int max_tile_nodes = 0;
+  int n_work = 0;
+  // device tables (in the caller's workspace)
+  LaneDev* d_lanes = nullptr;
+  LaneState* d_st = nullptr;
+  LaneInfo* d_info = nullptr;
+  TileLane<double>* d_rhs1 = nullptr;
+  TileLane<double>* d_rhs2 = nullptr;
+  TileLane<double>* d_true = nullptr;
+  TileLane<float>* d_cg32 = nullptr;
+  int2* d_work = nullptr;
+  // host copies
+  std::vector<LaneDev> lanes;
+  std::vector<LaneState> st;
+  std::vector<LaneInfo> info;
+  std::vector<TileLane<double>> rhs1;
 };
 
 extern "C" int sw_ctx_create(int device, void* hip_stream, sw_ctx** out) {
@@ -1370,28 +1391,399 @@ extern "C" int sw_case_samples(const sw_case* c, int64_t* rows) {
 
 // ------------------------------------------------------------ batch
 
+namespace {
+
+// Work items of the batched operator pass: (lane, tile) pairs.  Lanes that
+// share a mesh form a group; within a group the lanes of tile t get work
+// items whose index is congruent to t modulo 8 and adjacent in dispatch
+// order, so that (with workgroups handed to the 8 XCDs round-robin) one XCD
+// runs every lane of a tile at about the same time and reads the tile's mesh
+// data once into its L2.  Each group's range is padded to a multiple of 8.
+std::vector<int2> batch_work(sw_case* const* cases, int n) {
+  std::vector<int2> work;
+  std::vector<const sw_mesh*> meshes;
+  for (int l = 0; l < n; ++l)
+    if (std::find(meshes.begin(), meshes.end(), cases[l]->mesh) == meshes.end()) meshes.push_back(cases[l]->mesh);
+  for (const sw_mesh* m : meshes) {
+    std::vector<int> lanes;
+    for (int l = 0; l < n; ++l)
+      if (cases[l]->mesh == m) lanes.push_back(l);
+    const int nt = m->dev.n_tiles, K = (int)lanes.size();
+    for (int r = 0; r < (nt + 7) / 8; ++r)
+      for (int li = 0; li < K; ++li)
+        for (int x = 0; x < 8; ++x) {
+          const int t = 8 * r + x;
+          work.push_back(t < nt ? make_int2(lanes[li], t) : make_int2(-1, -1));
+        }
+  }
+  return work;
+}
+
+size_t batch_layout(int n, int n_work, Carver& cv, sw_batch* b) {
+  b->d_lanes = cv.take<LaneDev>(n);
+  b->d_st = cv.take<LaneState>(n);
+  b->d_info = cv.take<LaneInfo>(n);
+  b->d_rhs1 = cv.take<TileLane<double>>(n);
+  b->d_rhs2 = cv.take<TileLane<double>>(n);
+  b->d_true = cv.take<TileLane<double>>(n);
+  b->d_cg32 = cv.take<TileLane<float>>(n);
+  b->d_work = cv.take<int2>(n_work);
+  return cv.off + 256;
+}
+
+int batch_check(sw_ctx* ctx, sw_case* const* cases, int32_t n) {
+  if (!cases || n <= 0) return fail(SW_EINVAL, "bad batch arguments");
+  for (int i = 0; i < n; ++i) {
+    if (!cases[i]) return fail(SW_EINVAL, "case %d is NULL", i);
+    if (ctx && cases[i]->ctx != ctx) return fail(SW_EINVAL, "case %d belongs to another context", i);
+    if (cases[i]->ctx != cases[0]->ctx) return fail(SW_EINVAL, "cases of one batch must share a context");
+    if (cases[i]->precision != SW_MIXED_FP32)
+      return fail(SW_EINVAL, "case %d: batches march SW_MIXED_FP32 cases only", i);
+    for (int j = 0; j < i; ++j)
+      if (cases[j] == cases[i]) return fail(SW_EINVAL, "case %d appears twice in the batch", i);
+  }
+  return SW_OK;
+}
+
+template <typename T>
+TileLane<T> tile_lane(const sw_case* c) {
+  TileLane<T> t{};
+  t.m = c->mesh->dev;
+  t.emat = c->emat;
+  t.mats = c->mats;
+  return t;
+}
+
+int batch_upload(sw_batch* b, void* dst, const void* src, size_t bytes) {
+  HIPC(hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, b->ctx->stream));
+  return SW_OK;
+}
+
+int batch_gather(sw_batch* b) {
+  hipStream_t s = b->ctx->stream;
+  launch_lanes(LANE_GATHER, b->n, b->max_nodes, b->d_lanes, nullptr, b->d_info, s);
+  LAUNCHED();
+  HIPC(hipMemcpyAsync(b->info.data(), b->d_info, b->n * sizeof(LaneInfo), hipMemcpyDeviceToHost, s));
+  HIPC(hipStreamSynchronize(s));
+  return b->ctx->prof.on ? prof_flush(b->ctx) : SW_OK;
+}
+
+// One time step of every lane (mixed precision: FP32 inner CG inside FP64
+// refinement), the same arithmetic as solve_step + sw_case_step per case.
+int batch_step_once(sw_batch* b) {
+  sw_ctx* cx = b->ctx;
+  hipStream_t s = cx->stream;
+  const int n = b->n;
+  std::vector<int> g(n), iters(n, 0), outer(n, 0), flags(n, 0), est(n), stopped(n, 0), first(n, 1);
+  std::vector<double> rel(n, 0.0);
+  for (int l = 0; l < n; ++l) {
+    sw_case* c = b->cases[l];
+    if (c->guess == SW_GUESS_MLP && c->mlp && c->hist_count >= 4 && c->nb_count >= 4)
+      g[l] = GUESS_NET;
+    else if (c->guess != SW_GUESS_ZERO && c->hist_count > 0)
+      g[l] = GUESS_EXTRAP;
+    else
+      g[l] = GUESS_NONE;
+    LaneDev& L = b->lanes[l];
+    L.step = c->step;
+    L.hist_head = c->hist_head;
+    L.guess_order = g[l] == GUESS_NET ? -2 : (g[l] == GUESS_EXTRAP ? std::min(c->poly_order, c->hist_count - 1) : -1);
+    b->rhs1[l].A.vin = c->vin + 3 * (c->step + 1);
+    est[l] = std::max(1, c->last_iters / 2);
+  }
+  int rc = batch_upload(b, b->d_lanes, b->lanes.data(), n * sizeof(LaneDev));
+  if (!rc) rc = batch_upload(b, b->d_rhs1, b->rhs1.data(), n * sizeof(TileLane<double>));
+  if (rc) return rc;
+  // right-hand side, its norm, tolerance, initial guess
+  launch_lanes(LANE_BEGIN_STEP, n, b->max_nodes, b->d_lanes, nullptr, nullptr, s);
+  launch_tile_lanes_f64(b->d_rhs1, b->d_work, b->n_work, b->max_tile_nodes, nullptr, -1, s);
+  launch_tile_lanes_f64(b->d_rhs2, b->d_work, b->n_work, b->max_tile_nodes, nullptr, -1, s);
+  launch_lanes(LANE_NORM2_B, n, b->max_nodes, b->d_lanes, nullptr, nullptr, s);
+  launch_lanes(LANE_PREPARE64, n, b->max_nodes, b->d_lanes, nullptr, nullptr, s);
+  launch_lanes(LANE_GUESS, n, b->max_nodes, b->d_lanes, nullptr, nullptr, s);
+  LAUNCHED();
+  for (int l = 0; l < n; ++l)
+    if (g[l] == GUESS_NET && (rc = set_guess(b->cases[l], GUESS_NET))) return rc;
+  // refinement rounds
+  for (;;) {
+    for (int l = 0; l < n; ++l) {
+      b->st[l].active = !stopped[l];
+      b->st[l].zero_q = 1;
+    }
+    if ((rc = batch_upload(b, b->d_st, b->st.data(), n * sizeof(LaneState)))) return rc;
+    launch_lanes(LANE_RRTRUE_RESET, n, b->max_nodes, b->d_lanes, b->d_st, nullptr, s);
+    launch_tile_lanes_f64(b->d_true, b->d_work, b->n_work, b->max_tile_nodes, b->d_st, -1, s);
+    launch_lanes(LANE_TRUE_RES, n, b->max_nodes, b->d_lanes, b->d_st, nullptr, s);
+    LAUNCHED();
+    if ((rc = batch_gather(b))) return rc;
+    bool any_inner = false, any_open = false;
+    for (int l = 0; l < n; ++l) {
+      LaneState& S = b->st[l];
+      if (stopped[l]) {
+        S.active = 0;
+        continue;
+      }
+      sw_case* c = b->cases[l];
+      const LaneInfo& h = b->info[l];
+      ++outer[l];
+      S.active = 0;
+      if (first[l] && g[l] == GUESS_NET && !(h.rr_true <= h.bb)) {
+        // reject a learned guess whose residual exceeds that of the zero
+        // guess; the lane's true residual is taken again next round
+        flags[l] |= SW_FLAG_GUESS_FALLBACK;
+        g[l] = GUESS_EXTRAP;
+        first[l] = 0;
+        if ((rc = set_guess(c, GUESS_EXTRAP))) return rc;
+        any_open = true;
+        continue;
+      }
+      first[l] = 0;
+      bool stop = false;
+      if (!(h.rr_true == h.rr_true)) {
+        flags[l] |= SW_FLAG_NONFINITE;
+        stop = true;
+      } else if (h.rr_true <= c->rtol * c->rtol * h.bb) {
+        stop = true;
+      } else if (iters[l] >= c->max_iter) {
+        flags[l] |= SW_FLAG_NOCONV;
+        stop = true;
+      }
+      if (stop) {
+        stopped[l] = 1;
+        rel[l] = h.bb > 0.0 ? std::sqrt(h.rr_true / h.bb) : 0.0;
+        continue;
+      }
+      const double need = c->rtol * std::sqrt(h.bb / h.rr_true);
+      S.tol = std::min(0.5, std::max(c->inner_rtol, 0.3 * need));
+      S.iter_base = iters[l];
+      S.active = 1;
+      any_inner = any_open = true;
+    }
+    if (!any_open) break;
+    if (!any_inner) continue;
+    if ((rc = batch_upload(b, b->d_st, b->st.data(), n * sizeof(LaneState)))) return rc;
+    launch_lanes(LANE_TO_F32, n, b->max_nodes, b->d_lanes, b->d_st, nullptr, s);
+    launch_lanes(LANE_CG_INIT32, n, b->max_nodes, b->d_lanes, b->d_st, nullptr, s);
+    LAUNCHED();
+    // inner CG of every refining lane in lockstep; converged lanes' work
+    // items return at once
+    int chunk = 1;
+    for (int l = 0; l < n; ++l)
+      if (b->st[l].active) chunk = std::max(chunk, est[l]);
+    for (int it = 0;;) {
+      for (int k = 0; k < chunk; ++k) {
+        const int i = it + k;
+        int ev = prof_begin(cx, SW_PROF_TILE_F32);
+        launch_tile_lanes_f32(b->d_cg32, b->d_work, b->n_work, b->max_tile_nodes, b->d_st, i, s);
+        prof_end(cx, ev);
+        ev = prof_begin(cx, SW_PROF_UPDATE_F32);
+        launch_lanes_cg(true, false, n, b->max_nodes, b->d_lanes, b->d_st, i, s);
+        prof_end(cx, ev);
+        ev = prof_begin(cx, SW_PROF_DIR_F32);
+        launch_lanes_cg(true, true, n, b->max_nodes, b->d_lanes, b->d_st, i, s);
+        prof_end(cx, ev);
+      }
+      LAUNCHED();
+      it += chunk;
+      if ((rc = batch_gather(b))) return rc;
+      bool all = true;
+      for (int l = 0; l < n; ++l)
+        if (b->st[l].active && !b->info[l].done32) all = false;
+      if (all) break;
+      chunk = 2;
+    }
+    for (int l = 0; l < n; ++l) {
+      if (!b->st[l].active) continue;
+      const int itl = std::max(0, b->info[l].iters32 - b->st[l].iter_base);
+      iters[l] += itl;
+      est[l] = std::max(1, itl);
+    }
+    launch_lanes(LANE_IR_UPDATE, n, b->max_nodes, b->d_lanes, b->d_st, nullptr, s);
+    LAUNCHED();
+  }
+  // training samples, Newmark update, receivers, logs
+  for (int l = 0; l < n; ++l) {
+    sw_case* c = b->cases[l];
+    if (c->samp && c->hist_count >= 4 && c->nb_count >= 4) {
+      launch_mlp_collect(mlp_features(c), c->x, c->samp_per_step, c->samp_seed, c->step, c->samp_rows, c->samp_cap,
+                         c->samp, s);
+      c->samp_rows += c->samp_per_step;
+    }
+    b->st[l].active = 1;
+    b->st[l].iters = iters[l];
+    b->st[l].rel = rel[l];
+  }
+  if ((rc = batch_upload(b, b->d_st, b->st.data(), n * sizeof(LaneState)))) return rc;
+  launch_lanes(LANE_NEWMARK, n, b->max_nodes, b->d_lanes, b->d_st, nullptr, s);
+  launch_lanes(LANE_RECORD, n, b->max_nodes, b->d_lanes, b->d_st, nullptr, s);
+  LAUNCHED();
+  for (int l = 0; l < n; ++l) {
+    sw_case* c = b->cases[l];
+    const int64_t nd = 3 * c->mesh->n_nodes;
+    const int head = (c->hist_head + 1) & 3;
+    c->hist_head = head;
+    c->hist_count = std::min(c->hist_count + 1, 4);
+    if (c->nbh && (c->guess == SW_GUESS_MLP || c->samp)) {
+      const int nh = (c->nb_head + 1) & 3;
+      launch_fill_f32(nd, c->nbh + nh * nd, 0.0f, s);
+      launch_neighbour_mean(c->mesh->dev, c->hist + head * nd, c->nbh + nh * nd, s);
+      LAUNCHED();
+      c->nb_head = nh;
+      c->nb_count = std::min(c->nb_count + 1, 4);
+    }
+  }
+  HIPC(hipStreamSynchronize(s));
+  for (int l = 0; l < n; ++l) {
+    sw_case* c = b->cases[l];
+    c->step += 1;
+    c->last_iters = std::max(2, iters[l]);
+    c->stats.steps += 1;
+    c->stats.cg_iters += iters[l];
+    c->stats.ir_outer += outer[l];
+    c->stats.max_true_rel_res = std::max(c->stats.max_true_rel_res, rel[l]);
+    c->stats.flags |= flags[l];
+  }
+  return SW_OK;
+}
+
+}  // namespace
+
 extern "C" int sw_batch_workspace_bytes(sw_case* const* cases, int32_t n, size_t* bytes) {
-  if (!cases || n <= 0 || !bytes) return fail(SW_EINVAL, "bad batch arguments");
-  *bytes = 256;
+  if (!bytes) return fail(SW_EINVAL, "bytes is NULL");
+  int rc = batch_check(nullptr, cases, n);
+  if (rc) return rc;
+  const std::vector<int2> work = batch_work(cases, n);
+  sw_batch tmp;
+  Carver cv(nullptr);
+  *bytes = batch_layout(n, (int)work.size(), cv, &tmp);
   return SW_OK;
 }
 
 extern "C" int sw_batch_create(sw_ctx* ctx, sw_case* const* cases, int32_t n, void* ws, size_t ws_bytes,
                                sw_batch** out) {
-  if (!ctx || !cases || n <= 0 || !out) return fail(SW_EINVAL, "bad batch arguments");
-  for (int i = 0; i < n; ++i)
-    if (!cases[i] || cases[i]->ctx->device != ctx->device) return fail(SW_EINVAL, "case %d invalid or on another device", i);
-  sw_batch* b = new sw_batch{ctx, std::vector<sw_case*>(cases, cases + n)};
+  if (!ctx || !out) return fail(SW_EINVAL, "bad batch arguments");
+  int rc = batch_check(ctx, cases, n);
+  if (rc) return rc;
+  const std::vector<int2> work = batch_work(cases, n);
+  size_t need = 0;
+  {
+    sw_batch tmp;
+    Carver cv(nullptr);
+    need = batch_layout(n, (int)work.size(), cv, &tmp);
+  }
+  if (!ws || ws_bytes < need) return fail(SW_ENOWS, "batch workspace needs %zu bytes, got %zu", need, ws_bytes);
+  HIPC(hipSetDevice(ctx->device));
+  sw_batch* b = new sw_batch();
+  b->ctx = ctx;
+  b->cases.assign(cases, cases + n);
+  b->n = n;
+  b->n_work = (int)work.size();
+  Carver cv(ws);
+  batch_layout(n, b->n_work, cv, b);
+  b->lanes.resize(n);
+  b->st.assign(n, LaneState{});
+  b->info.resize(n);
+  b->rhs1.resize(n);
+  std::vector<TileLane<double>> rhs2(n), tru(n);
+  std::vector<TileLane<float>> cg32(n);
+  for (int l = 0; l < n; ++l) {
+    sw_case* c = cases[l];
+    b->max_nodes = std::max(b->max_nodes, c->mesh->n_nodes);
+    b->max_tile_nodes = std::max(b->max_tile_nodes, c->mesh->dev.max_tile_nodes);
+    LaneDev& L = b->lanes[l];
+    L = LaneDev{};
+    L.n_nodes = c->mesh->n_nodes;
+    L.dt = c->dt;
+    L.u = c->u;
+    L.v = c->v;
+    L.a = c->a;
+    L.b = c->b;
+    L.x = c->x;
+    L.r = c->r;
+    L.z = c->z;
+    L.p = c->p;
+    L.q = c->q;
+    L.hist = c->hist;
+    L.pinv64 = c->pinv64;
+    L.pinv32 = c->pinv32;
+    L.r32 = c->r32;
+    L.d32 = c->d32;
+    L.z32 = c->z32;
+    L.p32 = c->p32;
+    L.q32 = c->q32;
+    L.ctl64 = c->ctl64;
+    L.ctl32 = c->ctl32;
+    L.rec = c->rec;
+    L.wave = c->wave;
+    L.log_it = c->log_it;
+    L.log_rel = c->log_rel;
+    L.rtol = c->rtol;
+    L.n_rec = c->n_rec;
+    L.max_iter = c->max_iter;
+    // right-hand side: M (a + (4/dt + alpha) v) + C_abs v + F, then -K (u - beta v)
+    TileLane<double>& r1 = b->rhs1[l];
+    r1 = tile_lane<double>(c);
+    r1.A.sM = 1.0;
+    r1.A.sC = 1.0;
+    r1.A.x1 = c->a;
+    r1.A.a1 = 1.0;
+    r1.A.x2 = c->v;
+    r1.A.a2 = 4.0 / c->dt + c->alpha;
+    r1.A.xf = c->v;
+    r1.A.y = c->b;
+    TileLane<double>& r2 = rhs2[l];
+    r2 = tile_lane<double>(c);
+    r2.A.sK = -1.0;
+    r2.A.x1 = c->u;
+    r2.A.a1 = 1.0;
+    r2.A.x2 = c->v;
+    r2.A.a2 = -c->beta;
+    r2.A.y = c->b;
+    r2.A.accumulate = 1;
+    // q = A x (FP64) and q32 = A p32 (FP32 CG iterations)
+    TileLane<double>& t = tru[l];
+    t = tile_lane<double>(c);
+    t.A.sM = c->cM;
+    t.A.sK = c->cK;
+    t.A.sC = c->cC;
+    t.A.x1 = c->x;
+    t.A.a1 = 1.0;
+    t.A.xf = c->x;
+    t.A.y = c->q;
+    TileLane<float>& f = cg32[l];
+    f = tile_lane<float>(c);
+    f.A.sM = (float)c->cM;
+    f.A.sK = (float)c->cK;
+    f.A.sC = (float)c->cC;
+    f.A.x1 = c->p32;
+    f.A.a1 = 1.0f;
+    f.A.xf = c->p32;
+    f.A.y = c->q32;
+    f.ctl = c->ctl32;
+  }
+  rc = batch_upload(b, b->d_rhs2, rhs2.data(), n * sizeof(TileLane<double>));
+  if (!rc) rc = batch_upload(b, b->d_true, tru.data(), n * sizeof(TileLane<double>));
+  if (!rc) rc = batch_upload(b, b->d_cg32, cg32.data(), n * sizeof(TileLane<float>));
+  if (!rc) rc = batch_upload(b, b->d_work, work.data(), work.size() * sizeof(int2));
+  if (!rc && hipStreamSynchronize(ctx->stream) != hipSuccess) rc = fail(SW_EHIP, "batch upload failed");
+  if (rc) {
+    delete b;
+    return rc;
+  }
   *out = b;
   return SW_OK;
 }
 
 extern "C" int sw_batch_step(sw_batch* b, int32_t n_steps) {
   if (!b) return fail(SW_EINVAL, "NULL batch");
-  for (sw_case* c : b->cases)
-    if (c->step + n_steps > c->n_steps) return fail(SW_ESTATE, "a case would exceed its step capacity");
+  if (n_steps < 0) return fail(SW_EINVAL, "negative step count");
   for (sw_case* c : b->cases) {
-    int rc = sw_case_step(c, n_steps);
+    if (c->step + n_steps > c->n_steps) return fail(SW_ESTATE, "a case would exceed its step capacity");
+    if (c->guess == SW_GUESS_MLP && !c->mlp) return fail(SW_ESTATE, "SW_GUESS_MLP needs sw_case_attach_mlp first");
+  }
+  HIPC(hipSetDevice(b->ctx->device));
+  for (int k = 0; k < n_steps; ++k) {
+    int rc = batch_step_once(b);
     if (rc) return rc;
   }
   return SW_OK;

@@ -72,6 +72,85 @@ struct TileArgs {
   int accumulate;      // interior nodes: 0 overwrite, 1 add
 };
 
+// ---- several cases marched together (lanes) ------------------------------
+
+// One lane's operator pass: the lane's mesh, materials, pass arguments and,
+// in CG iterations, its control block.
+template <typename T>
+struct TileLane {
+  MeshDev m;
+  const uint8_t* emat;
+  const MatDev* mats;
+  TileArgs<T> A;
+  CgCtl* ctl;
+};
+
+// One lane's vectors and per-step values (internal node order of its mesh).
+struct LaneDev {
+  int64_t n_nodes;
+  double dt;
+  double *u, *v, *a, *b, *x, *r, *z, *p, *q;
+  double* hist;             // [4][3 n_nodes] increments, ring
+  const double* pinv64;
+  const float* pinv32;
+  float *r32, *d32, *z32, *p32, *q32;
+  CgCtl *ctl64, *ctl32;
+  const int32_t* rec;
+  double* wave;             // [n_steps][n_rec][3]
+  int32_t* log_it;
+  double* log_rel;
+  double rtol;
+  int64_t step;             // the step being solved goes from `step` to `step + 1`
+  int32_t n_rec;
+  int32_t hist_head;        // ring slot of the newest increment
+  int32_t guess_order;      // >= 0: extrapolation order; -1: zero; -2: written by the network
+  int32_t max_iter;
+};
+
+// Host decisions of the current phase, per lane.
+struct LaneState {
+  int32_t active;     // takes part in the current phase
+  int32_t iter_base;  // CG iterations of this step before the current solve
+  double tol;         // relative tolerance of the current inner solve
+  double rel;         // the step's final true relative residual (log)
+  int32_t iters;      // the step's CG iterations (log)
+  int32_t zero_q;     // true residual: clear q after use
+};
+
+// What the host reads back after a phase, per lane.
+struct LaneInfo {
+  double bb, rr_true, rr0;
+  int32_t done64, iters64, done32, iters32;
+};
+
+void launch_tile_lanes_f64(const TileLane<double>* lanes, const int2* work, int n_work, int max_tile_nodes,
+                           const LaneState* st, int iter, hipStream_t s);
+void launch_tile_lanes_f32(const TileLane<float>* lanes, const int2* work, int n_work, int max_tile_nodes,
+                           const LaneState* st, int iter, hipStream_t s);
+
+// Lane kernels (sw_kernels.hip): one launch covers every lane, grid
+// (blocks per lane, lanes); st == nullptr means every lane.
+enum LaneOp {
+  LANE_BEGIN_STEP,   // b = 0, ctl64->bb = 0
+  LANE_NORM2_B,      // ctl64->bb += b.b
+  LANE_PREPARE64,    // ctl_prepare(ctl64, rtol)
+  LANE_GUESS,        // x = extrapolation / zero (guess_order >= -1)
+  LANE_RRTRUE_RESET, // ctl64->rr_true = 0
+  LANE_TRUE_RES,     // r = b - q, rr_true; q = 0 when zero_q
+  LANE_TO_F32,       // r32 = r / |r|, scale; ctl32 reset with tol; d32 = 0
+  LANE_CG_INIT32,    // FP32 CG start on r32
+  LANE_CG_INIT64,    // FP64 CG start on r = b - q (q cleared)
+  LANE_IR_UPDATE,    // x += scale d32
+  LANE_ZERO_Q,       // q = 0
+  LANE_NEWMARK,      // Newmark update, increment ring
+  LANE_RECORD,       // receivers, step log
+  LANE_GATHER,       // LaneInfo of every lane
+};
+void launch_lanes(LaneOp op, int n_lanes, int64_t max_nodes, const LaneDev* lanes, const LaneState* st,
+                  LaneInfo* info, hipStream_t s);
+void launch_lanes_cg(bool f32, bool dir, int n_lanes, int64_t max_nodes, const LaneDev* lanes, const LaneState* st,
+                     int iter, hipStream_t s);
+
 // Launches (sw_kernels.hip).  iter >= 0: CG iteration `iter` of the solve in
 // ctl (early exit when done, p.Ap accumulated into ctl); iter < 0: plain.
 void launch_tile_f64(const MeshDev& m, const uint8_t* emat, const MatDev* mats, const TileArgs<double>& a,

@@ -34,9 +34,9 @@ static inline unsigned vgrid(int64_t n) {
 
 // r = b - q, z = P r, p = z, q = 0; rz[0], rr[0]
 template <typename T>
-__global__ __launch_bounds__(TPB) void k_cg_init(int64_t n, const T* __restrict__ b, const T* __restrict__ q,
-                                                 const T* __restrict__ P, T* __restrict__ r, T* __restrict__ z,
-                                                 T* __restrict__ p, T* __restrict__ qz, CgCtl* ctl) {
+__device__ __forceinline__ void cg_init_body(int64_t n, const T* __restrict__ b, const T* __restrict__ q,
+                                             const T* __restrict__ P, T* __restrict__ r, T* __restrict__ z,
+                                             T* __restrict__ p, T* __restrict__ qz, CgCtl* ctl) {
   __shared__ double sh[2 * TPB / 64];
   double rz = 0.0, rr = 0.0;
   for (int64_t i = (int64_t)blockIdx.x * TPB + threadIdx.x; i < n; i += (int64_t)gridDim.x * TPB) {
@@ -64,9 +64,9 @@ __global__ __launch_bounds__(TPB) void k_cg_init(int64_t n, const T* __restrict_
 // alpha = rz[par] / pAp; x += alpha p; r -= alpha q; z = P r; q = 0;
 // rz[par^1] += r.z, rr[par^1] += r.r
 template <typename T>
-__global__ __launch_bounds__(TPB) void k_cg_update(int64_t n, int par, const T* __restrict__ P, T* __restrict__ x,
-                                                   T* __restrict__ r, T* __restrict__ z, const T* __restrict__ p,
-                                                   T* __restrict__ q, CgCtl* ctl) {
+__device__ __forceinline__ void cg_update_body(int64_t n, int par, const T* __restrict__ P, T* __restrict__ x,
+                                               T* __restrict__ r, T* __restrict__ z, const T* __restrict__ p,
+                                               T* __restrict__ q, CgCtl* ctl) {
   __shared__ double sh[2 * TPB / 64];
   if (ctl->done) return;
   const T alpha = (T)(slot_sum<NSLOT>(ctl->rz[par]) / slot_sum<NSLOT>(ctl->pAp));
@@ -98,8 +98,8 @@ __global__ __launch_bounds__(TPB) void k_cg_update(int64_t n, int par, const T* 
 
 // convergence test, then p = z + beta p with beta = rz[par^1] / rz[par]
 template <typename T>
-__global__ __launch_bounds__(TPB) void k_cg_dir(int64_t n, int par, int iter_abs, int max_iter,
-                                                const T* __restrict__ z, T* __restrict__ p, CgCtl* ctl) {
+__device__ __forceinline__ void cg_dir_body(int64_t n, int par, int iter_abs, int max_iter, const T* __restrict__ z,
+                                            T* __restrict__ p, CgCtl* ctl) {
   if (ctl->done) return;
   const double rr = slot_sum<NSLOT>(ctl->rr[par ^ 1]);
   const bool stop = !(rr > ctl->tol2) || (iter_abs + 1 >= max_iter);  // NaN stops too
@@ -116,6 +116,22 @@ __global__ __launch_bounds__(TPB) void k_cg_dir(int64_t n, int par, int iter_abs
 #pragma unroll
     for (int c = 0; c < 3; ++c) p[3 * i + c] = z[3 * i + c] + beta * p[3 * i + c];
   }
+}
+
+template <typename T>
+__global__ __launch_bounds__(TPB) void k_cg_init(int64_t n, const T* b, const T* q, const T* P, T* r, T* z, T* p,
+                                                 T* qz, CgCtl* ctl) {
+  cg_init_body<T>(n, b, q, P, r, z, p, qz, ctl);
+}
+template <typename T>
+__global__ __launch_bounds__(TPB) void k_cg_update(int64_t n, int par, const T* P, T* x, T* r, T* z, const T* p,
+                                                   T* q, CgCtl* ctl) {
+  cg_update_body<T>(n, par, P, x, r, z, p, q, ctl);
+}
+template <typename T>
+__global__ __launch_bounds__(TPB) void k_cg_dir(int64_t n, int par, int iter_abs, int max_iter, const T* z, T* p,
+                                                CgCtl* ctl) {
+  cg_dir_body<T>(n, par, iter_abs, max_iter, z, p, ctl);
 }
 
 void launch_cg_init_f64(int64_t n, const double* b, const double* q, const double* P, double* r, double* z, double* p,
@@ -145,7 +161,7 @@ void launch_cg_dir_f32(int64_t n, int par, int iter_abs, int max_iter, const flo
 
 // ------------------------------------------------------------ scalars
 
-__global__ void k_ctl_prepare(CgCtl* ctl, double rtol) {
+__device__ __forceinline__ void ctl_prepare_body(CgCtl* ctl, double rtol) {
   const int i = threadIdx.x;
   if (i < NSLOT) {
     ctl->pAp[i] = 0.0;
@@ -159,6 +175,7 @@ __global__ void k_ctl_prepare(CgCtl* ctl, double rtol) {
     ctl->iters = 0;
   }
 }
+__global__ void k_ctl_prepare(CgCtl* ctl, double rtol) { ctl_prepare_body(ctl, rtol); }
 void launch_ctl_prepare(CgCtl* ctl, double rtol, hipStream_t s) {
   hipLaunchKernelGGL(k_ctl_prepare, dim3(1), dim3(64), 0, s, ctl, rtol);
 }
@@ -225,8 +242,8 @@ void launch_ir_update(int64_t n, double* x64, const float* d32, const CgCtl* ctl
 
 // Lagrange extrapolation of order p from the last p+1 increments:
 // x = sum_j (-1)^j C(p+1, j+1) hist[head - j]
-__global__ __launch_bounds__(TPB) void k_guess_poly(int64_t n, const double* __restrict__ hist, int head, int order,
-                                                    double* __restrict__ x, const CgCtl* ctl) {
+__device__ __forceinline__ void guess_poly_body(int64_t n, const double* __restrict__ hist, int head, int order,
+                                                double* __restrict__ x, const CgCtl* ctl) {
   const bool zero = !(ctl->bb > 0.0) || order < 0;
   double coef[4] = {0, 0, 0, 0};
   if (!zero) {
@@ -241,6 +258,10 @@ __global__ __launch_bounds__(TPB) void k_guess_poly(int64_t n, const double* __r
     x[i] = acc;
   }
 }
+__global__ __launch_bounds__(TPB) void k_guess_poly(int64_t n, const double* hist, int head, int order, double* x,
+                                                    const CgCtl* ctl) {
+  guess_poly_body(n, hist, head, order, x, ctl);
+}
 void launch_guess_poly(int64_t n, const double* hist, int head, int order, double* x, const CgCtl* ctl,
                        hipStream_t s) {
   unsigned g = nblocks(n);
@@ -250,9 +271,9 @@ void launch_guess_poly(int64_t n, const double* hist, int head, int order, doubl
 
 // ------------------------------------------------------------ Newmark
 
-__global__ __launch_bounds__(TPB) void k_newmark(int64_t n, double dt, const double* __restrict__ du,
-                                                 double* __restrict__ u, double* __restrict__ v,
-                                                 double* __restrict__ a, double* __restrict__ hist) {
+__device__ __forceinline__ void newmark_body(int64_t n, double dt, const double* __restrict__ du,
+                                             double* __restrict__ u, double* __restrict__ v, double* __restrict__ a,
+                                             double* __restrict__ hist) {
   const double c2 = 2.0 / dt, c4 = 4.0 / (dt * dt), c4v = 4.0 / dt;
   for (int64_t i = (int64_t)blockIdx.x * TPB + threadIdx.x; i < n; i += (int64_t)gridDim.x * TPB) {
     const double d = du[i], vo = v[i];
@@ -261,6 +282,10 @@ __global__ __launch_bounds__(TPB) void k_newmark(int64_t n, double dt, const dou
     a[i] = c4 * d - c4v * vo - a[i];
     if (hist) hist[i] = d;
   }
+}
+__global__ __launch_bounds__(TPB) void k_newmark(int64_t n, double dt, const double* du, double* u, double* v,
+                                                 double* a, double* hist) {
+  newmark_body(n, dt, du, u, v, a, hist);
 }
 void launch_newmark(int64_t n, double dt, const double* du, double* u, double* v, double* a, double* hist_slot,
                     hipStream_t s) {
@@ -379,6 +404,183 @@ void launch_permute_f32(int64_t n, int w, const float* src, const int32_t* map, 
   unsigned g = nblocks(n * w);
   if (g > 16384) g = 16384;
   hipLaunchKernelGGL(k_permute<float>, dim3(g), dim3(TPB), 0, s, n, w, src, map, dst);
+}
+
+// ---------------------------------------------------------------- lanes
+//
+// Several cases (lanes) in one launch: grid (blocks per lane, lanes), each
+// lane's blocks run the same body as the single-case kernel on that lane's
+// vectors; lanes marked inactive return at once.
+
+template <int OP>
+__global__ __launch_bounds__(TPB) void k_lane_op(const LaneDev* __restrict__ lanes, const LaneState* __restrict__ st,
+                                                 LaneInfo* __restrict__ info) {
+  const int l = blockIdx.y;
+  if (st != nullptr && !st[l].active) return;
+  const LaneDev& L = lanes[l];
+  const int64_t nn = L.n_nodes, nd = 3 * nn;
+  const int64_t i0 = (int64_t)blockIdx.x * TPB + threadIdx.x, stride = (int64_t)gridDim.x * TPB;
+  const bool lead = blockIdx.x == 0 && threadIdx.x == 0;
+  if constexpr (OP == LANE_BEGIN_STEP) {
+    if (lead) L.ctl64->bb = 0.0;
+    for (int64_t i = i0; i < nd; i += stride) L.b[i] = 0.0;
+  } else if constexpr (OP == LANE_NORM2_B) {
+    __shared__ double sh[TPB / 64];
+    double acc = 0.0;
+    for (int64_t i = i0; i < nd; i += stride) acc += L.b[i] * L.b[i];
+    acc = block_sum(acc, sh);
+    if (threadIdx.x == 0) atomic_add(&L.ctl64->bb, acc);
+  } else if constexpr (OP == LANE_PREPARE64) {
+    if (blockIdx.x == 0) ctl_prepare_body(L.ctl64, L.rtol);
+  } else if constexpr (OP == LANE_GUESS) {
+    if (L.guess_order >= -1) guess_poly_body(nd, L.hist, L.hist_head, L.guess_order, L.x, L.ctl64);
+  } else if constexpr (OP == LANE_RRTRUE_RESET) {
+    if (lead) L.ctl64->rr_true = 0.0;
+  } else if constexpr (OP == LANE_TRUE_RES) {
+    __shared__ double sh[TPB / 64];
+    const bool zq = st != nullptr && st[l].zero_q;
+    double acc = 0.0;
+    for (int64_t i = i0; i < nd; i += stride) {
+      const double t = L.b[i] - L.q[i];
+      L.r[i] = t;
+      if (zq) L.q[i] = 0.0;
+      acc += t * t;
+    }
+    acc = block_sum(acc, sh);
+    if (threadIdx.x == 0) atomic_add(&L.ctl64->rr_true, acc);
+  } else if constexpr (OP == LANE_TO_F32) {
+    const double nr = sqrt(L.ctl64->rr_true);
+    const double inv = nr > 0.0 ? 1.0 / nr : 0.0;
+    if (blockIdx.x == 0) {
+      CgCtl* c = L.ctl32;
+      if (threadIdx.x < NSLOT) {
+        c->pAp[threadIdx.x] = 0.0;
+        c->rz[0][threadIdx.x] = c->rz[1][threadIdx.x] = 0.0;
+        c->rr[0][threadIdx.x] = c->rr[1][threadIdx.x] = 0.0;
+      }
+      if (threadIdx.x == 0) {
+        const double tol = st != nullptr ? st[l].tol : 0.5;
+        L.ctl64->scale = nr;
+        c->bb = 1.0;
+        c->tol2 = tol * tol;
+        c->rr_true = 0.0;
+        c->scale = 0.0;
+        c->done = 0;
+        c->iters = 0;
+      }
+    }
+    for (int64_t i = i0; i < nd; i += stride) {
+      L.r32[i] = (float)(L.r[i] * inv);
+      L.d32[i] = 0.0f;
+    }
+  } else if constexpr (OP == LANE_CG_INIT32) {
+    cg_init_body<float>(nn, L.r32, nullptr, L.pinv32, L.r32, L.z32, L.p32, nullptr, L.ctl32);
+  } else if constexpr (OP == LANE_CG_INIT64) {
+    cg_init_body<double>(nn, L.b, L.q, L.pinv64, L.r, L.z, L.p, L.q, L.ctl64);
+  } else if constexpr (OP == LANE_IR_UPDATE) {
+    const double sc = L.ctl64->scale;
+    for (int64_t i = i0; i < nd; i += stride) L.x[i] += sc * (double)L.d32[i];
+  } else if constexpr (OP == LANE_ZERO_Q) {
+    for (int64_t i = i0; i < nd; i += stride) L.q[i] = 0.0;
+  } else if constexpr (OP == LANE_NEWMARK) {
+    newmark_body(nd, L.dt, L.x, L.u, L.v, L.a, L.hist + (int64_t)((L.hist_head + 1) & 3) * nd);
+  } else if constexpr (OP == LANE_RECORD) {
+    double* row = L.wave + L.step * 3 * (int64_t)L.n_rec;
+    for (int64_t i = i0; i < 3 * (int64_t)L.n_rec; i += stride) row[i] = L.v[3 * (int64_t)L.rec[i / 3] + i % 3];
+    if (lead && st != nullptr) {
+      L.log_it[L.step] = st[l].iters;
+      L.log_rel[L.step] = st[l].rel;
+    }
+  } else if constexpr (OP == LANE_GATHER) {
+    if (lead) {
+      LaneInfo o;
+      o.bb = L.ctl64->bb;
+      o.rr_true = L.ctl64->rr_true;
+      o.rr0 = slot_sum<NSLOT>(L.ctl64->rr[0]);
+      o.done64 = L.ctl64->done;
+      o.iters64 = L.ctl64->iters;
+      o.done32 = L.ctl32 ? L.ctl32->done : 0;
+      o.iters32 = L.ctl32 ? L.ctl32->iters : 0;
+      info[l] = o;
+    }
+  }
+}
+
+// CG update (DIR false) or direction (DIR true) kernel of iteration `iter`
+// of every active lane's current solve (FP32 inner or FP64).
+template <typename T, bool DIR>
+__global__ __launch_bounds__(TPB) void k_lane_cg(const LaneDev* __restrict__ lanes, const LaneState* __restrict__ st,
+                                                 int iter) {
+  const int l = blockIdx.y;
+  if (!st[l].active) return;
+  const LaneDev& L = lanes[l];
+  const int par = iter & 1;
+  if constexpr (sizeof(T) == 4) {
+    if constexpr (DIR)
+      cg_dir_body<float>(L.n_nodes, par, st[l].iter_base + iter, L.max_iter, L.z32, L.p32, L.ctl32);
+    else
+      cg_update_body<float>(L.n_nodes, par, L.pinv32, L.d32, L.r32, L.z32, L.p32, L.q32, L.ctl32);
+  } else {
+    if constexpr (DIR)
+      cg_dir_body<double>(L.n_nodes, par, st[l].iter_base + iter, L.max_iter, L.z, L.p, L.ctl64);
+    else
+      cg_update_body<double>(L.n_nodes, par, L.pinv64, L.x, L.r, L.z, L.p, L.q, L.ctl64);
+  }
+}
+
+// Blocks per lane: enough in total to fill the chip several times over,
+// never more than the largest lane needs.
+static unsigned lane_blocks(int n_lanes, int64_t max_items, unsigned total_cap) {
+  unsigned per = total_cap / (unsigned)(n_lanes > 0 ? n_lanes : 1);
+  if (per < 32) per = 32;
+  const unsigned need = nblocks(max_items);
+  if (per > need) per = need;
+  return per == 0 ? 1 : per;
+}
+
+void launch_lanes(LaneOp op, int n_lanes, int64_t max_nodes, const LaneDev* lanes, const LaneState* st,
+                  LaneInfo* info, hipStream_t s) {
+  if (n_lanes <= 0) return;
+  const unsigned bn = lane_blocks(n_lanes, max_nodes, 2048);       // node loops (dot products into slots)
+  const unsigned bd = lane_blocks(n_lanes, 3 * max_nodes, 8192);   // DOF loops
+  switch (op) {
+#define SW_LANE_CASE(OP, BX)                                                                          \
+  case OP:                                                                                            \
+    hipLaunchKernelGGL(k_lane_op<OP>, dim3(BX, n_lanes), dim3(TPB), 0, s, lanes, st, info);           \
+    break;
+    SW_LANE_CASE(LANE_BEGIN_STEP, bd)
+    SW_LANE_CASE(LANE_NORM2_B, bd)
+    SW_LANE_CASE(LANE_PREPARE64, 1)
+    SW_LANE_CASE(LANE_GUESS, bd)
+    SW_LANE_CASE(LANE_RRTRUE_RESET, 1)
+    SW_LANE_CASE(LANE_TRUE_RES, bd)
+    SW_LANE_CASE(LANE_TO_F32, bd)
+    SW_LANE_CASE(LANE_CG_INIT32, bn)
+    SW_LANE_CASE(LANE_CG_INIT64, bn)
+    SW_LANE_CASE(LANE_IR_UPDATE, bd)
+    SW_LANE_CASE(LANE_ZERO_Q, bd)
+    SW_LANE_CASE(LANE_NEWMARK, bd)
+    SW_LANE_CASE(LANE_RECORD, 8)
+    SW_LANE_CASE(LANE_GATHER, 1)
+#undef SW_LANE_CASE
+  }
+}
+
+void launch_lanes_cg(bool f32, bool dir, int n_lanes, int64_t max_nodes, const LaneDev* lanes, const LaneState* st,
+                     int iter, hipStream_t s) {
+  const unsigned bn = lane_blocks(n_lanes, max_nodes, 2048);
+  const dim3 g(bn, n_lanes);
+  if (f32) {
+    if (dir)
+      hipLaunchKernelGGL((k_lane_cg<float, true>), g, dim3(TPB), 0, s, lanes, st, iter);
+    else
+      hipLaunchKernelGGL((k_lane_cg<float, false>), g, dim3(TPB), 0, s, lanes, st, iter);
+  } else {
+    if (dir)
+      hipLaunchKernelGGL((k_lane_cg<double, true>), g, dim3(TPB), 0, s, lanes, st, iter);
+    else
+      hipLaunchKernelGGL((k_lane_cg<double, false>), g, dim3(TPB), 0, s, lanes, st, iter);
+  }
 }
 
 }  // namespace sw

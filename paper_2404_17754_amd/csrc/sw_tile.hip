@@ -71,32 +71,33 @@ __device__ __forceinline__ void elem_geometry(const ElemIn<float>& in, Geo<float
   G.vol = in.geo[9];
 }
 
+// One workgroup's share of an operator pass: tile t of mesh m.  smem_raw is
+// the dynamic LDS (sized for m.max_tile_nodes), sh NT/64 doubles.
 template <typename T, int NT>
-__global__ __launch_bounds__(NT) void k_tile(MeshDev m, const uint8_t* __restrict__ emat,
-                                              const MatDev* __restrict__ mats, TileArgs<T> A, CgCtl* ctl, int iter) {
+__device__ __forceinline__ void tile_body(const MeshDev& m, const uint8_t* __restrict__ emat,
+                                          const MatDev* __restrict__ mats, const TileArgs<T>& A, CgCtl* ctl,
+                                          int iter, int t, unsigned char* smem_raw, double* sh) {
   // LDS: FP64 accumulators (LDS FP64 atomics are much faster than FP32 ones
   // on this target), then the tile's input values in T
-  extern __shared__ __align__(16) unsigned char smem_raw[];
   double* ys = reinterpret_cast<double*>(smem_raw);
   int32_t* gid = reinterpret_cast<int32_t*>(ys + 3 * m.max_tile_nodes);
   T* xs = reinterpret_cast<T*>(gid + m.max_tile_nodes + (m.max_tile_nodes & 1));
-  __shared__ double sh[NT / 64];
   // CG-iteration protocol: exit when the solve is done; on the first
-  // iteration end a solve whose initial residual meets the tolerance; block
-  // 0 clears the scalar slots the next update kernel accumulates into.
+  // iteration end a solve whose initial residual meets the tolerance; the
+  // workgroup of tile 0 clears the scalar slots the next update kernel
+  // accumulates into.
   if (iter >= 0) {
     const int par = iter & 1;
     if (ctl->done) return;
     if (iter == 0 && slot_sum<NSLOT>(ctl->rr[0]) <= ctl->tol2) {
-      if (blockIdx.x == 0 && threadIdx.x == 0) ctl->done = 1;
+      if (t == 0 && threadIdx.x == 0) ctl->done = 1;
       return;
     }
-    if (blockIdx.x == 0 && threadIdx.x < NSLOT) {
+    if (t == 0 && threadIdx.x < NSLOT) {
       ctl->rz[par ^ 1][threadIdx.x] = 0.0;
       ctl->rr[par ^ 1][threadIdx.x] = 0.0;
     }
   }
-  const int t = blockIdx.x;
   const int n0 = m.tile_node_off[t];
   const int nt = m.tile_node_off[t + 1] - n0;
   const int nint = m.tile_nint[t];
@@ -243,15 +244,44 @@ __global__ __launch_bounds__(NT) void k_tile(MeshDev m, const uint8_t* __restric
   }
   if (iter >= 0) {
     const double s = block_sum_n<NT>(energy, sh);
-    if (threadIdx.x == 0) atomic_add(&ctl->pAp[blockIdx.x % NSLOT], s);
+    if (threadIdx.x == 0) atomic_add(&ctl->pAp[t % NSLOT], s);
   }
+}
+
+template <typename T, int NT>
+__global__ __launch_bounds__(NT) void k_tile(MeshDev m, const uint8_t* __restrict__ emat,
+                                              const MatDev* __restrict__ mats, TileArgs<T> A, CgCtl* ctl, int iter) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  __shared__ double sh[NT / 64];
+  tile_body<T, NT>(m, emat, mats, A, ctl, iter, blockIdx.x, smem_raw, sh);
+}
+
+// The same pass for several cases (lanes) in one launch: work item b is
+// (lane, tile) = work[b] (lane < 0: padding), lanes whose state is inactive
+// return at once.
+template <typename T, int NT>
+__global__ __launch_bounds__(NT) void k_tile_lanes(const TileLane<T>* __restrict__ lanes,
+                                                    const int2* __restrict__ work,
+                                                    const LaneState* __restrict__ st, int iter) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  __shared__ double sh[NT / 64];
+  const int2 w = work[blockIdx.x];
+  if (w.x < 0) return;
+  if (st != nullptr && !st[w.x].active) return;
+  const TileLane<T>& L = lanes[w.x];
+  tile_body<T, NT>(L.m, L.emat, L.mats, L.A, L.ctl, iter, w.y, smem_raw, sh);
+}
+
+template <typename T>
+static size_t tile_lds(int max_tile_nodes) {
+  const size_t nmax = max_tile_nodes;
+  return 3 * nmax * sizeof(double) + (nmax + (nmax & 1)) * sizeof(int32_t) + 3 * nmax * sizeof(T);
 }
 
 template <typename T>
 static void launch_tile(const MeshDev& m, const uint8_t* emat, const MatDev* mats, const TileArgs<T>& a, CgCtl* ctl,
                         int iter, hipStream_t s) {
-  const size_t nmax = m.max_tile_nodes;
-  const size_t lds = 3 * nmax * sizeof(double) + (nmax + (nmax & 1)) * sizeof(int32_t) + 3 * nmax * sizeof(T);
+  const size_t lds = tile_lds<T>(m.max_tile_nodes);
   // 4 waves per workgroup (6 measured slower for FP32)
   constexpr int NT = 256;
   hipLaunchKernelGGL((k_tile<T, NT>), dim3(m.n_tiles), dim3(NT), lds, s, m, emat, mats, a, ctl, iter);
@@ -264,6 +294,17 @@ void launch_tile_f64(const MeshDev& m, const uint8_t* emat, const MatDev* mats, 
 void launch_tile_f32(const MeshDev& m, const uint8_t* emat, const MatDev* mats, const TileArgs<float>& a,
                      CgCtl* ctl, int iter, hipStream_t s) {
   launch_tile<float>(m, emat, mats, a, ctl, iter, s);
+}
+
+void launch_tile_lanes_f64(const TileLane<double>* lanes, const int2* work, int n_work, int max_tile_nodes,
+                           const LaneState* st, int iter, hipStream_t s) {
+  hipLaunchKernelGGL((k_tile_lanes<double, 256>), dim3(n_work), dim3(256), tile_lds<double>(max_tile_nodes), s, lanes,
+                     work, st, iter);
+}
+void launch_tile_lanes_f32(const TileLane<float>* lanes, const int2* work, int n_work, int max_tile_nodes,
+                           const LaneState* st, int iter, hipStream_t s) {
+  hipLaunchKernelGGL((k_tile_lanes<float, 256>), dim3(n_work), dim3(256), tile_lds<float>(max_tile_nodes), s, lanes,
+                     work, st, iter);
 }
 
 // ------------------------------------------------------------ geometry
