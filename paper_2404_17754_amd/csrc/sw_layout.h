@@ -6,11 +6,15 @@
 
 namespace sw {
 
-// A tile's node values and accumulators live in LDS: FP64 needs 48 bytes per
-// node (input + accumulator, 3 components each) plus a 4-byte node id, so 1536
-// nodes take 78 KB and
-// two tiles fit in the 160 KB LDS of a gfx950 compute unit.
-constexpr int TILE_MAX_NODES = 1536;
+// A tile's node values and accumulators live in LDS: FP64 accumulators (24
+// bytes per node; LDS FP32 atomics measured 2.3x slower), the input values
+// (12 bytes in FP32, 24 in FP64) and a 4-byte node id.  At 1280 nodes an FP32
+// pass takes 51 KB, so three workgroups share a compute unit's 160 KB (the
+// FP32 kernel's registers allow three waves per SIMD), and an FP64 pass
+// 67 KB (two workgroups; its registers allow two waves per SIMD).  Measured
+// on the 9.6 M-tet mesh: FP32 pass 787 us at 1536 nodes, 655 us at 1280,
+// 670 us at 1152.
+constexpr int TILE_MAX_NODES = 1280;
 constexpr int TILE_MAX_ELEMS = 1024;
 
 struct HostLayout {

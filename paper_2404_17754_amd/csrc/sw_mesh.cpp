@@ -9,7 +9,9 @@
 //    (touched by no other tile), then the shared nodes it touches first.  A
 //    tile's interior nodes are thus one contiguous id range (plain coalesced
 //    stores); only shared nodes need atomics, and those are sorted.
-// 4. Element connectivity is stored as 16-bit indices into the tile's node
+// 4. Inside a tile, elements are interleaved (stride S along the curve) so
+//    that the elements of one wavefront rarely share nodes.
+// 5. Element connectivity is stored as 16-bit indices into the tile's node
 //    list; boundary faces are attached to the tile of their owning element.
 #include <algorithm>
 #include <cmath>
@@ -94,6 +96,21 @@ void build_layout(int64_t n_nodes, int64_t n_tets, int64_t n_faces, const double
   L.tile_elem_off.push_back((int32_t)n_tets);
   const int32_t n_tiles = tile + 1;
   L.n_tiles = n_tiles;
+  // --- element order inside each tile: position j holds the tile's
+  // (j * S mod n)-th element along the Morton curve, S coprime to n.  The
+  // kernels hand consecutive positions to consecutive lanes (coalesced
+  // loads), and those elements lie S apart along the curve, so they rarely
+  // share a node and the LDS atomics of one instruction seldom collide.
+  {
+    std::vector<int32_t> tmp;
+    for (int32_t t = 0; t < n_tiles; ++t) {
+      const int32_t e0 = L.tile_elem_off[t], n_e = L.tile_elem_off[t + 1] - e0;
+      // n_e <= TILE_MAX_ELEMS < 7 * 11 * 13 * 17, so one of these is coprime
+      const int S = (n_e % 7) ? 7 : ((n_e % 11) ? 11 : ((n_e % 13) ? 13 : 17));
+      tmp.assign(L.elem_order.begin() + e0, L.elem_order.begin() + e0 + n_e);
+      for (int32_t j = 0; j < n_e; ++j) L.elem_order[e0 + j] = tmp[(int32_t)(((int64_t)j * S) % n_e)];
+    }
+  }
   // --- how many tiles touch each node
   std::vector<int32_t> ntouch(n_nodes, 0);
   std::fill(mark.begin(), mark.end(), -1);

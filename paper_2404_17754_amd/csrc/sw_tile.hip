@@ -124,18 +124,14 @@ __device__ __forceinline__ void tile_body(const MeshDev& m, const uint8_t* __res
 
   double energy = 0.0;
   if (A.sM != (T)0 || A.sK != (T)0) {
-    const int e1 = m.tile_elem_off[t + 1];
-    // software pipeline: the next element's connectivity, coordinates and
-    // material are loaded before the current element is computed
-    // Work-item i takes the tile's element (i * S) mod n with S coprime to n:
-    // neighbouring lanes then work on elements S apart along the Morton
-    // order, which rarely share a node, so the LDS atomics of one
-    // instruction seldom hit the same address.
+    // Work-item i takes the tile's element i: the layout has interleaved
+    // the elements so that consecutive ones rarely share a node (few LDS
+    // atomic collisions) while their loads stay coalesced.  Software
+    // pipeline (FP32): the next element's connectivity, geometry and
+    // material are loaded before the current one is computed.
     const int eb = m.tile_elem_off[t];
-    const int n_e = e1 - eb;
-    // (n_e <= 1024 < 7 * 11 * 13 * 17, so one of these primes is coprime)
-    const int S = (n_e % 7) ? 7 : ((n_e % 11) ? 11 : ((n_e % 13) ? 13 : 17));
-    auto elem_of = [&](int i) { return eb + (int)(((int64_t)i * S) % n_e); };
+    const int n_e = m.tile_elem_off[t + 1] - eb;
+    auto elem_of = [&](int i) { return eb + i; };
     ElemIn<T> nx;
     int i = threadIdx.x;
     if (i < n_e) load_elem(m, gid, emat, elem_of(i), nx);
