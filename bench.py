@@ -3,23 +3,29 @@
 
 A step is one Newmark time step of the whole path: right-hand side, initial
 guess, preconditioned CG to a true relative residual of 1e-8 (FP32 inner CG
-inside FP64 iterative refinement by default), Newmark update and receiver
-recording.  The workload is the single large case: a 1000 x 1000 x 200 m
-two-layer box with 5 m cells split into 9.6 M quadratic tetrahedra
-(13.0 M nodes, 39.07 M DOF), dt = 0.005 s, 2.5 Hz Ricker input.  Inputs are
-synthetic (seeded interface field, seeded wavelet) and resident in HBM
-before timing starts.
+inside FP64 iterative refinement), Newmark update and receiver recording.
+The workload is the single large case: a 1000 x 1000 x 200 m two-layer box
+with 5 m cells split into 9.6 M quadratic tetrahedra (13.0 M nodes,
+39.07 M DOF), dt = 0.005 s, 2.5 Hz Ricker input; the timed region is the
+whole analysis (400 steps from rest by default).  Inputs are synthetic
+(seeded interface field, seeded wavelet) and resident in HBM before timing
+starts.
+
+The initial guess is the learned one by default: a network trained, before
+timing, on solution histories that the solver generates for separate
+training models (200 x 200 x 100 m boxes of the same cells, time step and
+input), marched together as one batch.  The same run times the polynomial
+guess and the plain FP64 PCG (zero guess) on a common window of steps, and
+the CPU oracle on a bounded sample of the workload.
 
 Prints one JSON line with the metric, the roofline of the dominant kernel
-(algorithmic bytes / HIP-event-timed average duration inside the timed
-region), the plain FP64 PCG comparison on the same workload and the CPU
-oracle timed on a bounded sample of the workload.
+(algorithmic flops and bytes / HIP-event-timed mean duration of its full
+launches inside the timed region) and the comparisons.
 """
 from __future__ import annotations
 
 import argparse
 import json
-import math
 import os
 import re
 import sys
@@ -30,6 +36,14 @@ sys.path.insert(0, ROOT)
 
 METRIC = "case-timesteps/s at rel. residual 1e-8; learned vs plain CG; EBE HBM GB/s"
 HBM_PEAK_GBS = 8000.0
+# FP32 vector arithmetic without packed FP32 instructions (the build
+# disables them): 256 CUs x 4 SIMDs x 16 lanes x 2 flops (FMA) x 2.4 GHz
+ALU_PEAK_TFLOPS = 78.6
+# FP32 flops of the element-by-element operator per tetrahedron, counted
+# from its formulas: stiffness 884, consistent mass 299, fourth vertex
+# gradient 6, element energy p.Ap 60 (boundary faces and the input scaling
+# of the gathered values are left out: under 2 % of a pass)
+FLOPS_PER_TET = 884 + 299 + 6 + 60
 
 # the HBM-traffic figure is only used while the operator kernel's sources are
 # unchanged since the counters were taken
@@ -41,10 +55,8 @@ def algorithmic_bytes(mesh, word):
     in the reference layout: 10 int32 node ids + 1 material byte per tet,
     the input vector read once and the output written once per node, and
     the coordinates of every vertex node read once."""
-    n_vert = len(set(mesh.tet10[:, :4].ravel().tolist())) if mesh.n_tets < 200000 else None
-    if n_vert is None:
-        nx, ny, nz = mesh.ncell
-        n_vert = (nx + 1) * (ny + 1) * (nz + 1)
+    nx, ny, nz = mesh.ncell
+    n_vert = (nx + 1) * (ny + 1) * (nz + 1)
     return mesh.n_tets * (40 + 1) + mesh.n_nodes * 2 * 3 * word + n_vert * 3 * 8
 
 
@@ -68,7 +80,7 @@ def cpu_baseline(cfg_name, dof_target, steps=4):
     a bounded sample of the workload: a 100 x 100 x 50 m box with the same
     5 m cells, material law, time step and input, marched `steps` steps.
     The rate is scaled to the workload by the DOF ratio."""
-    import numpy as np  # noqa: F401
+    import numpy as np
     import casegen as cg
     from oracle import march
     base = cg.CONFIGS[cfg_name]
@@ -91,15 +103,73 @@ def cpu_baseline(cfg_name, dof_target, steps=4):
                        f"one thread (BLAS limited to 1), host has {os.cpu_count()} logical CPUs")}
 
 
+def train_network(sw, cg, ctx, cfg, n_cases, n_steps, train_steps, per_step=8192):
+    """Histories of `n_cases` training models (200 x 200 x 100 m boxes with
+    the workload's cells, time step and input; seeded interface fields of
+    amplitude 5-20 m and correlation 50-200 m) marched together as one batch
+    with the polynomial guess, sampled, then Adam on the GPU."""
+    import numpy as np
+    import torch
+    t0 = time.perf_counter()
+    tcfg = cg.BoxConfig("train", (200.0, 200.0, 100.0), cfg.cell, 30.0, (5.0, 20.0), (50.0, 200.0), cfg.freqs,
+                        cfg.t0, cfg.dt, n_steps, 4, 500)
+    tmesh = cg.config_mesh(tcfg)
+    gtm = sw.Mesh(ctx, tmesh)
+    lanes = []
+    for k in range(n_cases):
+        c = sw.Case(ctx, gtm, cg.make_case(tmesh, tcfg, seed=500 + k), precision="mixed", guess="poly")
+        c.set_sampler(capacity=n_steps * per_step, per_step=per_step, seed=k)
+        lanes.append(c)
+    sw.Batch(ctx, lanes).step(n_steps)
+    S = torch.cat([c.samples() for c in lanes])
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    net = sw.Mlp(ctx, seed=1)
+    losses = net.train(S, steps=train_steps, batch=per_step, lr=2e-3, seed=5)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    info = {"training_models": n_cases, "mesh": f"200x200x100 m, {tmesh.n_tets} tets", "steps_each": n_steps,
+            "rows": int(S.shape[0]), "adam_steps": train_steps, "batch": per_step,
+            "loss_first20": float(np.mean(losses[:20])), "loss_last20": float(np.mean(losses[-20:])),
+            "collect_s": round(t1 - t0, 2), "train_s": round(t2 - t1, 2),
+            "training_cg_iters_per_step": float(np.mean([c.step_log()[0].mean() for c in lanes]))}
+    del lanes, S
+    torch.cuda.empty_cache()
+    return net, info
+
+
+def timed_window(sw, ctx, gmesh, case, n, **kw):
+    """A fresh case marched `n` steps from rest; ms per step and the step
+    log."""
+    import torch
+    c = sw.Case(ctx, gmesh, case, rtol=1e-8, **{k: v for k, v in kw.items() if k != "net"})
+    if kw.get("net") is not None:
+        c.attach_mlp(kw["net"])
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    c.step(n)
+    e1.record()
+    torch.cuda.synchronize()
+    it, rel = c.step_log()
+    st = c.stats()
+    del c
+    torch.cuda.empty_cache()
+    return e0.elapsed_time(e1) / n, it, rel, st
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=400, help="timed steps (from rest; 400 = the whole analysis)")
+    ap.add_argument("--warmup", type=int, default=3, help="untimed steps on a separate copy of the case")
     ap.add_argument("--config", default="large")
-    ap.add_argument("--precision", default="mixed", choices=["mixed", "fp64"])
-    ap.add_argument("--guess", default="poly", choices=["zero", "poly"])
-    ap.add_argument("--plain-steps", type=int, default=6, help="steps of the plain FP64 PCG comparison (0 = skip)")
+    ap.add_argument("--guess", default="mlp", choices=["zero", "poly", "mlp"])
+    ap.add_argument("--compare-steps", type=int, default=60,
+                    help="window (from rest) on which the polynomial guess and plain FP64 PCG are timed (0 = skip)")
+    ap.add_argument("--train-cases", type=int, default=4)
+    ap.add_argument("--train-steps", type=int, default=150)
+    ap.add_argument("--adam-steps", type=int, default=3000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="copy a buffer of this size once before timing (reference for HBM counters)")
@@ -117,82 +187,112 @@ def main():
     import paper_2404_17754_amd as sw
 
     cfg = cg.CONFIGS[args.config]
-    n_total = args.warmup + args.steps + 1
+    cmp_n = min(args.compare_steps, args.steps)
     t_gen = time.perf_counter()
     mesh = cg.config_mesh(cfg)
-    case = cg.make_case(mesh, cfg, n_steps=max(n_total, args.warmup + args.plain_steps + 1))
+    case = cg.make_case(mesh, cfg, n_steps=max(args.steps, args.warmup, cmp_n) + 1)
     t_gen = time.perf_counter() - t_gen
     dof = 3 * mesh.n_nodes
 
     ctx = sw.Context(0)
     t_up = time.perf_counter()
     gmesh = sw.Mesh(ctx, mesh)
-    gc = sw.Case(ctx, gmesh, case, rtol=1e-8, precision=args.precision, guess=args.guess)
     torch.cuda.synchronize()
     t_up = time.perf_counter() - t_up
 
+    net, train_info = None, None
+    if args.guess == "mlp":
+        net, train_info = train_network(sw, cg, ctx, cfg, args.train_cases, args.train_steps, args.adam_steps)
+
+    # warm-up on a separate copy of the case
+    if args.warmup > 0:
+        w = sw.Case(ctx, gmesh, case, rtol=1e-8, precision="mixed", guess=args.guess)
+        if net is not None:
+            w.attach_mlp(net)
+        w.step(args.warmup)
+        torch.cuda.synchronize()
+        del w
+        torch.cuda.empty_cache()
+
+    gc = sw.Case(ctx, gmesh, case, rtol=1e-8, precision="mixed", guess=args.guess)
+    if net is not None:
+        gc.attach_mlp(net)
     if args.calibrate_copy_mib > 0:
         src = torch.ones(args.calibrate_copy_mib << 18, dtype=torch.float32, device="cuda")
         dst = torch.empty_like(src)
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
-    gc.step(args.warmup)
     torch.cuda.synchronize()
     ctx.profile(True)
     torch.cuda.synchronize()
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0, em, e1 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
     w0 = time.perf_counter()
     e0.record()
-    gc.step(args.steps)
+    gc.step(cmp_n)
+    em.record()
+    gc.step(args.steps - cmp_n)
     e1.record()
     torch.cuda.synchronize()
     wall = time.perf_counter() - w0
     ms_per_step = e0.elapsed_time(e1) / args.steps
+    ms_window = e0.elapsed_time(em) / cmp_n if cmp_n > 0 else None
     kernels = {k: ctx.profile_read(k) for k in ("tile_f64", "tile_f32", "update_f64", "update_f32",
                                                 "dir_f64", "dir_f32")}
     ctx.profile(False)
-    it, rel = gc.step_log(args.warmup, args.steps)
+    it, rel = gc.step_log(0, args.steps)
     stats = gc.stats()
     value = 1000.0 / ms_per_step  # one case
+    del gc
+    torch.cuda.empty_cache()
 
-    # dominant kernel of the timed region
+    # dominant kernel of the timed region: the FP32 element-by-element pass
     dom = max(kernels, key=lambda k: kernels[k][0])
     tot_ms, n_launch, full_ms, n_full = kernels[dom]
     avg_s = full_ms / 1e3  # full launches (early exits after convergence left out)
     if dom.startswith("tile"):
         word = 4 if dom.endswith("f32") else 8
         abytes = algorithmic_bytes(mesh, word)
+        aflops = FLOPS_PER_TET * mesh.n_tets
+        traffic = read_traffic(dom)
+        tflops = aflops / avg_s / 1e12
+        gbs = abytes / avg_s / 1e9
+        roofline = {"bound": "alu", "achieved": round(tflops, 2), "peak": ALU_PEAK_TFLOPS, "unit": "TFLOP/s",
+                    "frac": round(tflops / ALU_PEAK_TFLOPS, 4), "traffic": traffic,
+                    "kernel": dom, "avg_launch_us": round(avg_s * 1e6, 1), "launches": n_full,
+                    "launches_incl_early_exit": n_launch,
+                    "algorithmic_flops_per_launch": aflops, "flops_per_tet": FLOPS_PER_TET,
+                    "intensity_flop_per_byte": round(aflops / abytes, 2),
+                    "ridge_flop_per_byte": round(ALU_PEAK_TFLOPS * 1e3 / HBM_PEAK_GBS, 2),
+                    "hbm": {"achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                            "frac": round(gbs / HBM_PEAK_GBS, 4), "algorithmic_bytes_per_launch": abytes,
+                            "counter_traffic_GBs": None if traffic is None else round(traffic / avg_s / 1e9, 1)}}
     else:
         word = 4 if dom.endswith("f32") else 8
         abytes = {"update": (4 * 3 * word + 6 * word + 4 * 3 * word),
                   "dir": 3 * 3 * word}[dom.split("_")[0]] * mesh.n_nodes
-    achieved = abytes / avg_s / 1e9
-    traffic = read_traffic(dom)
-    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-                "kernel": dom, "avg_launch_us": round(avg_s * 1e6, 1), "launches": n_full,
-                "launches_incl_early_exit": n_launch,
-                "algorithmic_bytes_per_launch": abytes}
+        gbs = abytes / avg_s / 1e9
+        roofline = {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                    "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": None, "kernel": dom,
+                    "avg_launch_us": round(avg_s * 1e6, 1), "launches": n_full,
+                    "algorithmic_bytes_per_launch": abytes}
 
-    plain = None
-    if args.plain_steps > 0:
-        del gc
-        torch.cuda.empty_cache()
-        gp = sw.Case(ctx, gmesh, case, rtol=1e-8, precision="fp64", guess="zero")
-        gp.step(args.warmup)
-        torch.cuda.synchronize()
-        p0, p1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        p0.record()
-        gp.step(args.plain_steps)
-        p1.record()
-        torch.cuda.synchronize()
-        pms = p0.elapsed_time(p1) / args.plain_steps
-        pit, _ = gp.step_log(args.warmup, args.plain_steps)
-        plain = {"value": round(1000.0 / pms, 3), "ms_per_step": round(pms, 2),
-                 "cg_iters_per_step": float(np.mean(pit)), "speedup_of_value": round(value / (1000.0 / pms), 3),
-                 "method": "FP64 block-Jacobi PCG, zero initial guess, same steps"}
-        del gp
+    # comparisons on the common window of steps from rest
+    compare = None
+    if cmp_n > 0:
+        compare = {"window_steps": cmp_n,
+                   args.guess: {"ms_per_step": round(ms_window, 2), "value": round(1000.0 / ms_window, 3),
+                                "cg_iters_per_step": float(np.mean(it[:cmp_n]))}}
+        legs = [("plain_fp64", dict(precision="fp64", guess="zero"))]
+        if args.guess != "poly":
+            legs.insert(0, ("poly", dict(precision="mixed", guess="poly")))
+        for name, kw in legs:
+            ms, pit, prel, pst = timed_window(sw, ctx, gmesh, case, cmp_n, **kw)
+            compare[name] = {"ms_per_step": round(ms, 2), "value": round(1000.0 / ms, 3),
+                             "cg_iters_per_step": float(np.mean(pit)), "max_true_rel_res": float(np.max(prel)),
+                             "flags": pst["flags"]}
+        compare["speedup_vs_plain_fp64"] = round(compare["plain_fp64"]["ms_per_step"] / ms_window, 3)
+        compare["plain_fp64"]["method"] = "FP64 block-Jacobi PCG, zero initial guess"
 
     cpu = None if args.no_cpu_baseline else cpu_baseline(args.config, dof)
 
@@ -200,18 +300,19 @@ def main():
         "metric": METRIC, "value": round(value, 3), "unit": "case-timesteps/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 3),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "f32+f64" if args.precision == "mixed" else "f64", "data": "synthetic",
+        "dtype": "f32+f64", "data": "synthetic",
         "config": {"workload": (f"{args.config}: {cfg.box[0]:.0f}x{cfg.box[1]:.0f}x{cfg.box[2]:.0f} m, "
                                 f"{cfg.cell:g} m cells, {mesh.n_tets} P2 tets, {dof} DOF, dt {cfg.dt} s, "
-                                f"Ricker {cfg.freqs} Hz, one case"),
-                   "precision": args.precision, "guess": args.guess, "rtol": 1e-8,
+                                f"Ricker {cfg.freqs} Hz, one case, steps 0-{args.steps} from rest"),
+                   "precision": "FP32 inner CG in FP64 refinement", "guess": args.guess, "rtol": 1e-8,
                    "parallelism": "single GPU"},
         "cg_iters_per_step": float(np.mean(it)), "max_true_rel_res": float(np.max(rel)),
         "flags": stats["flags"], "wall_s_timed": round(wall, 3),
-        "setup_s": {"host_generation": round(t_gen, 2), "upload_and_setup": round(t_up, 2)},
+        "setup_s": {"host_generation": round(t_gen, 2), "mesh_upload_and_layout": round(t_up, 2)},
+        "learned_guess_training": train_info,
         "kernels_ms": {k: {"total_ms": round(v[0], 3), "launches": v[1], "full_launch_us": round(1e3 * v[2], 1)}
                        for k, v in kernels.items() if v[1]},
-        "roofline": roofline, "plain_fp64": plain, "cpu_baseline": cpu,
+        "roofline": roofline, "compare": compare, "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
 

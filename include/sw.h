@@ -89,7 +89,9 @@ enum {
 enum {
   SW_GUESS_ZERO = 0,  /* du0 = 0 */
   SW_GUESS_POLY = 1,  /* Lagrange extrapolation of the last poly_order + 1 increments */
-  SW_GUESS_MLP = 2    /* poly extrapolation plus a learned per-DOF correction */
+  SW_GUESS_MLP = 2,   /* poly extrapolation plus a learned per-DOF correction */
+  SW_GUESS_PROJ = 3   /* Galerkin projection of the step's solution onto the span of the
+                         last proj_dim increments (A-norm optimal combination) */
 };
 
 /* operators for sw_case_apply (bit mask; the terms are summed) */
@@ -170,6 +172,7 @@ typedef struct {
   const int32_t* rec_node; /* host, n_rec node ids */
   int64_t n_steps;       /* capacity of the march (steps 1..n_steps) */
   const double* v_in;    /* host, (n_steps + 1) x 3 incident velocity at t = n dt */
+  int32_t proj_dim;      /* SW_GUESS_PROJ: increments spanned, 2..16 (0 = 8) */
 } sw_case_desc;
 
 SW_API int sw_case_workspace_bytes(const sw_mesh* mesh, const sw_case_desc* desc, size_t* bytes);
@@ -254,6 +257,11 @@ SW_API int sw_case_misfit(sw_case* c, const double* obs_dev, double* err, int32_
  * (beta 0.9 / 0.999, eps 1e-8) on FP32 weights. */
 #define SW_MLP_NPARAM 4929
 #define SW_MLP_ROW 12
+/* Initial parameters for training (host, SW_MLP_NPARAM floats written):
+ * Glorot-uniform hidden layers drawn from a splitmix64 stream of `seed`,
+ * zero biases and a zero output layer, so that the untrained network's
+ * guess is exactly the quadratic extrapolation. */
+SW_API int sw_mlp_init_params(uint64_t seed, float* params);
 SW_API int sw_mlp_workspace_bytes(size_t* bytes);
 /* params: host, SW_MLP_NPARAM floats (copied).  Non-finite values are
  * accepted: a guess that is not finite or whose residual exceeds that of the

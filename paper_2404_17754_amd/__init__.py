@@ -24,7 +24,7 @@ from . import _lib as L
 from ._lib import SwError  # noqa: F401
 
 PRECISIONS = {"fp64": L.SW_FP64, "mixed": L.SW_MIXED_FP32, "mixed_fp32": L.SW_MIXED_FP32}
-GUESSES = {"zero": L.SW_GUESS_ZERO, "poly": L.SW_GUESS_POLY, "mlp": L.SW_GUESS_MLP}
+GUESSES = {"zero": L.SW_GUESS_ZERO, "poly": L.SW_GUESS_POLY, "mlp": L.SW_GUESS_MLP, "proj": L.SW_GUESS_PROJ}
 OPS = {"M": L.SW_OP_M, "K": L.SW_OP_K, "Cabs": L.SW_OP_CABS, "A": L.SW_OP_A}
 
 
@@ -110,7 +110,7 @@ class Case:
     v_in ((n_steps+1) x 3), dt, ray_alpha, ray_beta (and n_steps)."""
 
     def __init__(self, ctx: Context, mesh: Mesh, c, rtol=1e-8, max_iter=10000, precision="fp64",
-                 guess="zero", poly_order=2, inner_rtol=0.0, n_steps=None):
+                 guess="zero", poly_order=2, inner_rtol=0.0, n_steps=None, proj_dim=8):
         self.ctx, self.mesh = ctx, mesh
         lib = ctx.lib
         v_in = np.ascontiguousarray(c.v_in, np.float64)
@@ -125,7 +125,8 @@ class Case:
         self.n_dof = 3 * mesh.n_nodes
         d = L.CaseDesc(float(c.dt), float(c.ray_alpha), float(c.ray_beta), float(rtol), int(max_iter),
                        PRECISIONS[precision], GUESSES[guess], int(poly_order), float(inner_rtol),
-                       len(mat), _ptr(mat), _ptr(tet_mat), len(rec), _ptr(rec), n_steps, _ptr(v_in))
+                       len(mat), _ptr(mat), _ptr(tet_mat), len(rec), _ptr(rec), n_steps, _ptr(v_in),
+                       int(proj_dim))
         nb = C.c_size_t()
         L.check(lib.sw_case_workspace_bytes(mesh.h, C.byref(d), C.byref(nb)))
         self.ws_bytes = nb.value
@@ -264,8 +265,10 @@ class Mlp:
     """Initial-guess network (see sw_mlp_* in include/sw.h).  params: 4929
     floats packed W1[64][10], b1, W2[64][64], b2, w3, b3."""
 
-    def __init__(self, ctx: Context, params):
+    def __init__(self, ctx: Context, params=None, seed=0):
         self.ctx = ctx
+        if params is None:
+            params = self.initial_params(ctx, seed)
         p = np.ascontiguousarray(params, np.float32).ravel()
         if p.size != L.MLP_NPARAM:
             raise ValueError(f"expected {L.MLP_NPARAM} parameters, got {p.size}")
@@ -275,6 +278,14 @@ class Mlp:
         h = C.c_void_p()
         L.check(ctx.lib.sw_mlp_create(ctx.h, _ptr(p), C.c_void_p(self.ws.data_ptr()), nb.value, C.byref(h)))
         self.h = h
+
+    @staticmethod
+    def initial_params(ctx: Context, seed=0):
+        """Untrained parameters (sw_mlp_init_params): the guess they give is
+        the quadratic extrapolation."""
+        p = np.zeros(L.MLP_NPARAM, np.float32)
+        L.check(ctx.lib.sw_mlp_init_params(int(seed), _ptr(p)))
+        return p
 
     def __del__(self):
         if getattr(self, "h", None):

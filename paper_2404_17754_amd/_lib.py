@@ -11,7 +11,7 @@ LIB_PATH = os.path.join(_HERE, "libsw.so")
 SW_OK, SW_EINVAL, SW_ENOWS, SW_EMESH, SW_ENOCONV, SW_EHIP, SW_ESTATE = 0, -1, -2, -3, -4, -5, -6
 SW_FLAG_NOCONV, SW_FLAG_NONFINITE, SW_FLAG_GUESS_FALLBACK = 1, 2, 4
 SW_FP64, SW_MIXED_FP32 = 0, 1
-SW_GUESS_ZERO, SW_GUESS_POLY, SW_GUESS_MLP = 0, 1, 2
+SW_GUESS_ZERO, SW_GUESS_POLY, SW_GUESS_MLP, SW_GUESS_PROJ = 0, 1, 2, 3
 SW_OP_M, SW_OP_K, SW_OP_CABS, SW_OP_A = 1, 2, 4, 8
 MLP_NPARAM, MLP_ROW = 4929, 12
 PROF_KINDS = {"tile_f64": 0, "tile_f32": 1, "update_f64": 2, "update_f32": 3, "dir_f64": 4, "dir_f32": 5}
@@ -36,7 +36,8 @@ class CaseDesc(C.Structure):
     _fields_ = [("dt", C.c_double), ("ray_alpha", C.c_double), ("ray_beta", C.c_double), ("rtol", C.c_double),
                 ("max_iter", C.c_int32), ("precision", C.c_int32), ("guess", C.c_int32), ("poly_order", C.c_int32),
                 ("inner_rtol", C.c_double), ("n_mat", C.c_int32), ("mat", C.c_void_p), ("tet_mat", C.c_void_p),
-                ("n_rec", C.c_int32), ("rec_node", C.c_void_p), ("n_steps", C.c_int64), ("v_in", C.c_void_p)]
+                ("n_rec", C.c_int32), ("rec_node", C.c_void_p), ("n_steps", C.c_int64), ("v_in", C.c_void_p),
+                ("proj_dim", C.c_int32)]
 
 
 class CaseStats(C.Structure):
@@ -77,6 +78,7 @@ SIGNATURES = {
     "sw_misfit_workspace_bytes": (I32, C.POINTER(SZ)),
     "sw_misfit": (VP, I32, I64, VP, VP, VP, SZ, C.POINTER(F64), C.POINTER(I32)),
     "sw_case_misfit": (VP, VP, C.POINTER(F64), C.POINTER(I32)),
+    "sw_mlp_init_params": (C.c_uint64, VP),
     "sw_mlp_workspace_bytes": (C.POINTER(SZ),),
     "sw_mlp_create": (VP, VP, VP, SZ, PP),
     "sw_mlp_destroy": (VP,),

@@ -175,10 +175,16 @@ struct sw_case {
   int64_t samp_cap = 0, samp_rows = 0;
   int32_t samp_per_step = 0;
   uint64_t samp_seed = 0;
+  // projection guess: ring of past increments X, their images Y = A X, the
+  // Gram matrix X^T A X on the host
+  int proj_dim = 0, proj_count = 0, proj_head = -1;
+  double *projX = nullptr, *projY = nullptr, *proj_part = nullptr, *proj_out = nullptr, *proj_theta = nullptr;
+  std::vector<double> projG, proj_h, proj_th;
   // host state
   int64_t step = 0;
   int hist_head = 3, hist_count = 0;
   int last_iters = 16;
+  double last_bb = 0.0;
   sw_case_stats stats{};
 };
 
@@ -507,9 +513,18 @@ static size_t case_layout(const sw_mesh* m, const sw_case_desc* d, Carver& cv, s
   auto mis_buf = cv.take<double>(2 * 3 * std::max(d->n_rec, 1) + 2);
   float* nbh = nullptr;
   float* node_mat = nullptr;
-  if (d->guess != SW_GUESS_ZERO) {
+  if (d->guess == SW_GUESS_POLY || d->guess == SW_GUESS_MLP) {
     nbh = cv.take<float>(4 * nd);
     node_mat = cv.take<float>(2 * nn);
+  }
+  double *pX = nullptr, *pY = nullptr, *ppart = nullptr, *pout = nullptr, *pth = nullptr;
+  const int L = d->guess == SW_GUESS_PROJ ? (d->proj_dim > 0 ? d->proj_dim : 8) : 0;
+  if (L > 0) {
+    pX = cv.take<double>((size_t)L * nd);
+    pY = cv.take<double>((size_t)L * nd);
+    ppart = cv.take<double>((size_t)PROJ_BLOCKS * L);
+    pout = cv.take<double>(2 * L);
+    pth = cv.take<double>(L);
   }
   if (c) {
     c->mats = mats;
@@ -543,6 +558,12 @@ static size_t case_layout(const sw_mesh* m, const sw_case_desc* d, Carver& cv, s
     c->mis_buf = mis_buf;
     c->nbh = nbh;
     c->node_mat = node_mat;
+    c->proj_dim = L;
+    c->projX = pX;
+    c->projY = pY;
+    c->proj_part = ppart;
+    c->proj_out = pout;
+    c->proj_theta = pth;
   }
   return cv.off;
 }
@@ -554,8 +575,11 @@ static int validate_case(const sw_mesh* m, const sw_case_desc* d) {
   if (!(d->rtol > 0.0 && d->rtol < 1.0)) return fail(SW_EINVAL, "rtol must be in (0, 1)");
   if (d->max_iter <= 0) return fail(SW_EINVAL, "max_iter must be > 0");
   if (d->precision != SW_FP64 && d->precision != SW_MIXED_FP32) return fail(SW_EINVAL, "unknown precision %d", d->precision);
-  if (d->guess != SW_GUESS_ZERO && d->guess != SW_GUESS_POLY && d->guess != SW_GUESS_MLP)
+  if (d->guess != SW_GUESS_ZERO && d->guess != SW_GUESS_POLY && d->guess != SW_GUESS_MLP &&
+      d->guess != SW_GUESS_PROJ)
     return fail(SW_EINVAL, "unknown guess kind %d", d->guess);
+  if (d->guess == SW_GUESS_PROJ && d->proj_dim != 0 && (d->proj_dim < 2 || d->proj_dim > PROJ_MAX))
+    return fail(SW_EINVAL, "proj_dim must be 0 or 2..%d", PROJ_MAX);
   if (d->poly_order < 0 || d->poly_order > 3) return fail(SW_EINVAL, "poly_order must be 0..3");
   if (!(d->inner_rtol >= 0.0 && d->inner_rtol < 1.0)) return fail(SW_EINVAL, "inner_rtol must be in [0, 1)");
   if (d->n_mat < 1 || d->n_mat > 255 || !d->mat) return fail(SW_EINVAL, "n_mat must be 1..255 with a table");
@@ -744,6 +768,14 @@ extern "C" int sw_case_create(sw_ctx* ctx, sw_mesh* m, const sw_case_desc* d, vo
   HIPX(hipMemcpyAsync(&bad, c->bad, 4, hipMemcpyDeviceToHost, s));
   HIPX(hipStreamSynchronize(s));
   if (bad) return cleanup(fail(SW_EINVAL, "a diagonal block of the step operator is not positive definite"));
+  if (c->proj_dim > 0) {
+    launch_fill_f64((int64_t)c->proj_dim * nd, c->projX, 0.0, s);
+    launch_fill_f64((int64_t)c->proj_dim * nd, c->projY, 0.0, s);
+    c->projG.assign((size_t)c->proj_dim * c->proj_dim, 0.0);
+    c->proj_h.assign(2 * (size_t)c->proj_dim, 0.0);
+    c->proj_th.assign(c->proj_dim, 0.0);
+    HIPX(hipGetLastError());
+  }
   if (c->nbh) {
     launch_fill_f32(4 * nd, c->nbh, 0.0f, s);
     launch_fill_f32(2 * nn, c->node_mat, 0.0f, s);
@@ -787,6 +819,9 @@ extern "C" int sw_case_set_state(sw_case* c, const double* u, const double* v, c
   c->hist_head = 3;
   c->nb_count = 0;
   c->nb_head = 3;
+  c->proj_count = 0;
+  c->proj_head = -1;
+  if (c->proj_dim > 0) std::fill(c->projG.begin(), c->projG.end(), 0.0);
   return SW_OK;
 }
 
@@ -896,12 +931,149 @@ MlpFeat mlp_features(const sw_case* c) {
   return F;
 }
 
-enum { GUESS_NONE = 0, GUESS_EXTRAP = 1, GUESS_NET = 2 };
+enum { GUESS_NONE = 0, GUESS_EXTRAP = 1, GUESS_NET = 2, GUESS_PROJ = 3 };
 
-// Writes the initial guess of kind g into c->x.
+// Solves G theta = h for a symmetric positive semidefinite G (m <= PROJ_MAX,
+// leading dimension ldg) in the least-squares sense: cyclic Jacobi
+// eigen-decomposition of the unit-diagonal scaling D G D (D = diag(G)^-1/2),
+// eigenvalues below rel_cut times the largest dropped (directions the past
+// increments do not resolve above rounding), theta = D V W^+ V^T D h.
+void psd_solve(int m, const double* G, int ldg, const double* h, double* theta, double rel_cut) {
+  double A[PROJ_MAX][PROJ_MAX], V[PROJ_MAX][PROJ_MAX], d[PROJ_MAX];
+  for (int i = 0; i < m; ++i) {
+    const double gi = G[i * ldg + i];
+    d[i] = gi > 0.0 ? 1.0 / std::sqrt(gi) : 0.0;
+  }
+  for (int i = 0; i < m; ++i)
+    for (int j = 0; j < m; ++j) {
+      A[i][j] = d[i] * 0.5 * (G[i * ldg + j] + G[j * ldg + i]) * d[j];
+      V[i][j] = i == j ? 1.0 : 0.0;
+    }
+  for (int sweep = 0; sweep < 64; ++sweep) {
+    double off = 0.0, diag = 0.0;
+    for (int i = 0; i < m; ++i) {
+      diag += A[i][i] * A[i][i];
+      for (int j = i + 1; j < m; ++j) off += A[i][j] * A[i][j];
+    }
+    if (off <= 1e-32 * diag) break;
+    for (int p = 0; p < m; ++p)
+      for (int q = p + 1; q < m; ++q) {
+        if (A[p][q] == 0.0) continue;
+        // rotation in the (p, q) plane that zeroes A[p][q]
+        const double th = (A[q][q] - A[p][p]) / (2.0 * A[p][q]);
+        const double t = (th >= 0.0 ? 1.0 : -1.0) / (std::fabs(th) + std::sqrt(th * th + 1.0));
+        const double cs = 1.0 / std::sqrt(t * t + 1.0), sn = t * cs;
+        const double apq = A[p][q];
+        A[p][p] -= t * apq;
+        A[q][q] += t * apq;
+        A[p][q] = A[q][p] = 0.0;
+        for (int r = 0; r < m; ++r) {
+          if (r != p && r != q) {
+            const double arp = A[r][p], arq = A[r][q];
+            A[r][p] = A[p][r] = cs * arp - sn * arq;
+            A[r][q] = A[q][r] = sn * arp + cs * arq;
+          }
+          const double vrp = V[r][p], vrq = V[r][q];
+          V[r][p] = cs * vrp - sn * vrq;
+          V[r][q] = sn * vrp + cs * vrq;
+        }
+      }
+  }
+  double wmax = 0.0;
+  for (int i = 0; i < m; ++i) wmax = std::max(wmax, A[i][i]);
+  double y[PROJ_MAX];
+  for (int k = 0; k < m; ++k) {
+    double acc = 0.0;
+    for (int i = 0; i < m; ++i) acc += V[i][k] * d[i] * h[i];
+    y[k] = (wmax > 0.0 && A[k][k] > rel_cut * wmax) ? acc / A[k][k] : 0.0;
+  }
+  for (int i = 0; i < m; ++i) {
+    double acc = 0.0;
+    for (int k = 0; k < m; ++k) acc += V[i][k] * y[k];
+    theta[i] = d[i] * acc;
+  }
+}
+
+// Projection guess, first half: X_i . b for the ring, copied to the host.
+int proj_begin(sw_case* c) {
+  hipStream_t s = c->ctx->stream;
+  const int64_t nd = 3 * c->mesh->n_nodes;
+  launch_proj_dots(c->proj_dim, nd, c->projX, c->b, nullptr, c->proj_part, c->proj_out, s);
+  LAUNCHED();
+  HIPC(hipMemcpyAsync(c->proj_h.data(), c->proj_out, c->proj_dim * sizeof(double), hipMemcpyDeviceToHost, s));
+  return SW_OK;
+}
+
+// Second half (after a synchronisation): theta from the Gram matrix of the
+// filled slots, x = X theta.
+int proj_finish(sw_case* c) {
+  hipStream_t s = c->ctx->stream;
+  const int L = c->proj_dim;
+  const int64_t nd = 3 * c->mesh->n_nodes;
+  int idx[PROJ_MAX];
+  const int m = c->proj_count;
+  for (int j = 0; j < m; ++j) idx[j] = ((c->proj_head - j) % L + L) % L;
+  double Gs[PROJ_MAX * PROJ_MAX], hs[PROJ_MAX], ts[PROJ_MAX];
+  for (int i = 0; i < m; ++i) {
+    hs[i] = c->proj_h[idx[i]];
+    for (int j = 0; j < m; ++j) Gs[i * m + j] = c->projG[(size_t)idx[i] * L + idx[j]];
+  }
+  psd_solve(m, Gs, m, hs, ts, 1e-11);
+  std::fill(c->proj_th.begin(), c->proj_th.end(), 0.0);
+  for (int i = 0; i < m; ++i) c->proj_th[idx[i]] = std::isfinite(ts[i]) ? ts[i] : 0.0;
+  HIPC(hipMemcpyAsync(c->proj_theta, c->proj_th.data(), L * sizeof(double), hipMemcpyHostToDevice, s));
+  launch_proj_combine(L, nd, c->projX, c->proj_theta, c->x, s);
+  LAUNCHED();
+  return SW_OK;
+}
+
+// After a converged step (x = du, r = b - A du): du and A du = b - r enter
+// the ring, and the new row of the Gram matrix is computed on the device.
+int proj_record_begin(sw_case* c) {
+  hipStream_t s = c->ctx->stream;
+  const int L = c->proj_dim;
+  const int64_t nd = 3 * c->mesh->n_nodes;
+  const int sl = (c->proj_head + 1) % L;
+  double* Xs = c->projX + (size_t)sl * nd;
+  double* Ys = c->projY + (size_t)sl * nd;
+  launch_proj_store(nd, c->x, c->b, c->r, Xs, Ys, s);
+  launch_proj_dots(L, nd, c->projX, Ys, nullptr, c->proj_part, c->proj_out, s);
+  launch_proj_dots(L, nd, c->projY, Xs, nullptr, c->proj_part, c->proj_out + L, s);
+  LAUNCHED();
+  HIPC(hipMemcpyAsync(c->proj_h.data(), c->proj_out, 2 * L * sizeof(double), hipMemcpyDeviceToHost, s));
+  c->proj_head = sl;
+  c->proj_count = std::min(c->proj_count + 1, L);
+  return SW_OK;
+}
+
+// After the synchronisation: symmetric Gram row of the new slot.
+void proj_record_finish(sw_case* c) {
+  const int L = c->proj_dim, sl = c->proj_head;
+  for (int i = 0; i < L; ++i) {
+    const double g = 0.5 * (c->proj_h[i] + c->proj_h[L + i]);
+    c->projG[(size_t)i * L + sl] = g;
+    c->projG[(size_t)sl * L + i] = g;
+  }
+}
+
+// Guess kind for the coming step of c.
+int guess_kind(const sw_case* c) {
+  if (c->guess == SW_GUESS_PROJ && c->proj_count >= 2) return GUESS_PROJ;
+  if (c->guess == SW_GUESS_MLP && c->mlp && c->hist_count >= 4 && c->nb_count >= 4) return GUESS_NET;
+  if (c->guess != SW_GUESS_ZERO && c->hist_count > 0) return GUESS_EXTRAP;
+  return GUESS_NONE;
+}
+
+// Writes the initial guess of kind g into c->x (the projection reads c->b).
 int set_guess(sw_case* c, int g) {
   hipStream_t s = c->ctx->stream;
   const int64_t nd = 3 * c->mesh->n_nodes;
+  if (g == GUESS_PROJ) {
+    int rc = proj_begin(c);
+    if (rc) return rc;
+    HIPC(hipStreamSynchronize(s));
+    return proj_finish(c);
+  }
   if (g == GUESS_NET) {
     launch_mlp_guess(mlp_features(c), c->mlp->theta, c->x, c->ctl64, s);
   } else if (g == GUESS_EXTRAP) {
@@ -925,13 +1097,9 @@ int solve_step(sw_case* c, int* iters, int* outer, double* relres, int* flags) {
   launch_fill_f64(1, &c->ctl64->bb, 0.0, s);
   launch_norm2(nd, c->b, &c->ctl64->bb, s);
   launch_ctl_prepare(c->ctl64, c->rtol, s);
-  // guess: the network needs four past increments and their neighbour means;
-  // extrapolation needs one; otherwise zero
-  int g = GUESS_NONE;
-  if (c->guess == SW_GUESS_MLP && c->mlp && c->hist_count >= 4 && c->nb_count >= 4)
-    g = GUESS_NET;
-  else if (c->guess != SW_GUESS_ZERO && c->hist_count > 0)
-    g = GUESS_EXTRAP;
+  // guess: the projection needs two past increments, the network four and
+  // their neighbour means, extrapolation one; otherwise zero
+  int g = guess_kind(c);
   rc = set_guess(c, g);
   if (rc) return rc;
   CgCtl h;
@@ -945,8 +1113,9 @@ int solve_step(sw_case* c, int* iters, int* outer, double* relres, int* flags) {
         launch_cg_init_f64(nn, c->b, nullptr, c->pinv64, c->r, c->z, c->p, nullptr, c->ctl64, s);
       }
       LAUNCHED();
-      if (g != GUESS_NET || attempt > 0) break;
-      // reject a learned guess whose residual exceeds that of the zero guess
+      if ((g != GUESS_NET && g != GUESS_PROJ) || attempt > 0) break;
+      // reject a learned or projected guess whose residual exceeds that of
+      // the zero guess
       rc = read_ctl(c, c->ctl64, &h);
       if (rc) return rc;
       double rr0 = 0.0;
@@ -993,8 +1162,9 @@ int solve_step(sw_case* c, int* iters, int* outer, double* relres, int* flags) {
       rc = true_residual(c, &h, true);
       if (rc) return rc;
       ++*outer;
-      if (first && g == GUESS_NET && !(h.rr_true <= h.bb)) {
-        // reject a learned guess whose residual exceeds that of the zero guess
+      if (first && (g == GUESS_NET || g == GUESS_PROJ) && !(h.rr_true <= h.bb)) {
+        // reject a learned or projected guess whose residual exceeds that of
+        // the zero guess
         *flags |= SW_FLAG_GUESS_FALLBACK;
         g = GUESS_EXTRAP;
         rc = set_guess(c, g);
@@ -1032,6 +1202,7 @@ int solve_step(sw_case* c, int* iters, int* outer, double* relres, int* flags) {
     }
   }
   *relres = h.bb > 0.0 ? std::sqrt(h.rr_true / h.bb) : 0.0;
+  c->last_bb = h.bb;
   return SW_OK;
 }
 
@@ -1057,6 +1228,8 @@ extern "C" int sw_case_step(sw_case* c, int32_t n) {
                          c->samp, s);
       c->samp_rows += c->samp_per_step;
     }
+    const bool rec_proj = c->proj_dim > 0 && c->last_bb > 0.0 && !(flags & SW_FLAG_NONFINITE);
+    if (rec_proj && (rc = proj_record_begin(c))) return rc;
     const int head = (c->hist_head + 1) & 3;
     launch_newmark(nd, c->dt, c->x, c->u, c->v, c->a, c->hist + head * nd, s);
     launch_record(c->n_rec, c->rec, c->v, c->wave + c->step * 3 * c->n_rec, s);
@@ -1075,6 +1248,7 @@ extern "C" int sw_case_step(sw_case* c, int32_t n) {
     HIPC(hipMemcpyAsync(c->log_it + c->step, &it32, 4, hipMemcpyHostToDevice, s));
     HIPC(hipMemcpyAsync(c->log_rel + c->step, &rel, 8, hipMemcpyHostToDevice, s));
     HIPC(hipStreamSynchronize(s));
+    if (rec_proj) proj_record_finish(c);
     c->step += 1;
     c->last_iters = std::max(2, iters);
     c->stats.steps += 1;
@@ -1181,12 +1355,7 @@ extern "C" int sw_case_guess(sw_case* c, double* y) {
   if (rc) return rc;
   launch_fill_f64(1, &c->ctl64->bb, 0.0, s);
   launch_norm2(nd, c->b, &c->ctl64->bb, s);
-  int g = GUESS_NONE;
-  if (c->guess == SW_GUESS_MLP && c->hist_count >= 4 && c->nb_count >= 4)
-    g = GUESS_NET;
-  else if (c->guess != SW_GUESS_ZERO && c->hist_count > 0)
-    g = GUESS_EXTRAP;
-  rc = set_guess(c, g);
+  rc = set_guess(c, guess_kind(c));
   if (rc) return rc;
   launch_permute_f64(c->mesh->n_nodes, 3, c->x, c->mesh->dev.node_u2i, y, s);
   LAUNCHED();
@@ -1259,6 +1428,24 @@ static size_t mlp_layout(Carver& cv, sw_mlp* o) {
     o->loss2 = l2;
   }
   return cv.off;
+}
+
+extern "C" int sw_mlp_init_params(uint64_t seed, float* params) {
+  if (!params) return fail(SW_EINVAL, "params is NULL");
+  uint64_t state = seed;
+  auto next = [&state]() {  // splitmix64
+    state += 0x9E3779B97F4A7C15ull;
+    uint64_t z = state;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+  };
+  auto uniform = [&next](double a) { return (float)(a * (2.0 * (double)(next() >> 11) * 0x1.0p-53 - 1.0)); };
+  const double a1 = std::sqrt(6.0 / (MLP_IN + MLP_H)), a2 = std::sqrt(6.0 / (MLP_H + MLP_H));
+  for (int i = 0; i < MLP_NP; ++i) params[i] = 0.0f;
+  for (int i = 0; i < MLP_H * MLP_IN; ++i) params[MLP_OFF_W1 + i] = uniform(a1);
+  for (int i = 0; i < MLP_H * MLP_H; ++i) params[MLP_OFF_W2 + i] = uniform(a2);
+  return SW_OK;
 }
 
 extern "C" int sw_mlp_workspace_bytes(size_t* bytes) {
@@ -1478,16 +1665,13 @@ int batch_step_once(sw_batch* b) {
   std::vector<double> rel(n, 0.0);
   for (int l = 0; l < n; ++l) {
     sw_case* c = b->cases[l];
-    if (c->guess == SW_GUESS_MLP && c->mlp && c->hist_count >= 4 && c->nb_count >= 4)
-      g[l] = GUESS_NET;
-    else if (c->guess != SW_GUESS_ZERO && c->hist_count > 0)
-      g[l] = GUESS_EXTRAP;
-    else
-      g[l] = GUESS_NONE;
+    g[l] = guess_kind(c);
     LaneDev& L = b->lanes[l];
     L.step = c->step;
     L.hist_head = c->hist_head;
-    L.guess_order = g[l] == GUESS_NET ? -2 : (g[l] == GUESS_EXTRAP ? std::min(c->poly_order, c->hist_count - 1) : -1);
+    L.guess_order = (g[l] == GUESS_NET || g[l] == GUESS_PROJ)
+                        ? -2
+                        : (g[l] == GUESS_EXTRAP ? std::min(c->poly_order, c->hist_count - 1) : -1);
     b->rhs1[l].A.vin = c->vin + 3 * (c->step + 1);
     est[l] = std::max(1, c->last_iters / 2);
   }
@@ -1502,8 +1686,19 @@ int batch_step_once(sw_batch* b) {
   launch_lanes(LANE_PREPARE64, n, b->max_nodes, b->d_lanes, nullptr, nullptr, s);
   launch_lanes(LANE_GUESS, n, b->max_nodes, b->d_lanes, nullptr, nullptr, s);
   LAUNCHED();
-  for (int l = 0; l < n; ++l)
+  bool any_proj = false;
+  for (int l = 0; l < n; ++l) {
     if (g[l] == GUESS_NET && (rc = set_guess(b->cases[l], GUESS_NET))) return rc;
+    if (g[l] == GUESS_PROJ) {
+      if ((rc = proj_begin(b->cases[l]))) return rc;
+      any_proj = true;
+    }
+  }
+  if (any_proj) {
+    HIPC(hipStreamSynchronize(s));
+    for (int l = 0; l < n; ++l)
+      if (g[l] == GUESS_PROJ && (rc = proj_finish(b->cases[l]))) return rc;
+  }
   // refinement rounds
   for (;;) {
     for (int l = 0; l < n; ++l) {
@@ -1527,9 +1722,9 @@ int batch_step_once(sw_batch* b) {
       const LaneInfo& h = b->info[l];
       ++outer[l];
       S.active = 0;
-      if (first[l] && g[l] == GUESS_NET && !(h.rr_true <= h.bb)) {
-        // reject a learned guess whose residual exceeds that of the zero
-        // guess; the lane's true residual is taken again next round
+      if (first[l] && (g[l] == GUESS_NET || g[l] == GUESS_PROJ) && !(h.rr_true <= h.bb)) {
+        // reject a learned or projected guess whose residual exceeds that of
+        // the zero guess; the lane's true residual is taken again next round
         flags[l] |= SW_FLAG_GUESS_FALLBACK;
         g[l] = GUESS_EXTRAP;
         first[l] = 0;
@@ -1601,7 +1796,8 @@ int batch_step_once(sw_batch* b) {
     launch_lanes(LANE_IR_UPDATE, n, b->max_nodes, b->d_lanes, b->d_st, nullptr, s);
     LAUNCHED();
   }
-  // training samples, Newmark update, receivers, logs
+  // training samples, projection ring, Newmark update, receivers, logs
+  std::vector<char> rec_proj(n, 0);
   for (int l = 0; l < n; ++l) {
     sw_case* c = b->cases[l];
     if (c->samp && c->hist_count >= 4 && c->nb_count >= 4) {
@@ -1609,6 +1805,9 @@ int batch_step_once(sw_batch* b) {
                          c->samp, s);
       c->samp_rows += c->samp_per_step;
     }
+    c->last_bb = b->info[l].bb;
+    rec_proj[l] = c->proj_dim > 0 && c->last_bb > 0.0 && !(flags[l] & SW_FLAG_NONFINITE);
+    if (rec_proj[l] && (rc = proj_record_begin(c))) return rc;
     b->st[l].active = 1;
     b->st[l].iters = iters[l];
     b->st[l].rel = rel[l];
@@ -1635,6 +1834,7 @@ int batch_step_once(sw_batch* b) {
   HIPC(hipStreamSynchronize(s));
   for (int l = 0; l < n; ++l) {
     sw_case* c = b->cases[l];
+    if (rec_proj[l]) proj_record_finish(c);
     c->step += 1;
     c->last_iters = std::max(2, iters[l]);
     c->stats.steps += 1;

@@ -236,6 +236,20 @@ void launch_neighbour_mean(const MeshDev& m, const double* in, float* out, hipSt
 // out[node][2] = (Vs, rho) averaged over the node's elements (out cleared first)
 void launch_node_material(const MeshDev& m, const uint8_t* emat, const MatDev* mats, float* out, hipStream_t s);
 
+// ---- projection initial guess (sw_proj.hip) -------------------------------
+
+constexpr int PROJ_MAX = 16;      // largest ring of past increments
+constexpr int PROJ_BLOCKS = 1024; // workgroups of a dot-product pass
+// out[i] = R_i . (v - w) for the L ring vectors R_i (w may be null); part
+// holds PROJ_BLOCKS * L doubles of workgroup partials
+void launch_proj_dots(int L, int64_t n, const double* R, const double* v, const double* w, double* part,
+                      double* out, hipStream_t s);
+// x = sum_i theta[i] X_i (theta on the device)
+void launch_proj_combine(int L, int64_t n, const double* X, const double* theta, double* x, hipStream_t s);
+// Xs = x, Ys = b - r
+void launch_proj_store(int64_t n, const double* x, const double* b, const double* r, double* Xs, double* Ys,
+                       hipStream_t s);
+
 void launch_fill_f64(int64_t n, double* x, double val, hipStream_t s);
 void launch_fill_f32(int64_t n, float* x, float val, hipStream_t s);
 

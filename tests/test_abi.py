@@ -49,3 +49,26 @@ def test_product_has_no_oracle_dependency():
                 txt = open(os.path.join(dp, f)).read()
                 assert not re.search(r"^\s*(from|import)\s+oracle", txt, flags=re.M), f
                 assert "casegen" not in txt, f
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="library not built")
+def test_mlp_initial_parameters():
+    """Host-side initializer: Glorot-uniform hidden weights within their
+    bounds, zero biases and output layer, deterministic per seed."""
+    import numpy as np
+    from paper_2404_17754_amd import _lib as L
+    lib = L.load()
+
+    def init(seed):
+        p = np.zeros(L.MLP_NPARAM, np.float32)
+        L.check(lib.sw_mlp_init_params(seed, p.ctypes.data_as(C.c_void_p)))
+        return p
+
+    p = init(7)
+    W1, b1, W2, b2, w3, b3 = p[:640], p[640:704], p[704:4800], p[4800:4864], p[4864:4928], p[4928:]
+    a1, a2 = np.sqrt(6.0 / 74), np.sqrt(6.0 / 128)
+    assert np.all(np.abs(W1) <= a1) and np.all(np.abs(W2) <= a2)
+    # uniform over [-a, a): mean near 0, variance near a^2 / 3
+    assert abs(W2.mean()) < 0.05 * a2 and abs(W2.var() / (a2 * a2 / 3) - 1) < 0.1
+    assert not b1.any() and not b2.any() and not w3.any() and not b3.any()
+    assert np.array_equal(p, init(7)) and not np.array_equal(p, init(8))
