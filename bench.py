@@ -11,12 +11,16 @@ whole analysis (400 steps from rest by default).  Inputs are synthetic
 (seeded interface field, seeded wavelet) and resident in HBM before timing
 starts.
 
-The initial guess is the learned one by default: a network trained, before
-timing, on solution histories that the solver generates for separate
-training models (200 x 200 x 100 m boxes of the same cells, time step and
-input), marched together as one batch.  The same run times the polynomial
-guess and the plain FP64 PCG (zero guess) on a common window of steps, and
-the CPU oracle on a bounded sample of the workload.
+Each step starts by default from the projection guess: the Galerkin
+projection of its solution onto the span of the last 12 increments.  The
+same run times, on a common window of steps from rest, the polynomial
+guess, the learned guess (a network trained before timing on solution
+histories that the solver generates for separate training models, 200 x
+200 x 100 m boxes of the same cells, time step and input, marched together
+as one batch) and the plain FP64 PCG (zero guess), and the CPU oracle on a
+bounded sample of the workload.  --batched K adds a study of K candidate
+models per mesh on the three uneven meshes of the batched workload, marched
+case by case and as one batch.
 
 Prints one JSON line with the metric, the roofline of the dominant kernel
 (algorithmic flops and bytes / HIP-event-timed mean duration of its full
@@ -138,6 +142,48 @@ def train_network(sw, cg, ctx, cfg, n_cases, n_steps, train_steps, per_step=8192
     return net, info
 
 
+def batched_study(sw, cg, ctx, per_mesh, steps, proj_dim):
+    """Candidate models on the three uneven meshes of the batched workload
+    (200/300/400 x 100 m boxes, 5 m cells; seeded interface fields), marched
+    `steps` steps from rest with the projection guess: once case by case,
+    once as one batch.  Returns the two rates in case-timesteps/s."""
+    import numpy as np
+    import torch
+    meshes, cases = [], []
+    for name in ("batch200", "batch300", "batch400"):
+        cfg = cg.CONFIGS[name]
+        m = cg.config_mesh(cfg)
+        gm = sw.Mesh(ctx, m)
+        meshes.append((name, m.n_tets))
+        for k in range(per_mesh):
+            cases.append((gm, cg.make_case(m, cfg, seed=cfg.seed + 3 * k + len(cases), n_steps=steps)))
+
+    def run(batched):
+        lanes = [sw.Case(ctx, gm, c, precision="mixed", guess="proj", proj_dim=proj_dim) for gm, c in cases]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        if batched:
+            sw.Batch(ctx, lanes).step(steps)
+        else:
+            for lane in lanes:
+                lane.step(steps)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        its = float(np.mean([lane.step_log()[0].mean() for lane in lanes]))
+        worst = float(max(lane.stats()["max_true_rel_res"] for lane in lanes))
+        del lanes
+        torch.cuda.empty_cache()
+        return len(cases) * steps / dt, its, worst
+
+    seq, its_s, _ = run(False)
+    bat, its_b, worst = run(True)
+    return {"meshes": [f"{n}: {t} tets" for n, t in meshes], "cases": len(cases), "steps": steps,
+            "guess": f"proj (L={proj_dim})", "sequential_case_timesteps_per_s": round(seq, 2),
+            "batched_case_timesteps_per_s": round(bat, 2), "speedup": round(bat / seq, 3),
+            "cg_iters_per_step": {"sequential": round(its_s, 2), "batched": round(its_b, 2)},
+            "max_true_rel_res": worst}
+
+
 def timed_window(sw, ctx, gmesh, case, n, **kw):
     """A fresh case marched `n` steps from rest; ms per step and the step
     log."""
@@ -164,9 +210,16 @@ def main():
     ap.add_argument("--steps", type=int, default=400, help="timed steps (from rest; 400 = the whole analysis)")
     ap.add_argument("--warmup", type=int, default=3, help="untimed steps on a separate copy of the case")
     ap.add_argument("--config", default="large")
-    ap.add_argument("--guess", default="mlp", choices=["zero", "poly", "mlp"])
-    ap.add_argument("--compare-steps", type=int, default=60,
-                    help="window (from rest) on which the polynomial guess and plain FP64 PCG are timed (0 = skip)")
+    ap.add_argument("--guess", default="proj", choices=["zero", "poly", "mlp", "proj"])
+    ap.add_argument("--proj-dim", type=int, default=12, help="past increments spanned by the projection guess")
+    ap.add_argument("--inner-rtol", type=float, default=0.0,
+                    help="floor of the inner FP32 CG tolerance (0 = the library default)")
+    ap.add_argument("--compare-steps", type=int, default=100,
+                    help="window (from rest) on which the other guesses and plain FP64 PCG are timed (0 = skip)")
+    ap.add_argument("--no-mlp-compare", action="store_true", help="leave the trained-network leg out")
+    ap.add_argument("--batched", type=int, default=0,
+                    help="cases per mesh of an extra batched-vs-sequential study on the 200/300/400 m meshes")
+    ap.add_argument("--batched-steps", type=int, default=30)
     ap.add_argument("--train-cases", type=int, default=4)
     ap.add_argument("--train-steps", type=int, default=150)
     ap.add_argument("--adam-steps", type=int, default=3000)
@@ -201,21 +254,23 @@ def main():
     t_up = time.perf_counter() - t_up
 
     net, train_info = None, None
-    if args.guess == "mlp":
+    if args.guess == "mlp" or (args.compare_steps > 0 and not args.no_mlp_compare):
         net, train_info = train_network(sw, cg, ctx, cfg, args.train_cases, args.train_steps, args.adam_steps)
 
     # warm-up on a separate copy of the case
     if args.warmup > 0:
-        w = sw.Case(ctx, gmesh, case, rtol=1e-8, precision="mixed", guess=args.guess)
-        if net is not None:
+        w = sw.Case(ctx, gmesh, case, rtol=1e-8, precision="mixed", guess=args.guess, proj_dim=args.proj_dim,
+                    inner_rtol=args.inner_rtol)
+        if args.guess == "mlp":
             w.attach_mlp(net)
         w.step(args.warmup)
         torch.cuda.synchronize()
         del w
         torch.cuda.empty_cache()
 
-    gc = sw.Case(ctx, gmesh, case, rtol=1e-8, precision="mixed", guess=args.guess)
-    if net is not None:
+    gc = sw.Case(ctx, gmesh, case, rtol=1e-8, precision="mixed", guess=args.guess, proj_dim=args.proj_dim,
+                 inner_rtol=args.inner_rtol)
+    if args.guess == "mlp":
         gc.attach_mlp(net)
     if args.calibrate_copy_mib > 0:
         src = torch.ones(args.calibrate_copy_mib << 18, dtype=torch.float32, device="cuda")
@@ -283,9 +338,9 @@ def main():
         compare = {"window_steps": cmp_n,
                    args.guess: {"ms_per_step": round(ms_window, 2), "value": round(1000.0 / ms_window, 3),
                                 "cg_iters_per_step": float(np.mean(it[:cmp_n]))}}
-        legs = [("plain_fp64", dict(precision="fp64", guess="zero"))]
-        if args.guess != "poly":
-            legs.insert(0, ("poly", dict(precision="mixed", guess="poly")))
+        legs = [(g, dict(precision="mixed", guess=g, proj_dim=args.proj_dim, net=net if g == "mlp" else None))
+                for g in ("poly", "mlp", "proj") if g != args.guess and (g != "mlp" or net is not None)]
+        legs.append(("plain_fp64", dict(precision="fp64", guess="zero")))
         for name, kw in legs:
             ms, pit, prel, pst = timed_window(sw, ctx, gmesh, case, cmp_n, **kw)
             compare[name] = {"ms_per_step": round(ms, 2), "value": round(1000.0 / ms, 3),
@@ -293,6 +348,12 @@ def main():
                              "flags": pst["flags"]}
         compare["speedup_vs_plain_fp64"] = round(compare["plain_fp64"]["ms_per_step"] / ms_window, 3)
         compare["plain_fp64"]["method"] = "FP64 block-Jacobi PCG, zero initial guess"
+
+    batched = None
+    if args.batched > 0:
+        del gmesh
+        torch.cuda.empty_cache()
+        batched = batched_study(sw, cg, ctx, args.batched, args.batched_steps, args.proj_dim)
 
     cpu = None if args.no_cpu_baseline else cpu_baseline(args.config, dof)
 
@@ -306,13 +367,14 @@ def main():
                                 f"Ricker {cfg.freqs} Hz, one case, steps 0-{args.steps} from rest"),
                    "precision": "FP32 inner CG in FP64 refinement", "guess": args.guess, "rtol": 1e-8,
                    "parallelism": "single GPU"},
-        "cg_iters_per_step": float(np.mean(it)), "max_true_rel_res": float(np.max(rel)),
+        "cg_iters_per_step": float(np.mean(it)), "refinement_rounds_per_step": round(stats["ir_outer"] / stats["steps"], 3),
+        "max_true_rel_res": float(np.max(rel)),
         "flags": stats["flags"], "wall_s_timed": round(wall, 3),
         "setup_s": {"host_generation": round(t_gen, 2), "mesh_upload_and_layout": round(t_up, 2)},
         "learned_guess_training": train_info,
         "kernels_ms": {k: {"total_ms": round(v[0], 3), "launches": v[1], "full_launch_us": round(1e3 * v[2], 1)}
                        for k, v in kernels.items() if v[1]},
-        "roofline": roofline, "compare": compare, "cpu_baseline": cpu,
+        "roofline": roofline, "compare": compare, "batched": batched, "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
 
