@@ -1005,8 +1005,9 @@ int proj_begin(sw_case* c) {
 }
 
 // Second half (after a synchronisation): theta from the Gram matrix of the
-// filled slots, x = X theta.
-int proj_finish(sw_case* c) {
+// filled slots, x = X theta; with_res: also r = b - Y theta and its norm in
+// ctl64->rr_true (the residual of x from the stored images).
+int proj_finish(sw_case* c, bool with_res) {
   hipStream_t s = c->ctx->stream;
   const int L = c->proj_dim;
   const int64_t nd = 3 * c->mesh->n_nodes;
@@ -1022,7 +1023,11 @@ int proj_finish(sw_case* c) {
   std::fill(c->proj_th.begin(), c->proj_th.end(), 0.0);
   for (int i = 0; i < m; ++i) c->proj_th[idx[i]] = std::isfinite(ts[i]) ? ts[i] : 0.0;
   HIPC(hipMemcpyAsync(c->proj_theta, c->proj_th.data(), L * sizeof(double), hipMemcpyHostToDevice, s));
-  launch_proj_combine(L, nd, c->projX, c->proj_theta, c->x, s);
+  if (with_res)
+    launch_proj_combine_res(L, nd, c->projX, c->projY, c->proj_theta, c->b, c->x, c->r, c->proj_part,
+                            &c->ctl64->rr_true, s);
+  else
+    launch_proj_combine(L, nd, c->projX, c->proj_theta, c->x, s);
   LAUNCHED();
   return SW_OK;
 }
@@ -1038,19 +1043,19 @@ int proj_record_begin(sw_case* c) {
   double* Ys = c->projY + (size_t)sl * nd;
   launch_proj_store(nd, c->x, c->b, c->r, Xs, Ys, s);
   launch_proj_dots(L, nd, c->projX, Ys, nullptr, c->proj_part, c->proj_out, s);
-  launch_proj_dots(L, nd, c->projY, Xs, nullptr, c->proj_part, c->proj_out + L, s);
   LAUNCHED();
-  HIPC(hipMemcpyAsync(c->proj_h.data(), c->proj_out, 2 * L * sizeof(double), hipMemcpyDeviceToHost, s));
+  HIPC(hipMemcpyAsync(c->proj_h.data(), c->proj_out, L * sizeof(double), hipMemcpyDeviceToHost, s));
   c->proj_head = sl;
   c->proj_count = std::min(c->proj_count + 1, L);
   return SW_OK;
 }
 
-// After the synchronisation: symmetric Gram row of the new slot.
+// After the synchronisation: the Gram row and column of the new slot
+// (X_i . A X_s = X_s . A X_i: A is symmetric and the images are exact).
 void proj_record_finish(sw_case* c) {
   const int L = c->proj_dim, sl = c->proj_head;
   for (int i = 0; i < L; ++i) {
-    const double g = 0.5 * (c->proj_h[i] + c->proj_h[L + i]);
+    const double g = c->proj_h[i];
     c->projG[(size_t)i * L + sl] = g;
     c->projG[(size_t)sl * L + i] = g;
   }
@@ -1064,15 +1069,16 @@ int guess_kind(const sw_case* c) {
   return GUESS_NONE;
 }
 
-// Writes the initial guess of kind g into c->x (the projection reads c->b).
-int set_guess(sw_case* c, int g) {
+// Writes the initial guess of kind g into c->x (the projection reads c->b;
+// with_res: it also leaves its residual in c->r and ctl64->rr_true).
+int set_guess(sw_case* c, int g, bool with_res = false) {
   hipStream_t s = c->ctx->stream;
   const int64_t nd = 3 * c->mesh->n_nodes;
   if (g == GUESS_PROJ) {
     int rc = proj_begin(c);
     if (rc) return rc;
     HIPC(hipStreamSynchronize(s));
-    return proj_finish(c);
+    return proj_finish(c, with_res);
   }
   if (g == GUESS_NET) {
     launch_mlp_guess(mlp_features(c), c->mlp->theta, c->x, c->ctl64, s);
@@ -1100,7 +1106,7 @@ int solve_step(sw_case* c, int* iters, int* outer, double* relres, int* flags) {
   // guess: the projection needs two past increments, the network four and
   // their neighbour means, extrapolation one; otherwise zero
   int g = guess_kind(c);
-  rc = set_guess(c, g);
+  rc = set_guess(c, g, c->precision == SW_MIXED_FP32);
   if (rc) return rc;
   CgCtl h;
   if (c->precision == SW_FP64) {
@@ -1158,8 +1164,12 @@ int solve_step(sw_case* c, int* iters, int* outer, double* relres, int* flags) {
   } else {
     int inner_est = std::max(1, c->last_iters / 2);
     bool first = true;
+    // a projected guess comes with its residual from the stored images
+    bool image_res = g == GUESS_PROJ;
     for (;;) {
-      rc = true_residual(c, &h, true);
+      const bool from_images = image_res;
+      image_res = false;
+      rc = from_images ? read_ctl(c, c->ctl64, &h) : true_residual(c, &h, true);
       if (rc) return rc;
       ++*outer;
       if (first && (g == GUESS_NET || g == GUESS_PROJ) && !(h.rr_true <= h.bb)) {
@@ -1176,7 +1186,10 @@ int solve_step(sw_case* c, int* iters, int* outer, double* relres, int* flags) {
         *flags |= SW_FLAG_NONFINITE;
         break;
       }
-      if (h.rr_true <= c->rtol * c->rtol * h.bb) break;
+      if (h.rr_true <= c->rtol * c->rtol * h.bb) {
+        if (from_images) continue;  // confirm with an operator pass
+        break;
+      }
       if (*iters >= c->max_iter) {
         *flags |= SW_FLAG_NOCONV;
         break;
@@ -1694,15 +1707,20 @@ int batch_step_once(sw_batch* b) {
       any_proj = true;
     }
   }
+  // a projected guess comes with its residual from the stored images
+  std::vector<char> image_res(n, 0);
   if (any_proj) {
     HIPC(hipStreamSynchronize(s));
     for (int l = 0; l < n; ++l)
-      if (g[l] == GUESS_PROJ && (rc = proj_finish(b->cases[l]))) return rc;
+      if (g[l] == GUESS_PROJ) {
+        if ((rc = proj_finish(b->cases[l], true))) return rc;
+        image_res[l] = 1;
+      }
   }
   // refinement rounds
   for (;;) {
     for (int l = 0; l < n; ++l) {
-      b->st[l].active = !stopped[l];
+      b->st[l].active = !stopped[l] && !image_res[l];
       b->st[l].zero_q = 1;
     }
     if ((rc = batch_upload(b, b->d_st, b->st.data(), n * sizeof(LaneState)))) return rc;
@@ -1720,6 +1738,8 @@ int batch_step_once(sw_batch* b) {
       }
       sw_case* c = b->cases[l];
       const LaneInfo& h = b->info[l];
+      const bool from_images = image_res[l];
+      image_res[l] = 0;
       ++outer[l];
       S.active = 0;
       if (first[l] && (g[l] == GUESS_NET || g[l] == GUESS_PROJ) && !(h.rr_true <= h.bb)) {
@@ -1738,6 +1758,10 @@ int batch_step_once(sw_batch* b) {
         flags[l] |= SW_FLAG_NONFINITE;
         stop = true;
       } else if (h.rr_true <= c->rtol * c->rtol * h.bb) {
+        if (from_images) {  // confirm with an operator pass next round
+          any_open = true;
+          continue;
+        }
         stop = true;
       } else if (iters[l] >= c->max_iter) {
         flags[l] |= SW_FLAG_NOCONV;

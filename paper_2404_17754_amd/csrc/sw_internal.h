@@ -246,6 +246,9 @@ void launch_proj_dots(int L, int64_t n, const double* R, const double* v, const 
                       double* out, hipStream_t s);
 // x = sum_i theta[i] X_i (theta on the device)
 void launch_proj_combine(int L, int64_t n, const double* X, const double* theta, double* x, hipStream_t s);
+// x = sum_i theta[i] X_i, r = b - sum_i theta[i] Y_i, *rr_out = r.r
+void launch_proj_combine_res(int L, int64_t n, const double* X, const double* Y, const double* theta,
+                             const double* b, double* x, double* r, double* part, double* rr_out, hipStream_t s);
 // Xs = x, Ys = b - r
 void launch_proj_store(int64_t n, const double* x, const double* b, const double* r, double* Xs, double* Ys,
                        hipStream_t s);

@@ -76,6 +76,36 @@ __global__ __launch_bounds__(TPB) void k_proj_combine(int64_t n, const double* _
   }
 }
 
+// x = sum_i theta[i] X_i and its residual r = b - sum_i theta[i] Y_i (the
+// images Y_i = A X_i are exact, so no operator pass is needed); workgroup
+// partials of r.r into part[blk]
+template <int L>
+__global__ __launch_bounds__(TPB) void k_proj_combine_res(int64_t n, const double* __restrict__ X,
+                                                          const double* __restrict__ Y,
+                                                          const double* __restrict__ theta,
+                                                          const double* __restrict__ b, double* __restrict__ x,
+                                                          double* __restrict__ r, double* __restrict__ part) {
+  __shared__ double sh[TPB / 64];
+  double th[L];
+#pragma unroll
+  for (int i = 0; i < L; ++i) th[i] = theta[i];
+  double acc = 0.0;
+  for (int64_t k = (int64_t)blockIdx.x * TPB + threadIdx.x; k < n; k += (int64_t)gridDim.x * TPB) {
+    double sx = 0.0, sy = 0.0;
+#pragma unroll
+    for (int i = 0; i < L; ++i) {
+      sx += th[i] * X[(int64_t)i * n + k];
+      sy += th[i] * Y[(int64_t)i * n + k];
+    }
+    x[k] = sx;
+    const double t = b[k] - sy;
+    r[k] = t;
+    acc += t * t;
+  }
+  acc = block_sum(acc, sh);
+  if (threadIdx.x == 0) part[blockIdx.x] = acc;
+}
+
 // X_slot = x, Y_slot = b - r
 __global__ __launch_bounds__(TPB) void k_proj_store(int64_t n, const double* __restrict__ x,
                                                     const double* __restrict__ b, const double* __restrict__ r,
@@ -124,6 +154,24 @@ void launch_proj_combine(int L, int64_t n, const double* X, const double* theta,
     default:
       return;
   }
+}
+
+void launch_proj_combine_res(int L, int64_t n, const double* X, const double* Y, const double* theta,
+                             const double* b, double* x, double* r, double* part, double* rr_out, hipStream_t s) {
+  const unsigned g = proj_grid(n);
+  switch (L) {
+#define SW_PROJ_CASE(K)                                                                                  \
+  case K:                                                                                                \
+    hipLaunchKernelGGL(k_proj_combine_res<K>, dim3(g), dim3(TPB), 0, s, n, X, Y, theta, b, x, r, part); \
+    break;
+    SW_PROJ_CASE(2) SW_PROJ_CASE(3) SW_PROJ_CASE(4) SW_PROJ_CASE(5) SW_PROJ_CASE(6) SW_PROJ_CASE(7)
+    SW_PROJ_CASE(8) SW_PROJ_CASE(9) SW_PROJ_CASE(10) SW_PROJ_CASE(11) SW_PROJ_CASE(12) SW_PROJ_CASE(13)
+    SW_PROJ_CASE(14) SW_PROJ_CASE(15) SW_PROJ_CASE(16)
+#undef SW_PROJ_CASE
+    default:
+      return;
+  }
+  hipLaunchKernelGGL(k_proj_reduce, dim3(1), dim3(TPB), 0, s, (int)g, 1, part, rr_out);
 }
 
 void launch_proj_store(int64_t n, const double* x, const double* b, const double* r, double* Xs, double* Ys,
