@@ -14,6 +14,12 @@
 #include "sw_internal.h"
 #include "sw_layout.h"
 
+#include <algorithm>
+
+#ifndef SW_PIPE_PF
+#define SW_PIPE_PF false
+#endif
+
 namespace sw {
 
 // Per-element inputs fetched from global memory: tile-local connectivity,
@@ -71,72 +77,27 @@ __device__ __forceinline__ void elem_geometry(const ElemIn<float>& in, Geo<float
   G.vol = in.geo[9];
 }
 
-// One workgroup's share of an operator pass: tile t of mesh m.  smem_raw is
-// the dynamic LDS (sized for m.max_tile_nodes), sh NT/64 doubles.
-template <typename T, int NT>
-__device__ __forceinline__ void tile_body(const MeshDev& m, const uint8_t* __restrict__ emat,
-                                          const MatDev* __restrict__ mats, const TileArgs<T>& A, CgCtl* ctl,
-                                          int iter, int t, unsigned char* smem_raw, double* sh) {
-  // LDS: FP64 accumulators (LDS FP64 atomics are much faster than FP32 ones
-  // on this target), then the tile's input values in T
-  double* ys = reinterpret_cast<double*>(smem_raw);
-  int32_t* gid = reinterpret_cast<int32_t*>(ys + 3 * m.max_tile_nodes);
-  T* xs = reinterpret_cast<T*>(gid + m.max_tile_nodes + (m.max_tile_nodes & 1));
-  // CG-iteration protocol: exit when the solve is done; on the first
-  // iteration end a solve whose initial residual meets the tolerance; the
-  // workgroup of tile 0 clears the scalar slots the next update kernel
-  // accumulates into.
-  if (iter >= 0) {
-    const int par = iter & 1;
-    if (ctl->done) return;
-    if (iter == 0 && slot_sum<NSLOT>(ctl->rr[0]) <= ctl->tol2) {
-      if (t == 0 && threadIdx.x == 0) ctl->done = 1;
-      return;
-    }
-    if (t == 0 && threadIdx.x < NSLOT) {
-      ctl->rz[par ^ 1][threadIdx.x] = 0.0;
-      ctl->rr[par ^ 1][threadIdx.x] = 0.0;
-    }
-  }
-  const int n0 = m.tile_node_off[t];
-  const int nt = m.tile_node_off[t + 1] - n0;
-  const int nint = m.tile_nint[t];
-  const int64_t ib3 = 3 * (int64_t)m.tile_int_base[t];
-
-  // node ids of the tile into LDS
-  for (int j = threadIdx.x; j < nt; j += NT) gid[j] = m.tile_nodes[n0 + j];
-  __syncthreads();
-  // gather xe = a1 x1 + a2 x2 for the tile's nodes; clear the accumulator
-  for (int k = threadIdx.x; k < 3 * nt; k += NT) {
-    int64_t gi;
-    if (k < 3 * nint) {
-      gi = ib3 + k;
-    } else {
-      const int j = k / 3;
-      gi = 3 * (int64_t)gid[j] + (k - 3 * j);
-    }
-    T v = A.a1 * A.x1[gi];
-    if (A.x2 != nullptr) v += A.a2 * A.x2[gi];
-    xs[k] = v;
-    ys[k] = 0.0;
-  }
-  __syncthreads();
-
+// Element and face work of tile t on the values gathered in LDS (xs, node
+// ids gid), accumulated into ys; returns the tile's share of x.A x (only the
+// CG passes use it).  Work-item i takes the tile's element i: the layout
+// has interleaved the elements so that consecutive ones rarely share a node
+// (few LDS atomic collisions) while their loads stay coalesced.  PF: software
+// pipeline, the next element's connectivity, geometry and material are
+// loaded before the current one is computed (FP32; in FP64 the registers
+// would halve the occupancy).
+template <typename T, int NT, bool PF>
+__device__ __forceinline__ double tile_elements(const MeshDev& m, const uint8_t* __restrict__ emat,
+                                                const MatDev* __restrict__ mats, const TileArgs<T>& A, int t,
+                                                const int32_t* gid, const T* xs, double* ys) {
   double energy = 0.0;
   if (A.sM != (T)0 || A.sK != (T)0) {
-    // Work-item i takes the tile's element i: the layout has interleaved
-    // the elements so that consecutive ones rarely share a node (few LDS
-    // atomic collisions) while their loads stay coalesced.  Software
-    // pipeline (FP32): the next element's connectivity, geometry and
-    // material are loaded before the current one is computed.
     const int eb = m.tile_elem_off[t];
     const int n_e = m.tile_elem_off[t + 1] - eb;
     auto elem_of = [&](int i) { return eb + i; };
     ElemIn<T> nx;
     int i = threadIdx.x;
     if (i < n_e) load_elem(m, gid, emat, elem_of(i), nx);
-    // (FP64: the prefetch registers would halve the occupancy, so no pipeline)
-    constexpr bool kPrefetch = sizeof(T) == 4;
+    constexpr bool kPrefetch = PF;
     for (; i < n_e; i += NT) {
       if (!kPrefetch && i != (int)threadIdx.x) load_elem(m, gid, emat, elem_of(i), nx);
       const ElemIn<T> cur = nx;
@@ -223,9 +184,17 @@ __device__ __forceinline__ void tile_body(const MeshDev& m, const uint8_t* __res
       }
     }
   }
-  __syncthreads();
+  return energy;
+}
 
-  // interior nodes: one contiguous range, plain stores
+// Results of tile t: interior nodes (one contiguous range) with plain
+// stores, shared nodes with address-sorted global atomics.
+template <typename T, int NT>
+__device__ __forceinline__ void tile_scatter(const MeshDev& m, const TileArgs<T>& A, int t, const int32_t* gid,
+                                             const double* ys) {
+  const int nt = m.tile_node_off[t + 1] - m.tile_node_off[t];
+  const int nint = m.tile_nint[t];
+  const int64_t ib3 = 3 * (int64_t)m.tile_int_base[t];
   T* __restrict__ y = A.y;
   for (int k = threadIdx.x; k < 3 * nint; k += NT) {
     if (A.accumulate)
@@ -238,6 +207,62 @@ __device__ __forceinline__ void tile_body(const MeshDev& m, const uint8_t* __res
     const int j = k / 3;
     atomic_add(&y[3 * (int64_t)gid[j] + (k - 3 * j)], (T)ys[k]);
   }
+}
+
+// One workgroup's share of an operator pass: tile t of mesh m.  smem_raw is
+// the dynamic LDS (sized for m.max_tile_nodes), sh NT/64 doubles.
+template <typename T, int NT>
+__device__ __forceinline__ void tile_body(const MeshDev& m, const uint8_t* __restrict__ emat,
+                                          const MatDev* __restrict__ mats, const TileArgs<T>& A, CgCtl* ctl,
+                                          int iter, int t, unsigned char* smem_raw, double* sh) {
+  // LDS: FP64 accumulators (LDS FP64 atomics are much faster than FP32 ones
+  // on this target), then the tile's input values in T
+  double* ys = reinterpret_cast<double*>(smem_raw);
+  int32_t* gid = reinterpret_cast<int32_t*>(ys + 3 * m.max_tile_nodes);
+  T* xs = reinterpret_cast<T*>(gid + m.max_tile_nodes + (m.max_tile_nodes & 1));
+  // CG-iteration protocol: exit when the solve is done; on the first
+  // iteration end a solve whose initial residual meets the tolerance; the
+  // workgroup of tile 0 clears the scalar slots the next update kernel
+  // accumulates into.
+  if (iter >= 0) {
+    const int par = iter & 1;
+    if (ctl->done) return;
+    if (iter == 0 && slot_sum<NSLOT>(ctl->rr[0]) <= ctl->tol2) {
+      if (t == 0 && threadIdx.x == 0) ctl->done = 1;
+      return;
+    }
+    if (t == 0 && threadIdx.x < NSLOT) {
+      ctl->rz[par ^ 1][threadIdx.x] = 0.0;
+      ctl->rr[par ^ 1][threadIdx.x] = 0.0;
+    }
+  }
+  const int n0 = m.tile_node_off[t];
+  const int nt = m.tile_node_off[t + 1] - n0;
+  const int nint = m.tile_nint[t];
+  const int64_t ib3 = 3 * (int64_t)m.tile_int_base[t];
+
+  // node ids of the tile into LDS
+  for (int j = threadIdx.x; j < nt; j += NT) gid[j] = m.tile_nodes[n0 + j];
+  __syncthreads();
+  // gather xe = a1 x1 + a2 x2 for the tile's nodes; clear the accumulator
+  for (int k = threadIdx.x; k < 3 * nt; k += NT) {
+    int64_t gi;
+    if (k < 3 * nint) {
+      gi = ib3 + k;
+    } else {
+      const int j = k / 3;
+      gi = 3 * (int64_t)gid[j] + (k - 3 * j);
+    }
+    T v = A.a1 * A.x1[gi];
+    if (A.x2 != nullptr) v += A.a2 * A.x2[gi];
+    xs[k] = v;
+    ys[k] = 0.0;
+  }
+  __syncthreads();
+
+  double energy = tile_elements<T, NT, sizeof(T) == 4>(m, emat, mats, A, t, gid, xs, ys);
+  __syncthreads();
+  tile_scatter<T, NT>(m, A, t, gid, ys);
   if (iter >= 0) {
     const double s = block_sum_n<NT>(energy, sh);
     if (threadIdx.x == 0) atomic_add(&ctl->pAp[t % NSLOT], s);
@@ -268,16 +293,138 @@ __global__ __launch_bounds__(NT) void k_tile_lanes(const TileLane<T>* __restrict
   tile_body<T, NT>(L.m, L.emat, L.mats, L.A, L.ctl, iter, w.y, smem_raw, sh);
 }
 
+// FP32 operator pass of a CG iteration (input scaled by 1, no second input),
+// persistent and software-pipelined.  Each workgroup walks a run of tiles;
+// while it computes tile t it already loads the node ids and input values of
+// its next tile into registers (node by node, 12 contiguous bytes per node),
+// so a tile's gather latency hides behind the element work of the one
+// before.  XCD-aware: workgroup b runs on XCD b mod 8 (workgroups are dealt
+// to the 8 XCDs round-robin) and takes its tiles from that XCD's contiguous
+// eighth of the tile list, so neighbouring tiles, which share nodes, meet in
+// the same L2.  NPT * NT must cover the largest tile.
+template <int NT, int NPT, bool PF>
+__global__ __launch_bounds__(NT) void k_tile_pipe(MeshDev m, const uint8_t* __restrict__ emat,
+                                                   const MatDev* __restrict__ mats, TileArgs<float> A, CgCtl* ctl,
+                                                   int iter) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  __shared__ double sh[NT / 64];
+  double* ys = reinterpret_cast<double*>(smem_raw);
+  int32_t* gid = reinterpret_cast<int32_t*>(ys + 3 * m.max_tile_nodes);
+  float* xs = reinterpret_cast<float*>(gid + m.max_tile_nodes + (m.max_tile_nodes & 1));
+  // CG-iteration protocol (as in tile_body; workgroup 0 leads)
+  const int par = iter & 1;
+  if (ctl->done) return;
+  if (iter == 0 && slot_sum<NSLOT>(ctl->rr[0]) <= ctl->tol2) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) ctl->done = 1;
+    return;
+  }
+  if (blockIdx.x == 0 && threadIdx.x < NSLOT) {
+    ctl->rz[par ^ 1][threadIdx.x] = 0.0;
+    ctl->rr[par ^ 1][threadIdx.x] = 0.0;
+  }
+  const int xcd = blockIdx.x & 7, slots = gridDim.x >> 3, slot = blockIdx.x >> 3;
+  const int lo = (int)(((int64_t)m.n_tiles * xcd) >> 3);
+  const int hi = (int)(((int64_t)m.n_tiles * (xcd + 1)) >> 3);
+  int t = lo + slot;
+  if (t >= hi) return;
+  const float* __restrict__ x = A.x1;
+  {
+    // first tile: node ids and values straight into LDS
+    const int n0 = m.tile_node_off[t], nt = m.tile_node_off[t + 1] - n0;
+    for (int j = threadIdx.x; j < nt; j += NT) {
+      const int32_t g = m.tile_nodes[n0 + j];
+      gid[j] = g;
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        xs[3 * j + c] = x[3 * (int64_t)g + c];
+        ys[3 * j + c] = 0.0;
+      }
+    }
+    __syncthreads();
+  }
+  double energy = 0.0;
+  for (;;) {
+    const int tn = t + slots;
+    const bool more = tn < hi;
+    int32_t pg[NPT];
+    float px[NPT][3];
+    int ntn = 0;
+    if (more) {
+      const int n0 = m.tile_node_off[tn];
+      ntn = m.tile_node_off[tn + 1] - n0;
+#pragma unroll
+      for (int q = 0; q < NPT; ++q) {
+        const int j = threadIdx.x + q * NT;
+        pg[q] = j < ntn ? m.tile_nodes[n0 + j] : 0;
+      }
+#pragma unroll
+      for (int q = 0; q < NPT; ++q) {
+        const int64_t g3 = 3 * (int64_t)pg[q];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) px[q][c] = (threadIdx.x + q * NT < ntn) ? x[g3 + c] : 0.0f;
+      }
+    }
+    energy += tile_elements<float, NT, PF>(m, emat, mats, A, t, gid, xs, ys);
+    __syncthreads();
+    tile_scatter<float, NT>(m, A, t, gid, ys);
+    __syncthreads();
+    if (!more) break;
+#pragma unroll
+    for (int q = 0; q < NPT; ++q) {
+      const int j = threadIdx.x + q * NT;
+      if (j < ntn) {
+        gid[j] = pg[q];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          xs[3 * j + c] = px[q][c];
+          ys[3 * j + c] = 0.0;
+        }
+      }
+    }
+    __syncthreads();
+    t = tn;
+  }
+  const double e = block_sum_n<NT>(energy, sh);
+  if (threadIdx.x == 0) atomic_add(&ctl->pAp[blockIdx.x % NSLOT], e);
+}
+
+// Workgroups of the persistent pass: three per compute unit (the LDS and
+// register budget of the FP32 tile pass), a multiple of 8 (one run per XCD).
+static unsigned pipe_grid(int n_tiles) {
+  static int n_cu = 0;
+  if (n_cu == 0) {
+    int dev = 0, v = 0;
+    if (hipGetDevice(&dev) == hipSuccess && hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) ==
+                                                 hipSuccess && v > 0)
+      n_cu = v;
+    else
+      n_cu = 256;
+  }
+  const int per_xcd = std::max(1, std::min((n_tiles + 7) / 8, 3 * n_cu / 8));
+  return (unsigned)(8 * per_xcd);
+}
+
 template <typename T>
 static size_t tile_lds(int max_tile_nodes) {
   const size_t nmax = max_tile_nodes;
   return 3 * nmax * sizeof(double) + (nmax + (nmax & 1)) * sizeof(int32_t) + 3 * nmax * sizeof(T);
 }
 
+constexpr int PIPE_NT = 256, PIPE_NPT = 5;
+static_assert(PIPE_NT * PIPE_NPT >= TILE_MAX_NODES, "the pipelined pass must cover a whole tile");
+
 template <typename T>
 static void launch_tile(const MeshDev& m, const uint8_t* emat, const MatDev* mats, const TileArgs<T>& a, CgCtl* ctl,
                         int iter, hipStream_t s) {
   const size_t lds = tile_lds<T>(m.max_tile_nodes);
+  if constexpr (sizeof(T) == 4) {
+    if (iter >= 0 && a.x2 == nullptr && a.a1 == 1.0f && a.accumulate == 0 && a.vin == nullptr &&
+        m.max_tile_nodes <= PIPE_NT * PIPE_NPT) {
+      hipLaunchKernelGGL((k_tile_pipe<PIPE_NT, PIPE_NPT, SW_PIPE_PF>), dim3(pipe_grid(m.n_tiles)), dim3(PIPE_NT),
+                         lds, s, m, emat, mats, a, ctl, iter);
+      return;
+    }
+  }
   // 4 waves per workgroup (6 measured slower for FP32)
   constexpr int NT = 256;
   hipLaunchKernelGGL((k_tile<T, NT>), dim3(m.n_tiles), dim3(NT), lds, s, m, emat, mats, a, ctl, iter);
