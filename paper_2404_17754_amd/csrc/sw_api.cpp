@@ -215,6 +215,8 @@ struct sw_batch {
   TileLane<double>* d_true = nullptr;
   TileLane<float>* d_cg32 = nullptr;
   int2* d_work = nullptr;
+  int2* d_items = nullptr;  // (lane, tile), tile-major, for the persistent FP32 pass
+  int n_items = 0;
   // host copies
   std::vector<LaneDev> lanes;
   std::vector<LaneState> st;
@@ -1619,7 +1621,21 @@ std::vector<int2> batch_work(sw_case* const* cases, int n) {
   return work;
 }
 
-size_t batch_layout(int n, int n_work, Carver& cv, sw_batch* b) {
+// Items of the persistent FP32 pass: for each mesh, tile by tile, the lanes
+// of that mesh adjacent (they share the tile's mesh data).
+std::vector<int2> batch_items(sw_case* const* cases, int n) {
+  std::vector<int2> items;
+  std::vector<const sw_mesh*> meshes;
+  for (int l = 0; l < n; ++l)
+    if (std::find(meshes.begin(), meshes.end(), cases[l]->mesh) == meshes.end()) meshes.push_back(cases[l]->mesh);
+  for (const sw_mesh* m : meshes)
+    for (int t = 0; t < m->dev.n_tiles; ++t)
+      for (int l = 0; l < n; ++l)
+        if (cases[l]->mesh == m) items.push_back(make_int2(l, t));
+  return items;
+}
+
+size_t batch_layout(int n, int n_work, int n_items, Carver& cv, sw_batch* b) {
   b->d_lanes = cv.take<LaneDev>(n);
   b->d_st = cv.take<LaneState>(n);
   b->d_info = cv.take<LaneInfo>(n);
@@ -1628,6 +1644,7 @@ size_t batch_layout(int n, int n_work, Carver& cv, sw_batch* b) {
   b->d_true = cv.take<TileLane<double>>(n);
   b->d_cg32 = cv.take<TileLane<float>>(n);
   b->d_work = cv.take<int2>(n_work);
+  b->d_items = cv.take<int2>(n_items);
   return cv.off + 256;
 }
 
@@ -1793,7 +1810,7 @@ int batch_step_once(sw_batch* b) {
       for (int k = 0; k < chunk; ++k) {
         const int i = it + k;
         int ev = prof_begin(cx, SW_PROF_TILE_F32);
-        launch_tile_lanes_f32(b->d_cg32, b->d_work, b->n_work, b->max_tile_nodes, b->d_st, i, s);
+        launch_tile_lanes_pipe_f32(b->d_cg32, b->d_items, b->n_items, b->max_tile_nodes, b->d_st, i, s);
         prof_end(cx, ev);
         ev = prof_begin(cx, SW_PROF_UPDATE_F32);
         launch_lanes_cg(true, false, n, b->max_nodes, b->d_lanes, b->d_st, i, s);
@@ -1877,9 +1894,10 @@ extern "C" int sw_batch_workspace_bytes(sw_case* const* cases, int32_t n, size_t
   int rc = batch_check(nullptr, cases, n);
   if (rc) return rc;
   const std::vector<int2> work = batch_work(cases, n);
+  const std::vector<int2> items = batch_items(cases, n);
   sw_batch tmp;
   Carver cv(nullptr);
-  *bytes = batch_layout(n, (int)work.size(), cv, &tmp);
+  *bytes = batch_layout(n, (int)work.size(), (int)items.size(), cv, &tmp);
   return SW_OK;
 }
 
@@ -1889,11 +1907,12 @@ extern "C" int sw_batch_create(sw_ctx* ctx, sw_case* const* cases, int32_t n, vo
   int rc = batch_check(ctx, cases, n);
   if (rc) return rc;
   const std::vector<int2> work = batch_work(cases, n);
+  const std::vector<int2> items = batch_items(cases, n);
   size_t need = 0;
   {
     sw_batch tmp;
     Carver cv(nullptr);
-    need = batch_layout(n, (int)work.size(), cv, &tmp);
+    need = batch_layout(n, (int)work.size(), (int)items.size(), cv, &tmp);
   }
   if (!ws || ws_bytes < need) return fail(SW_ENOWS, "batch workspace needs %zu bytes, got %zu", need, ws_bytes);
   HIPC(hipSetDevice(ctx->device));
@@ -1902,8 +1921,9 @@ extern "C" int sw_batch_create(sw_ctx* ctx, sw_case* const* cases, int32_t n, vo
   b->cases.assign(cases, cases + n);
   b->n = n;
   b->n_work = (int)work.size();
+  b->n_items = (int)items.size();
   Carver cv(ws);
-  batch_layout(n, b->n_work, cv, b);
+  batch_layout(n, b->n_work, b->n_items, cv, b);
   b->lanes.resize(n);
   b->st.assign(n, LaneState{});
   b->info.resize(n);
@@ -1989,6 +2009,7 @@ extern "C" int sw_batch_create(sw_ctx* ctx, sw_case* const* cases, int32_t n, vo
   if (!rc) rc = batch_upload(b, b->d_true, tru.data(), n * sizeof(TileLane<double>));
   if (!rc) rc = batch_upload(b, b->d_cg32, cg32.data(), n * sizeof(TileLane<float>));
   if (!rc) rc = batch_upload(b, b->d_work, work.data(), work.size() * sizeof(int2));
+  if (!rc) rc = batch_upload(b, b->d_items, items.data(), items.size() * sizeof(int2));
   if (!rc && hipStreamSynchronize(ctx->stream) != hipSuccess) rc = fail(SW_EHIP, "batch upload failed");
   if (rc) {
     delete b;

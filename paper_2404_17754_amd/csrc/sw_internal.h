@@ -127,6 +127,11 @@ void launch_tile_lanes_f64(const TileLane<double>* lanes, const int2* work, int 
                            const LaneState* st, int iter, hipStream_t s);
 void launch_tile_lanes_f32(const TileLane<float>* lanes, const int2* work, int n_work, int max_tile_nodes,
                            const LaneState* st, int iter, hipStream_t s);
+// FP32 CG-iteration pass of every lane, persistent and pipelined over items
+// (lane, tile) listed tile-major with a tile's lanes adjacent; tiles of at
+// most 1280 nodes.
+void launch_tile_lanes_pipe_f32(const TileLane<float>* lanes, const int2* items, int n_items, int max_tile_nodes,
+                                const LaneState* st, int iter, hipStream_t s);
 
 // Lane kernels (sw_kernels.hip): one launch covers every lane, grid
 // (blocks per lane, lanes); st == nullptr means every lane.

@@ -388,6 +388,121 @@ __global__ __launch_bounds__(NT) void k_tile_pipe(MeshDev m, const uint8_t* __re
   if (threadIdx.x == 0) atomic_add(&ctl->pAp[blockIdx.x % NSLOT], e);
 }
 
+// The same persistent pipeline over the (lane, tile) items of several cases:
+// items[k] = (lane, tile), tile-major with the lanes of a tile adjacent (they
+// share the tile's mesh data through L2); XCD x owns the contiguous eighth
+// [k_x, k_{x+1}) of the list.  An item is skipped when its lane is inactive or
+// its solve is done (or, on the first iteration, already converged): every
+// workgroup evaluates the same condition, so a skipped lane's output is left
+// untouched; on the first iteration the workgroup whose scan passes the
+// tile-0 item of an already converged lane marks that lane done (every item
+// is visited by exactly one workgroup's scan).  nmax: the largest tile over
+// the lanes (LDS layout).
+
+template <int NT, int NPT>
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(3, 3))) void k_tile_lanes_pipe(const TileLane<float>* __restrict__ lanes,
+                                                         const int2* __restrict__ items, int n_items, int nmax,
+                                                         const LaneState* __restrict__ st, int iter) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  __shared__ double sh[NT / 64];
+  double* ys = reinterpret_cast<double*>(smem_raw);
+  int32_t* gid = reinterpret_cast<int32_t*>(ys + 3 * nmax);
+  float* xs = reinterpret_cast<float*>(gid + nmax + (nmax & 1));
+  const int par = iter & 1;
+  const int xcd = blockIdx.x & 7, slots = gridDim.x >> 3, slot = blockIdx.x >> 3;
+  const int lo = (int)(((int64_t)n_items * xcd) >> 3);
+  const int hi = (int)(((int64_t)n_items * (xcd + 1)) >> 3);
+  // next item at or after k (in steps of slots) that is not skipped (hi if none)
+  auto next_live = [&](int k) {
+    for (; k < hi; k += slots) {
+      const int2 w = items[k];
+      if (st != nullptr && !st[w.x].active) continue;
+      CgCtl* c = lanes[w.x].ctl;
+      if (c->done) continue;
+      if (iter == 0 && slot_sum<NSLOT>(c->rr[0]) <= c->tol2) {
+        if (w.y == 0 && threadIdx.x == 0) c->done = 1;
+        continue;
+      }
+      break;
+    }
+    return k;
+  };
+  int k = next_live(lo + slot);
+  if (k >= hi) return;
+  int2 w = items[k];
+  {
+    const TileLane<float>& L = lanes[w.x];
+    const int n0 = L.m.tile_node_off[w.y], nt = L.m.tile_node_off[w.y + 1] - n0;
+    const float* __restrict__ x = L.A.x1;
+    for (int j = threadIdx.x; j < nt; j += NT) {
+      const int32_t g = L.m.tile_nodes[n0 + j];
+      gid[j] = g;
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        xs[3 * j + c] = x[3 * (int64_t)g + c];
+        ys[3 * j + c] = 0.0;
+      }
+    }
+    __syncthreads();
+  }
+  for (;;) {
+    const TileLane<float>& L = lanes[w.x];
+    const int t = w.y;
+    // lane duties of the tile-0 item: clear the slots the next update kernel
+    // accumulates into
+    if (t == 0 && threadIdx.x < NSLOT) {
+      L.ctl->rz[par ^ 1][threadIdx.x] = 0.0;
+      L.ctl->rr[par ^ 1][threadIdx.x] = 0.0;
+    }
+    const int kn = next_live(k + slots);
+    const bool more = kn < hi;
+    int2 wn = make_int2(0, 0);
+    int32_t pg[NPT];
+    float px[NPT][3];
+    int ntn = 0;
+    if (more) {
+      wn = items[kn];
+      const TileLane<float>& Ln = lanes[wn.x];
+      const int n0 = Ln.m.tile_node_off[wn.y];
+      ntn = Ln.m.tile_node_off[wn.y + 1] - n0;
+      const float* __restrict__ xn = Ln.A.x1;
+#pragma unroll
+      for (int q = 0; q < NPT; ++q) {
+        const int j = threadIdx.x + q * NT;
+        pg[q] = j < ntn ? Ln.m.tile_nodes[n0 + j] : 0;
+      }
+#pragma unroll
+      for (int q = 0; q < NPT; ++q) {
+        const int64_t g3 = 3 * (int64_t)pg[q];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) px[q][c] = (threadIdx.x + q * NT < ntn) ? xn[g3 + c] : 0.0f;
+      }
+    }
+    const double energy = tile_elements<float, NT, false>(L.m, L.emat, L.mats, L.A, t, gid, xs, ys);
+    __syncthreads();
+    tile_scatter<float, NT>(L.m, L.A, t, gid, ys);
+    const double e = block_sum_n<NT>(energy, sh);
+    if (threadIdx.x == 0) atomic_add(&L.ctl->pAp[t % NSLOT], e);
+    __syncthreads();
+    if (!more) break;
+#pragma unroll
+    for (int q = 0; q < NPT; ++q) {
+      const int j = threadIdx.x + q * NT;
+      if (j < ntn) {
+        gid[j] = pg[q];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          xs[3 * j + c] = px[q][c];
+          ys[3 * j + c] = 0.0;
+        }
+      }
+    }
+    __syncthreads();
+    k = kn;
+    w = wn;
+  }
+}
+
 // Workgroups of the persistent pass: three per compute unit (the LDS and
 // register budget of the FP32 tile pass), a multiple of 8 (one run per XCD).
 static unsigned pipe_grid(int n_tiles) {
@@ -443,6 +558,11 @@ void launch_tile_lanes_f64(const TileLane<double>* lanes, const int2* work, int 
                            const LaneState* st, int iter, hipStream_t s) {
   hipLaunchKernelGGL((k_tile_lanes<double, 256>), dim3(n_work), dim3(256), tile_lds<double>(max_tile_nodes), s, lanes,
                      work, st, iter);
+}
+void launch_tile_lanes_pipe_f32(const TileLane<float>* lanes, const int2* items, int n_items, int max_tile_nodes,
+                                const LaneState* st, int iter, hipStream_t s) {
+  hipLaunchKernelGGL((k_tile_lanes_pipe<PIPE_NT, PIPE_NPT>), dim3(pipe_grid(n_items)), dim3(PIPE_NT),
+                     tile_lds<float>(max_tile_nodes), s, lanes, items, n_items, max_tile_nodes, st, iter);
 }
 void launch_tile_lanes_f32(const TileLane<float>* lanes, const int2* work, int n_work, int max_tile_nodes,
                            const LaneState* st, int iter, hipStream_t s) {
