@@ -156,8 +156,8 @@ struct sw_case {
   double* vin;
   double *u, *v, *a, *b, *x, *r, *z, *p, *q;
   double* hist;  // [4][n_dof]
-  double *diag6, *pinv64;
-  float* pinv32;
+  double *diag6, *pinv64, *pmax;
+  __half* pinv16;  // block-Jacobi inverse / its largest diagonal entry, FP16 (FP32 CG)
   float *r32, *d32, *z32, *p32, *q32;
   double* wave;
   int32_t* log_it;
@@ -407,6 +407,7 @@ size_t mesh_layout(const HostLayout& L, Carver& cv, MeshDev* md) {
     md->n_faces = L.n_faces;
     md->n_tiles = nT;
     md->max_tile_nodes = L.max_tile_nodes;
+    md->n_interior = L.n_interior;
     md->tet_stride = L.tet_stride;
     md->face_stride = L.face_stride;
     md->conn_loc = conn_loc;
@@ -503,7 +504,8 @@ static size_t case_layout(const sw_mesh* m, const sw_case_desc* d, Carver& cv, s
   auto hist = cv.take<double>(4 * nd);
   auto diag6 = cv.take<double>(6 * nn);
   auto pinv64 = cv.take<double>(6 * nn);
-  auto pinv32 = cv.take<float>(6 * nn);
+  auto pinv16 = cv.take<__half>(6 * nn);
+  auto pmax = cv.take<double>(1);
   float* f32[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
   if (mixed)
     for (int i = 0; i < 5; ++i) f32[i] = cv.take<float>(nd);
@@ -545,7 +547,8 @@ static size_t case_layout(const sw_mesh* m, const sw_case_desc* d, Carver& cv, s
     c->hist = hist;
     c->diag6 = diag6;
     c->pinv64 = pinv64;
-    c->pinv32 = pinv32;
+    c->pinv16 = pinv16;
+    c->pmax = pmax;
     c->r32 = f32[0];
     c->d32 = f32[1];
     c->z32 = f32[2];
@@ -764,7 +767,7 @@ extern "C" int sw_case_create(sw_ctx* ctx, sw_mesh* m, const sw_case_desc* d, vo
   launch_fill_f64(6 * nn, c->diag6, 0.0, s);
   HIPX(hipMemsetAsync(c->bad, 0, 4, s));
   launch_tile_diag(m->dev, c->emat, c->mats, c->cM, c->cK, c->cC, c->diag6, s);
-  launch_invert_blocks(nn, c->diag6, c->pinv64, c->pinv32, c->bad, s);
+  launch_invert_blocks(nn, c->diag6, c->pinv64, c->pinv16, c->pmax, c->bad, s);
   HIPX(hipGetLastError());
   int32_t bad = 0;
   HIPX(hipMemcpyAsync(&bad, c->bad, 4, hipMemcpyDeviceToHost, s));
@@ -879,7 +882,8 @@ int cg_loop(sw_case* c, CgCtl* ctl, int iter_base, int first_chunk, int* iters_o
         prof_end(cx, ev);
         if (rc) return rc;
         ev = prof_begin(cx, SW_PROF_UPDATE_F32);
-        launch_cg_update_f32(nn, i & 1, c->pinv32, c->d32, c->r32, c->z32, c->p32, c->q32, ctl, s);
+        launch_cg_update_f32(nn, c->mesh->dev.n_interior, i & 1, c->pinv16, c->d32, c->r32, c->z32, c->p32, c->q32,
+                             ctl, s);
         prof_end(cx, ev);
         ev = prof_begin(cx, SW_PROF_DIR_F32);
         launch_cg_dir_f32(nn, i & 1, iter_base + i, c->max_iter, c->z32, c->p32, ctl, s);
@@ -1205,7 +1209,7 @@ int solve_step(sw_case* c, int* iters, int* outer, double* relres, int* flags) {
       launch_fill_f64(1, &c->ctl32->bb, 1.0, s);
       launch_ctl_prepare(c->ctl32, tol, s);
       launch_fill_f32(nd, c->d32, 0.0f, s);
-      launch_cg_init_f32(nn, c->r32, nullptr, c->pinv32, c->r32, c->z32, c->p32, nullptr, c->ctl32, s);
+      launch_cg_init_f32(nn, c->r32, nullptr, c->pinv16, c->r32, c->z32, c->p32, nullptr, c->ctl32, s);
       LAUNCHED();
       int it = 0;
       rc = cg_loop<true>(c, c->ctl32, *iters, inner_est - 1, &it);
@@ -1949,7 +1953,8 @@ extern "C" int sw_batch_create(sw_ctx* ctx, sw_case* const* cases, int32_t n, vo
     L.q = c->q;
     L.hist = c->hist;
     L.pinv64 = c->pinv64;
-    L.pinv32 = c->pinv32;
+    L.pinv16 = c->pinv16;
+    L.n_interior = c->mesh->dev.n_interior;
     L.r32 = c->r32;
     L.d32 = c->d32;
     L.z32 = c->z32;

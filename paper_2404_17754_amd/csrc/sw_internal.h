@@ -2,6 +2,7 @@
 // (sw_kernels.hip).  Not part of the C-ABI.
 #pragma once
 
+#include <hip/hip_fp16.h>
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -36,6 +37,7 @@ struct CgCtl {
 // sw_layout.h).
 struct MeshDev {
   int64_t n_nodes, n_tets, n_faces;
+  int64_t n_interior;            // nodes [0, n_interior) belong to one tile each
   int32_t n_tiles, max_tile_nodes;
   int64_t tet_stride, face_stride;
   const uint16_t* conn_loc;      // [10][tet_stride]
@@ -88,11 +90,12 @@ struct TileLane {
 // One lane's vectors and per-step values (internal node order of its mesh).
 struct LaneDev {
   int64_t n_nodes;
+  int64_t n_interior;       // q is cleared only past the interior nodes
   double dt;
   double *u, *v, *a, *b, *x, *r, *z, *p, *q;
   double* hist;             // [4][3 n_nodes] increments, ring
   const double* pinv64;
-  const float* pinv32;
+  const __half* pinv16;
   float *r32, *d32, *z32, *p32, *q32;
   CgCtl *ctl64, *ctl32;
   const int32_t* rec;
@@ -167,18 +170,23 @@ void launch_geom32(const MeshDev& m, float* geo32, hipStream_t s);
 // Diagonal 3x3 blocks (6 values per node) of cM M + cK K + cC C_abs.
 void launch_tile_diag(const MeshDev& m, const uint8_t* emat, const MatDev* mats, double cM, double cK, double cC,
                       double* diag6, hipStream_t s);
-void launch_invert_blocks(int64_t n_nodes, const double* diag6, double* pinv64, float* pinv32, int* bad,
-                          hipStream_t s);
+// pinv64 = inverse blocks; pinv16 = the same divided by their largest
+// diagonal entry (pmax, one double of scratch), in FP16 for the FP32 CG (a
+// constant factor on the preconditioner leaves the CG iterates unchanged)
+void launch_invert_blocks(int64_t n_nodes, const double* diag6, double* pinv64, __half* pinv16, double* pmax,
+                          int* bad, hipStream_t s);
 
 // CG vector kernels (node-parallel), T = double or float vectors
 void launch_cg_init_f64(int64_t n_nodes, const double* b, const double* q, const double* pinv, double* r, double* z,
                         double* p, double* qz, CgCtl* ctl, hipStream_t s);
-void launch_cg_init_f32(int64_t n_nodes, const float* b, const float* q, const float* pinv, float* r, float* z,
+void launch_cg_init_f32(int64_t n_nodes, const float* b, const float* q, const __half* pinv, float* r, float* z,
                         float* p, float* qz, CgCtl* ctl, hipStream_t s);
 void launch_cg_update_f64(int64_t n_nodes, int par, const double* pinv, double* x, double* r, double* z,
                           const double* p, double* q, CgCtl* ctl, hipStream_t s);
-void launch_cg_update_f32(int64_t n_nodes, int par, const float* pinv, float* x, float* r, float* z,
-                          const float* p, float* q, CgCtl* ctl, hipStream_t s);
+// q is cleared only for nodes >= n_interior (the next operator pass
+// overwrites interior nodes)
+void launch_cg_update_f32(int64_t n_nodes, int64_t n_interior, int par, const __half* pinv, float* x, float* r,
+                          float* z, const float* p, float* q, CgCtl* ctl, hipStream_t s);
 void launch_cg_dir_f64(int64_t n_nodes, int par, int iter_abs, int max_iter, const double* z, double* p,
                        CgCtl* ctl, hipStream_t s);
 void launch_cg_dir_f32(int64_t n_nodes, int par, int iter_abs, int max_iter, const float* z, float* p,

@@ -16,10 +16,36 @@ namespace sw {
 
 // --------------------------------------------------------- CG vector ops
 
-template <typename T>
-__device__ __forceinline__ void bj_apply(const T* __restrict__ P, int64_t i, const T r[3], T z[3]) {
-  const T a = P[6 * i + 0], b = P[6 * i + 1], c = P[6 * i + 2];
-  const T yz = P[6 * i + 3], xz = P[6 * i + 4], xy = P[6 * i + 5];
+__device__ __forceinline__ float to_t(__half v, float) { return __half2float(v); }
+__device__ __forceinline__ float to_t(float v, float) { return v; }
+__device__ __forceinline__ double to_t(double v, double) { return v; }
+
+// the six values (xx yy zz yz xz xy) of node i's block
+template <typename T, typename PT>
+__device__ __forceinline__ void bj_load(const PT* __restrict__ P, int64_t i, T v[6]) {
+#pragma unroll
+  for (int k = 0; k < 6; ++k) v[k] = to_t(P[6 * i + k], T());
+}
+// FP16 blocks: three 32-bit loads of two values each (12-byte records are
+// 4-byte aligned)
+template <>
+__device__ __forceinline__ void bj_load<float, __half>(const __half* __restrict__ P, int64_t i, float v[6]) {
+  const __half2* P2 = reinterpret_cast<const __half2*>(P) + 3 * i;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    const float2 f = __half22float2(P2[k]);
+    v[2 * k] = f.x;
+    v[2 * k + 1] = f.y;
+  }
+}
+
+// z = P r for the symmetric 3x3 block of node i (xx yy zz yz xz xy), stored
+// in PT, applied in T
+template <typename T, typename PT>
+__device__ __forceinline__ void bj_apply(const PT* __restrict__ P, int64_t i, const T r[3], T z[3]) {
+  T v[6];
+  bj_load<T, PT>(P, i, v);
+  const T a = v[0], b = v[1], c = v[2], yz = v[3], xz = v[4], xy = v[5];
   z[0] = a * r[0] + xy * r[1] + xz * r[2];
   z[1] = xy * r[0] + b * r[1] + yz * r[2];
   z[2] = xz * r[0] + yz * r[1] + c * r[2];
@@ -33,9 +59,9 @@ static inline unsigned vgrid(int64_t n) {
 }
 
 // r = b - q, z = P r, p = z, q = 0; rz[0], rr[0]
-template <typename T>
+template <typename T, typename PT>
 __device__ __forceinline__ void cg_init_body(int64_t n, const T* __restrict__ b, const T* __restrict__ q,
-                                             const T* __restrict__ P, T* __restrict__ r, T* __restrict__ z,
+                                             const PT* __restrict__ P, T* __restrict__ r, T* __restrict__ z,
                                              T* __restrict__ p, T* __restrict__ qz, CgCtl* ctl) {
   __shared__ double sh[2 * TPB / 64];
   double rz = 0.0, rr = 0.0;
@@ -43,7 +69,7 @@ __device__ __forceinline__ void cg_init_body(int64_t n, const T* __restrict__ b,
     T rv[3], zv[3];
 #pragma unroll
     for (int c = 0; c < 3; ++c) rv[c] = b[3 * i + c] - (q ? q[3 * i + c] : (T)0);
-    bj_apply<T>(P, i, rv, zv);
+    bj_apply<T, PT>(P, i, rv, zv);
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
       r[3 * i + c] = rv[c];
@@ -63,28 +89,42 @@ __device__ __forceinline__ void cg_init_body(int64_t n, const T* __restrict__ b,
 
 // alpha = rz[par] / pAp; x += alpha p; r -= alpha q; z = P r; q = 0;
 // rz[par^1] += r.z, rr[par^1] += r.r
-template <typename T>
-__device__ __forceinline__ void cg_update_body(int64_t n, int par, const T* __restrict__ P, T* __restrict__ x,
-                                               T* __restrict__ r, T* __restrict__ z, const T* __restrict__ p,
-                                               T* __restrict__ q, CgCtl* ctl) {
+template <typename T, typename PT>
+__device__ __forceinline__ void cg_update_body(int64_t n, int64_t n_int, int par, const PT* __restrict__ P,
+                                               T* __restrict__ x, T* __restrict__ r, T* __restrict__ z,
+                                               const T* __restrict__ p, T* __restrict__ q, CgCtl* ctl) {
   __shared__ double sh[2 * TPB / 64];
   if (ctl->done) return;
   const T alpha = (T)(slot_sum<NSLOT>(ctl->rz[par]) / slot_sum<NSLOT>(ctl->pAp));
   double rz = 0.0, rr = 0.0;
   for (int64_t i = (int64_t)blockIdx.x * TPB + threadIdx.x; i < n; i += (int64_t)gridDim.x * TPB) {
-    T rv[3], zv[3];
+    // every load of the node first (12-byte accesses), then the stores
+    T xv[3], pv[3], rv[3], qv[3], zv[3];
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
-      const int64_t k = 3 * i + c;
-      x[k] += alpha * p[k];
-      rv[c] = r[k] - alpha * q[k];
-      q[k] = (T)0;
+      xv[c] = x[3 * i + c];
+      pv[c] = p[3 * i + c];
+      rv[c] = r[3 * i + c];
+      qv[c] = q[3 * i + c];
     }
-    bj_apply<T>(P, i, rv, zv);
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
-      r[3 * i + c] = rv[c];
-      z[3 * i + c] = zv[c];
+      xv[c] += alpha * pv[c];
+      rv[c] -= alpha * qv[c];
+    }
+    bj_apply<T, PT>(P, i, rv, zv);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) x[3 * i + c] = xv[c];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) r[3 * i + c] = rv[c];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) z[3 * i + c] = zv[c];
+    if (i >= n_int) {
+#pragma unroll
+      for (int c = 0; c < 3; ++c) q[3 * i + c] = (T)0;
+    }
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
       rz += (double)rv[c] * (double)zv[c];
       rr += (double)rv[c] * (double)rv[c];
     }
@@ -113,20 +153,26 @@ __device__ __forceinline__ void cg_dir_body(int64_t n, int par, int iter_abs, in
   }
   if (stop) return;
   for (int64_t i = (int64_t)blockIdx.x * TPB + threadIdx.x; i < n; i += (int64_t)gridDim.x * TPB) {
+    T zv[3], pv[3];
 #pragma unroll
-    for (int c = 0; c < 3; ++c) p[3 * i + c] = z[3 * i + c] + beta * p[3 * i + c];
+    for (int c = 0; c < 3; ++c) {
+      zv[c] = z[3 * i + c];
+      pv[c] = p[3 * i + c];
+    }
+#pragma unroll
+    for (int c = 0; c < 3; ++c) p[3 * i + c] = zv[c] + beta * pv[c];
   }
 }
 
-template <typename T>
-__global__ __launch_bounds__(TPB) void k_cg_init(int64_t n, const T* b, const T* q, const T* P, T* r, T* z, T* p,
+template <typename T, typename PT>
+__global__ __launch_bounds__(TPB) void k_cg_init(int64_t n, const T* b, const T* q, const PT* P, T* r, T* z, T* p,
                                                  T* qz, CgCtl* ctl) {
-  cg_init_body<T>(n, b, q, P, r, z, p, qz, ctl);
+  cg_init_body<T, PT>(n, b, q, P, r, z, p, qz, ctl);
 }
-template <typename T>
-__global__ __launch_bounds__(TPB) void k_cg_update(int64_t n, int par, const T* P, T* x, T* r, T* z, const T* p,
-                                                   T* q, CgCtl* ctl) {
-  cg_update_body<T>(n, par, P, x, r, z, p, q, ctl);
+template <typename T, typename PT>
+__global__ __launch_bounds__(TPB) void k_cg_update(int64_t n, int64_t n_int, int par, const PT* P, T* x, T* r, T* z,
+                                                   const T* p, T* q, CgCtl* ctl) {
+  cg_update_body<T, PT>(n, n_int, par, P, x, r, z, p, q, ctl);
 }
 template <typename T>
 __global__ __launch_bounds__(TPB) void k_cg_dir(int64_t n, int par, int iter_abs, int max_iter, const T* z, T* p,
@@ -136,19 +182,21 @@ __global__ __launch_bounds__(TPB) void k_cg_dir(int64_t n, int par, int iter_abs
 
 void launch_cg_init_f64(int64_t n, const double* b, const double* q, const double* P, double* r, double* z, double* p,
                         double* qz, CgCtl* ctl, hipStream_t s) {
-  hipLaunchKernelGGL(k_cg_init<double>, dim3(vgrid(n)), dim3(TPB), 0, s, n, b, q, P, r, z, p, qz, ctl);
+  hipLaunchKernelGGL((k_cg_init<double, double>), dim3(vgrid(n)), dim3(TPB), 0, s, n, b, q, P, r, z, p, qz, ctl);
 }
-void launch_cg_init_f32(int64_t n, const float* b, const float* q, const float* P, float* r, float* z, float* p,
+void launch_cg_init_f32(int64_t n, const float* b, const float* q, const __half* P, float* r, float* z, float* p,
                         float* qz, CgCtl* ctl, hipStream_t s) {
-  hipLaunchKernelGGL(k_cg_init<float>, dim3(vgrid(n)), dim3(TPB), 0, s, n, b, q, P, r, z, p, qz, ctl);
+  hipLaunchKernelGGL((k_cg_init<float, __half>), dim3(vgrid(n)), dim3(TPB), 0, s, n, b, q, P, r, z, p, qz, ctl);
 }
 void launch_cg_update_f64(int64_t n, int par, const double* P, double* x, double* r, double* z, const double* p,
                           double* q, CgCtl* ctl, hipStream_t s) {
-  hipLaunchKernelGGL(k_cg_update<double>, dim3(vgrid(n)), dim3(TPB), 0, s, n, par, P, x, r, z, p, q, ctl);
+  hipLaunchKernelGGL((k_cg_update<double, double>), dim3(vgrid(n)), dim3(TPB), 0, s, n, (int64_t)0, par, P, x, r,
+                     z, p, q, ctl);
 }
-void launch_cg_update_f32(int64_t n, int par, const float* P, float* x, float* r, float* z, const float* p, float* q,
-                          CgCtl* ctl, hipStream_t s) {
-  hipLaunchKernelGGL(k_cg_update<float>, dim3(vgrid(n)), dim3(TPB), 0, s, n, par, P, x, r, z, p, q, ctl);
+void launch_cg_update_f32(int64_t n, int64_t n_int, int par, const __half* P, float* x, float* r, float* z,
+                          const float* p, float* q, CgCtl* ctl, hipStream_t s) {
+  hipLaunchKernelGGL((k_cg_update<float, __half>), dim3(vgrid(n)), dim3(TPB), 0, s, n, n_int, par, P, x, r, z, p,
+                     q, ctl);
 }
 void launch_cg_dir_f64(int64_t n, int par, int iter_abs, int max_iter, const double* z, double* p, CgCtl* ctl,
                        hipStream_t s) {
@@ -474,9 +522,9 @@ __global__ __launch_bounds__(TPB) void k_lane_op(const LaneDev* __restrict__ lan
       L.d32[i] = 0.0f;
     }
   } else if constexpr (OP == LANE_CG_INIT32) {
-    cg_init_body<float>(nn, L.r32, nullptr, L.pinv32, L.r32, L.z32, L.p32, nullptr, L.ctl32);
+    cg_init_body<float, __half>(nn, L.r32, nullptr, L.pinv16, L.r32, L.z32, L.p32, nullptr, L.ctl32);
   } else if constexpr (OP == LANE_CG_INIT64) {
-    cg_init_body<double>(nn, L.b, L.q, L.pinv64, L.r, L.z, L.p, L.q, L.ctl64);
+    cg_init_body<double, double>(nn, L.b, L.q, L.pinv64, L.r, L.z, L.p, L.q, L.ctl64);
   } else if constexpr (OP == LANE_IR_UPDATE) {
     const double sc = L.ctl64->scale;
     for (int64_t i = i0; i < nd; i += stride) L.x[i] += sc * (double)L.d32[i];
@@ -519,12 +567,13 @@ __global__ __launch_bounds__(TPB) void k_lane_cg(const LaneDev* __restrict__ lan
     if constexpr (DIR)
       cg_dir_body<float>(L.n_nodes, par, st[l].iter_base + iter, L.max_iter, L.z32, L.p32, L.ctl32);
     else
-      cg_update_body<float>(L.n_nodes, par, L.pinv32, L.d32, L.r32, L.z32, L.p32, L.q32, L.ctl32);
+      cg_update_body<float, __half>(L.n_nodes, L.n_interior, par, L.pinv16, L.d32, L.r32, L.z32, L.p32, L.q32,
+                                    L.ctl32);
   } else {
     if constexpr (DIR)
       cg_dir_body<double>(L.n_nodes, par, st[l].iter_base + iter, L.max_iter, L.z, L.p, L.ctl64);
     else
-      cg_update_body<double>(L.n_nodes, par, L.pinv64, L.x, L.r, L.z, L.p, L.q, L.ctl64);
+      cg_update_body<double, double>(L.n_nodes, 0, par, L.pinv64, L.x, L.r, L.z, L.p, L.q, L.ctl64);
   }
 }
 

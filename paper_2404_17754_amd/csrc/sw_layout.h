@@ -21,6 +21,7 @@ struct HostLayout {
   int64_t n_nodes = 0, n_tets = 0, n_faces = 0;
   int32_t n_tiles = 0;
   int32_t max_tile_nodes = 0;
+  int64_t n_interior = 0;              // nodes [0, n_interior) are interior to one tile
   int64_t tet_stride = 0, face_stride = 0;
   std::vector<int32_t> elem_order;     // internal element i = user element elem_order[i]
   std::vector<int32_t> elem_u2i;       // user element -> internal

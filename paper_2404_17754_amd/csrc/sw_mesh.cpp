@@ -5,10 +5,12 @@
 // 2. Consecutive elements form tiles, closed when the next element would
 //    exceed TILE_MAX_NODES distinct nodes or TILE_MAX_ELEMS elements, so a
 //    tile's node values and accumulators fit in one workgroup's LDS.
-// 3. Nodes are renumbered tile by tile: first the tile's interior nodes
-//    (touched by no other tile), then the shared nodes it touches first.  A
-//    tile's interior nodes are thus one contiguous id range (plain coalesced
-//    stores); only shared nodes need atomics, and those are sorted.
+// 3. Nodes are renumbered: every tile's interior nodes (touched by no other
+//    tile), tile by tile, then all shared nodes in the order tiles first
+//    touch them.  A tile's interior nodes are thus one contiguous id range
+//    (plain coalesced stores, and overwritten by every pass, so never
+//    cleared); only shared nodes, one range at the end, need atomics and
+//    clearing.
 // 4. Inside a tile, elements are interleaved (stride S along the curve) so
 //    that the elements of one wavefront rarely share nodes.
 // 5. Element connectivity is stored as 16-bit indices into the tile's node
@@ -125,14 +127,16 @@ void build_layout(int64_t n_nodes, int64_t n_tets, int64_t n_faces, const double
         }
       }
     }
-  // --- node renumbering: per tile, interior nodes then first-touched shared nodes
+  // --- node renumbering: every tile's interior nodes, tile by tile (one
+  // contiguous range per tile), then all shared nodes in the order tiles
+  // first touch them (one contiguous range at the end)
   L.node_u2i.assign(n_nodes, -1);
   int32_t next = 0;
   L.tile_int_base.resize(n_tiles);
   L.tile_nint.resize(n_tiles);
-  for (int32_t t = 0; t < n_tiles; ++t) {
-    L.tile_int_base[t] = next;
-    for (int pass = 0; pass < 2; ++pass) {
+  for (int pass = 0; pass < 2; ++pass) {
+    for (int32_t t = 0; t < n_tiles; ++t) {
+      if (pass == 0) L.tile_int_base[t] = next;
       for (int32_t i = L.tile_elem_off[t]; i < L.tile_elem_off[t + 1]; ++i) {
         const int32_t e = L.elem_order[i];
         for (int k = 0; k < 10; ++k) {
@@ -143,6 +147,7 @@ void build_layout(int64_t n_nodes, int64_t n_tets, int64_t n_faces, const double
       }
       if (pass == 0) L.tile_nint[t] = next - L.tile_int_base[t];
     }
+    if (pass == 0) L.n_interior = next;
   }
   for (int64_t n = 0; n < n_nodes; ++n)
     if (L.node_u2i[n] < 0) L.node_u2i[n] = next++;  // nodes of no element

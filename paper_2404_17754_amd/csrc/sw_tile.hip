@@ -666,27 +666,52 @@ void launch_tile_diag(const MeshDev& m, const uint8_t* emat, const MatDev* mats,
 
 // Inverse of each symmetric 3x3 block [[a xy xz][xy b yz][xz yz c]] by
 // cofactors, in FP64; FP32 copy for the mixed-precision inner solve.
+__global__ void k_fill_zero_d(double* p) { *p = 0.0; }
+
 __global__ __launch_bounds__(TPB) void k_invert(int64_t n, const double* __restrict__ d6, double* __restrict__ p64,
-                                                float* __restrict__ p32, int* bad) {
+                                                double* pmax, int* bad) {
+  __shared__ double sh[TPB / 64];
   const int64_t i = (int64_t)blockIdx.x * TPB + threadIdx.x;
-  if (i >= n) return;
-  const double a = d6[6 * i + 0], b = d6[6 * i + 1], c = d6[6 * i + 2];
-  const double yz = d6[6 * i + 3], xz = d6[6 * i + 4], xy = d6[6 * i + 5];
-  const double c00 = b * c - yz * yz, c11 = a * c - xz * xz, c22 = a * b - xy * xy;
-  const double c12 = -(a * yz - xy * xz), c02 = xy * yz - b * xz, c01 = -(xy * c - yz * xz);
-  const double det = a * c00 + xy * c01 + xz * c02;
-  if (!(det > 0.0) || !(a > 0.0)) *bad = 1;
-  const double id = 1.0 / det;
-  const double r[6] = {c00 * id, c11 * id, c22 * id, c12 * id, c02 * id, c01 * id};
-  for (int k = 0; k < 6; ++k) {
-    p64[6 * i + k] = r[k];
-    p32[6 * i + k] = (float)r[k];
+  double mx = 0.0;
+  if (i < n) {
+    const double a = d6[6 * i + 0], b = d6[6 * i + 1], c = d6[6 * i + 2];
+    const double yz = d6[6 * i + 3], xz = d6[6 * i + 4], xy = d6[6 * i + 5];
+    const double c00 = b * c - yz * yz, c11 = a * c - xz * xz, c22 = a * b - xy * xy;
+    const double c12 = -(a * yz - xy * xz), c02 = xy * yz - b * xz, c01 = -(xy * c - yz * xz);
+    const double det = a * c00 + xy * c01 + xz * c02;
+    if (!(det > 0.0) || !(a > 0.0)) *bad = 1;
+    const double id = 1.0 / det;
+    const double r[6] = {c00 * id, c11 * id, c22 * id, c12 * id, c02 * id, c01 * id};
+    for (int k = 0; k < 6; ++k) p64[6 * i + k] = r[k];
+    mx = fmax(fmax(r[0], r[1]), r[2]);
+    if (!(mx > 0.0)) mx = 0.0;
+  }
+  // largest diagonal entry: positive doubles order like their bit patterns
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) mx = fmax(mx, __shfl_xor(mx, off, 64));
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = mx;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int w = 1; w < TPB / 64; ++w) mx = fmax(mx, sh[w]);
+    mx = fmax(mx, sh[0]);
+    atomicMax(reinterpret_cast<unsigned long long*>(pmax), (unsigned long long)__double_as_longlong(mx));
   }
 }
 
-void launch_invert_blocks(int64_t n_nodes, const double* diag6, double* pinv64, float* pinv32, int* bad,
-                          hipStream_t s) {
-  hipLaunchKernelGGL(k_invert, dim3(nblocks(n_nodes)), dim3(TPB), 0, s, n_nodes, diag6, pinv64, pinv32, bad);
+__global__ __launch_bounds__(TPB) void k_to_half(int64_t n6, const double* __restrict__ p64,
+                                                 const double* __restrict__ pmax, __half* __restrict__ p16) {
+  const double s = *pmax > 0.0 ? 1.0 / *pmax : 0.0;
+  for (int64_t k = (int64_t)blockIdx.x * TPB + threadIdx.x; k < n6; k += (int64_t)gridDim.x * TPB)
+    p16[k] = __float2half((float)(p64[k] * s));
+}
+
+void launch_invert_blocks(int64_t n_nodes, const double* diag6, double* pinv64, __half* pinv16, double* pmax,
+                          int* bad, hipStream_t s) {
+  hipLaunchKernelGGL(k_fill_zero_d, dim3(1), dim3(1), 0, s, pmax);
+  hipLaunchKernelGGL(k_invert, dim3(nblocks(n_nodes)), dim3(TPB), 0, s, n_nodes, diag6, pinv64, pmax, bad);
+  unsigned g = nblocks(6 * n_nodes);
+  if (g > 8192) g = 8192;
+  hipLaunchKernelGGL(k_to_half, dim3(g), dim3(TPB), 0, s, 6 * n_nodes, pinv64, pmax, pinv16);
 }
 
 }  // namespace sw
