@@ -44,7 +44,7 @@ def trace(db, out, command, top=16):
                      f"{100.0 * tot / total:6.1f}")
     lines.append(f"(total kernel time {total / 1e6:.1f} ms over {sum(r[1] for r in rows)} dispatches)")
     # full launches of the tile kernels (early exits after convergence left out)
-    for pat in ("k_tile<float", "k_tile<double"):
+    for pat in ("k_tile_pipe<", "k_tile_lanes_pipe<", "k_tile<float", "k_tile<double"):
         d = [r[0] for r in con.execute("select end - start from kernels where name like ?", (f"%{pat}%",))]
         if d:
             mx = max(d)
