@@ -272,6 +272,29 @@ def incident_velocity(n_steps, dt, freqs, t0, direction=0):
     return v
 
 
+def hann_impulse(n_steps, stride):
+    """Unit impulse p of the input parametrisation, sampled at the time
+    steps n = 0..n_steps: a Hann pulse sin^2(pi n / (2 stride)) on
+    0 <= n <= 2 stride (peak 1 at n = stride), zero elsewhere.  Copies
+    shifted by multiples of the stride sum to one (partition of unity)."""
+    n = np.arange(n_steps + 1, dtype=float)
+    p = np.sin(np.pi * n / (2.0 * stride)) ** 2
+    p[n > 2 * stride] = 0.0
+    return p
+
+
+def impulse_inputs(n_steps, stride):
+    """The three inputs of the Green's-function runs: the unit impulse along
+    x1, x2 and x3 ((n_steps + 1) x 3 each)."""
+    p = hann_impulse(n_steps, stride)
+    out = []
+    for j in range(3):
+        v = np.zeros((n_steps + 1, 3))
+        v[:, j] = p
+        out.append(v)
+    return out
+
+
 def rayleigh_coefficients(xi, f1, f2):
     """Mass/stiffness-proportional coefficients giving damping ratio xi at
     frequencies f1 and f2 (Hz)."""
