@@ -294,6 +294,37 @@ SW_API int sw_case_set_sampler(sw_case* c, float* dev_buf, int64_t capacity, int
 /* Rows recorded so far (at most the capacity). */
 SW_API int sw_case_samples(const sw_case* c, int64_t* rows);
 
+/* ------------------------------------------------------ input estimation */
+
+/* The misfit of a candidate model with the input estimated (Section 2):
+ * the input velocity along j is sum_l c_jl p(t - l dT), shifted copies of a
+ * unit impulse p, and the response at the receivers is
+ *     U_i^k(t) = sum_{j,l} G_ij^k(t - l dT) c_jl
+ * with G_j the Green's records, i.e. the receiver velocities of three runs
+ * of the model driven by p along x1, x2 and x3 (for instance the
+ * waveforms of three cases whose v_in is p along one direction; the model
+ * starts from rest, so a delayed impulse gives the delayed record).  The
+ * coefficients minimise sum_{k,i} |U_i^k - obs_i^k|^2 / |obs_i^k|^2 (the
+ * squares of the terms of ERR; silent pairs, norm <= 1e-12 of the largest,
+ * carry no weight): the normal equations A c = b are formed on the GPU from
+ * block inner products of the records and solved on the host with the
+ * eigen-decomposition of the symmetric A, eigenvalues at or below
+ * rel_cut times the largest discarded (the pseudo-inverse of Section 2).
+ * ERR (Eq. eqerr) is then evaluated at that c.
+ *
+ * green: host array of 3 device pointers, records [n_steps][n_rec][3]
+ * (FP64, step 1..n_steps); obs: device, same layout; stride: dT in time
+ * steps (n_steps must be a multiple); n_shift: shifts l = 0..n_shift-1
+ * (<= n_steps / stride, <= 128); ws: device workspace of
+ * sw_fit_workspace_bytes, 256-byte aligned.  Outputs: c_host (3 x n_shift,
+ * row j = direction), err, n_pairs (pairs used), rank (eigenvalues kept),
+ * U_dev (optional, device [n_steps][n_rec][3]: the fitted response).
+ * Synchronises the context stream. */
+SW_API int sw_fit_workspace_bytes(int32_t n_rec, int64_t n_steps, int32_t stride, int32_t n_shift, size_t* bytes);
+SW_API int sw_fit_input(sw_ctx* ctx, int32_t n_rec, int64_t n_steps, const double* const* green, const double* obs,
+                        int32_t stride, int32_t n_shift, double rel_cut, void* dev_ws, size_t ws_bytes,
+                        double* c_host, double* err, int32_t* n_pairs, int32_t* rank, double* U_dev);
+
 /* ----------------------------------------------------------------- batch */
 
 /* A batch marches many candidate models together: the repeated analyses of

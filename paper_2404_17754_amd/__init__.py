@@ -349,6 +349,32 @@ def misfit(ctx: Context, U, obs):
     return e.value, n.value
 
 
+def fit_input(ctx: Context, green, obs, stride, n_shift, rel_cut=1e-6, return_response=False):
+    """Input estimation and ERR of Section 2 (sw_fit_input).  green: three
+    device tensors (n_steps, n_rec, 3), the Green's records for the impulse
+    along x1, x2, x3; obs: device tensor of the same shape.  Returns
+    (c (3, n_shift), ERR, pairs used, rank[, fitted response])."""
+    torch = _torch()
+    green = [g.to(ctx.device, torch.float64).contiguous() for g in green]
+    obs = obs.to(ctx.device, torch.float64).contiguous()
+    n_steps, n_rec = int(obs.shape[0]), int(obs.shape[1])
+    for g in green:
+        if tuple(g.shape) != (n_steps, n_rec, 3):
+            raise ValueError("Green's records must have the shape of obs")
+    nb = C.c_size_t()
+    L.check(ctx.lib.sw_fit_workspace_bytes(n_rec, n_steps, int(stride), int(n_shift), C.byref(nb)))
+    ws = _workspace(nb.value, ctx.device)
+    ptrs = (C.c_void_p * 3)(*[g.data_ptr() for g in green])
+    c = np.zeros((3, int(n_shift)))
+    e, used, rank = C.c_double(), C.c_int32(), C.c_int32()
+    U = torch.empty_like(obs) if return_response else None
+    L.check(ctx.lib.sw_fit_input(ctx.h, n_rec, n_steps, ptrs, C.c_void_p(obs.data_ptr()), int(stride), int(n_shift),
+                                 float(rel_cut), C.c_void_p(ws.data_ptr()), nb.value, _ptr(c), C.byref(e),
+                                 C.byref(used), C.byref(rank), C.c_void_p(U.data_ptr() if U is not None else 0)))
+    out = (c, e.value, used.value, rank.value)
+    return out + (U,) if return_response else out
+
+
 class Batch:
     """Several cases marched together (see sw_batch_* in include/sw.h)."""
 

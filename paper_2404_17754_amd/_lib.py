@@ -78,6 +78,9 @@ SIGNATURES = {
     "sw_misfit_workspace_bytes": (I32, C.POINTER(SZ)),
     "sw_misfit": (VP, I32, I64, VP, VP, VP, SZ, C.POINTER(F64), C.POINTER(I32)),
     "sw_case_misfit": (VP, VP, C.POINTER(F64), C.POINTER(I32)),
+    "sw_fit_workspace_bytes": (I32, I64, I32, I32, C.POINTER(SZ)),
+    "sw_fit_input": (VP, I32, I64, C.POINTER(VP), VP, I32, I32, F64, VP, SZ, VP, C.POINTER(F64), C.POINTER(I32),
+                     C.POINTER(I32), VP),
     "sw_mlp_init_params": (C.c_uint64, VP),
     "sw_mlp_workspace_bytes": (C.POINTER(SZ),),
     "sw_mlp_create": (VP, VP, VP, SZ, PP),

@@ -15,7 +15,7 @@ CSRC = os.path.join(PKG, "csrc")
 ROOT = os.path.dirname(PKG)
 LIB = os.path.join(PKG, "libsw.so")
 
-SOURCES = ["sw_tile.hip", "sw_kernels.hip", "sw_mlp.hip", "sw_proj.hip", "sw_mesh.cpp", "sw_api.cpp"]
+SOURCES = ["sw_tile.hip", "sw_kernels.hip", "sw_mlp.hip", "sw_proj.hip", "sw_fit.hip", "sw_mesh.cpp", "sw_api.cpp"]
 HEADERS = ["sw_elem.h", "sw_internal.h", "sw_device.h", "sw_layout.h"]
 
 HIPCC_FLAGS = [

@@ -939,65 +939,86 @@ MlpFeat mlp_features(const sw_case* c) {
 
 enum { GUESS_NONE = 0, GUESS_EXTRAP = 1, GUESS_NET = 2, GUESS_PROJ = 3 };
 
-// Solves G theta = h for a symmetric positive semidefinite G (m <= PROJ_MAX,
-// leading dimension ldg) in the least-squares sense: cyclic Jacobi
-// eigen-decomposition of the unit-diagonal scaling D G D (D = diag(G)^-1/2),
-// eigenvalues below rel_cut times the largest dropped (directions the past
-// increments do not resolve above rounding), theta = D V W^+ V^T D h.
+// Eigen-decomposition of a symmetric n x n matrix (row-major, destroyed) by
+// cyclic Jacobi rotations: A = V diag(w) V^T, V row-major with eigenvectors
+// in its columns.
+void sym_eig(int n, std::vector<double>& A, std::vector<double>& V, std::vector<double>& w) {
+  V.assign((size_t)n * n, 0.0);
+  for (int i = 0; i < n; ++i) V[(size_t)i * n + i] = 1.0;
+  auto a = [&](int i, int j) -> double& { return A[(size_t)i * n + j]; };
+  auto v = [&](int i, int j) -> double& { return V[(size_t)i * n + j]; };
+  for (int sweep = 0; sweep < 100; ++sweep) {
+    double off = 0.0, diag = 0.0;
+    for (int i = 0; i < n; ++i) {
+      diag += a(i, i) * a(i, i);
+      for (int j = i + 1; j < n; ++j) off += a(i, j) * a(i, j);
+    }
+    if (off <= 1e-32 * diag || off == 0.0) break;
+    for (int p = 0; p < n; ++p)
+      for (int q = p + 1; q < n; ++q) {
+        const double apq = a(p, q);
+        if (apq == 0.0) continue;
+        // rotation in the (p, q) plane that zeroes a(p, q)
+        const double th = (a(q, q) - a(p, p)) / (2.0 * apq);
+        const double t = (th >= 0.0 ? 1.0 : -1.0) / (std::fabs(th) + std::sqrt(th * th + 1.0));
+        const double cs = 1.0 / std::sqrt(t * t + 1.0), sn = t * cs;
+        a(p, p) -= t * apq;
+        a(q, q) += t * apq;
+        a(p, q) = a(q, p) = 0.0;
+        for (int r = 0; r < n; ++r) {
+          if (r != p && r != q) {
+            const double arp = a(r, p), arq = a(r, q);
+            a(r, p) = a(p, r) = cs * arp - sn * arq;
+            a(r, q) = a(q, r) = sn * arp + cs * arq;
+          }
+          const double vrp = v(r, p), vrq = v(r, q);
+          v(r, p) = cs * vrp - sn * vrq;
+          v(r, q) = sn * vrp + cs * vrq;
+        }
+      }
+  }
+  w.resize(n);
+  for (int i = 0; i < n; ++i) w[i] = a(i, i);
+}
+
+// theta = V W^+ V^T h for A = V diag(w) V^T, eigenvalues at or below
+// rel_cut times the largest dropped; returns how many were kept.
+int truncated_solve(int n, const std::vector<double>& V, const std::vector<double>& w, const double* h,
+                    double* theta, double rel_cut) {
+  double wmax = 0.0;
+  for (int i = 0; i < n; ++i) wmax = std::max(wmax, w[i]);
+  std::vector<double> y(n, 0.0);
+  int kept = 0;
+  for (int k = 0; k < n; ++k) {
+    if (!(wmax > 0.0 && w[k] > rel_cut * wmax)) continue;
+    double acc = 0.0;
+    for (int i = 0; i < n; ++i) acc += V[(size_t)i * n + k] * h[i];
+    y[k] = acc / w[k];
+    ++kept;
+  }
+  for (int i = 0; i < n; ++i) {
+    double acc = 0.0;
+    for (int k = 0; k < n; ++k) acc += V[(size_t)i * n + k] * y[k];
+    theta[i] = acc;
+  }
+  return kept;
+}
+
+// Solves G theta = h for a symmetric positive semidefinite G (leading
+// dimension ldg) in the least-squares sense, on the unit-diagonal scaling
+// D G D (D = diag(G)^-1/2) truncated at rel_cut: theta = D (D G D)^+ D h.
 void psd_solve(int m, const double* G, int ldg, const double* h, double* theta, double rel_cut) {
-  double A[PROJ_MAX][PROJ_MAX], V[PROJ_MAX][PROJ_MAX], d[PROJ_MAX];
+  std::vector<double> d(m), A((size_t)m * m), V, w, hs(m), ts(m);
   for (int i = 0; i < m; ++i) {
     const double gi = G[i * ldg + i];
     d[i] = gi > 0.0 ? 1.0 / std::sqrt(gi) : 0.0;
   }
   for (int i = 0; i < m; ++i)
-    for (int j = 0; j < m; ++j) {
-      A[i][j] = d[i] * 0.5 * (G[i * ldg + j] + G[j * ldg + i]) * d[j];
-      V[i][j] = i == j ? 1.0 : 0.0;
-    }
-  for (int sweep = 0; sweep < 64; ++sweep) {
-    double off = 0.0, diag = 0.0;
-    for (int i = 0; i < m; ++i) {
-      diag += A[i][i] * A[i][i];
-      for (int j = i + 1; j < m; ++j) off += A[i][j] * A[i][j];
-    }
-    if (off <= 1e-32 * diag) break;
-    for (int p = 0; p < m; ++p)
-      for (int q = p + 1; q < m; ++q) {
-        if (A[p][q] == 0.0) continue;
-        // rotation in the (p, q) plane that zeroes A[p][q]
-        const double th = (A[q][q] - A[p][p]) / (2.0 * A[p][q]);
-        const double t = (th >= 0.0 ? 1.0 : -1.0) / (std::fabs(th) + std::sqrt(th * th + 1.0));
-        const double cs = 1.0 / std::sqrt(t * t + 1.0), sn = t * cs;
-        const double apq = A[p][q];
-        A[p][p] -= t * apq;
-        A[q][q] += t * apq;
-        A[p][q] = A[q][p] = 0.0;
-        for (int r = 0; r < m; ++r) {
-          if (r != p && r != q) {
-            const double arp = A[r][p], arq = A[r][q];
-            A[r][p] = A[p][r] = cs * arp - sn * arq;
-            A[r][q] = A[q][r] = sn * arp + cs * arq;
-          }
-          const double vrp = V[r][p], vrq = V[r][q];
-          V[r][p] = cs * vrp - sn * vrq;
-          V[r][q] = sn * vrp + cs * vrq;
-        }
-      }
-  }
-  double wmax = 0.0;
-  for (int i = 0; i < m; ++i) wmax = std::max(wmax, A[i][i]);
-  double y[PROJ_MAX];
-  for (int k = 0; k < m; ++k) {
-    double acc = 0.0;
-    for (int i = 0; i < m; ++i) acc += V[i][k] * d[i] * h[i];
-    y[k] = (wmax > 0.0 && A[k][k] > rel_cut * wmax) ? acc / A[k][k] : 0.0;
-  }
-  for (int i = 0; i < m; ++i) {
-    double acc = 0.0;
-    for (int k = 0; k < m; ++k) acc += V[i][k] * y[k];
-    theta[i] = d[i] * acc;
-  }
+    for (int j = 0; j < m; ++j) A[(size_t)i * m + j] = d[i] * 0.5 * (G[i * ldg + j] + G[j * ldg + i]) * d[j];
+  sym_eig(m, A, V, w);
+  for (int i = 0; i < m; ++i) hs[i] = d[i] * h[i];
+  truncated_solve(m, V, w, hs.data(), ts.data(), rel_cut);
+  for (int i = 0; i < m; ++i) theta[i] = d[i] * ts[i];
 }
 
 // Projection guess, first half: X_i . b for the ring, copied to the host.
@@ -1432,6 +1453,112 @@ extern "C" int sw_case_misfit(sw_case* c, const double* obs, double* err, int32_
 }
 
 // ------------------------------------------------------------ network
+
+// ------------------------------------------------------- input estimation
+
+namespace {
+
+struct FitWs {
+  double *o2, *w, *C, *c, *U, *mis, *out2;
+};
+
+constexpr int FIT_MAX_SHIFT = 128;
+
+size_t fit_layout(int32_t n_rec, int64_t n_steps, int32_t stride, Carver& cv, FitWs* f) {
+  const int np = 3 * n_rec;
+  const int64_t nb = n_steps / stride;
+  FitWs t{};
+  t.o2 = cv.take<double>(np);
+  t.w = cv.take<double>(np);
+  t.C = cv.take<double>((size_t)(4 * nb) * (4 * nb));
+  t.c = cv.take<double>(3 * FIT_MAX_SHIFT);
+  t.U = cv.take<double>((size_t)n_steps * np);
+  t.mis = cv.take<double>(2 * np + 2);
+  t.out2 = cv.take<double>(2);
+  if (f) *f = t;
+  return cv.off + 256;
+}
+
+int fit_check(int32_t n_rec, int64_t n_steps, int32_t stride, int32_t n_shift) {
+  if (n_rec < 1 || n_steps < 1) return fail(SW_EINVAL, "need receivers and steps");
+  if (stride < 1 || n_steps % stride) return fail(SW_EINVAL, "n_steps must be a positive multiple of the stride");
+  if (n_shift < 1 || n_shift > n_steps / stride || n_shift > FIT_MAX_SHIFT)
+    return fail(SW_EINVAL, "n_shift must be in 1..min(n_steps / stride, %d)", FIT_MAX_SHIFT);
+  return SW_OK;
+}
+
+}  // namespace
+
+extern "C" int sw_fit_workspace_bytes(int32_t n_rec, int64_t n_steps, int32_t stride, int32_t n_shift,
+                                      size_t* bytes) {
+  if (!bytes) return fail(SW_EINVAL, "bytes is NULL");
+  int rc = fit_check(n_rec, n_steps, stride, n_shift);
+  if (rc) return rc;
+  Carver cv(nullptr);
+  *bytes = fit_layout(n_rec, n_steps, stride, cv, nullptr);
+  return SW_OK;
+}
+
+extern "C" int sw_fit_input(sw_ctx* ctx, int32_t n_rec, int64_t n_steps, const double* const* green,
+                            const double* obs, int32_t stride, int32_t n_shift, double rel_cut, void* ws,
+                            size_t ws_bytes, double* c_host, double* err, int32_t* n_pairs, int32_t* rank,
+                            double* U_dev) {
+  if (!ctx || !green || !obs || !c_host || !err) return fail(SW_EINVAL, "NULL argument");
+  for (int j = 0; j < 3; ++j)
+    if (!green[j]) return fail(SW_EINVAL, "Green's record %d is NULL", j);
+  int rc = fit_check(n_rec, n_steps, stride, n_shift);
+  if (rc) return rc;
+  if (!(rel_cut >= 0.0 && rel_cut < 1.0)) return fail(SW_EINVAL, "rel_cut must be in [0, 1)");
+  {
+    Carver dry(nullptr);
+    const size_t need = fit_layout(n_rec, n_steps, stride, dry, nullptr);
+    if (!ws || ((uintptr_t)ws & 255) || ws_bytes < need)
+      return fail(SW_ENOWS, "fit workspace needs %zu bytes, 256-byte aligned", need);
+  }
+  HIPC(hipSetDevice(ctx->device));
+  hipStream_t s = ctx->stream;
+  FitWs f;
+  Carver cv(ws);
+  fit_layout(n_rec, n_steps, stride, cv, &f);
+  const int np = 3 * n_rec, nb = (int)(n_steps / stride), L = n_shift, ncol = 4 * nb;
+  launch_fit_weights(np, n_steps, obs, f.o2, f.w, s);
+  launch_fit_gram(green, obs, np, stride, nb, f.w, f.C, s);
+  LAUNCHED();
+  std::vector<double> C((size_t)ncol * ncol);
+  HIPC(hipMemcpyAsync(C.data(), f.C, C.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+  HIPC(hipStreamSynchronize(s));
+  // normal equations from block inner products (shift l delays by l blocks)
+  const int n = 3 * L;
+  std::vector<double> A((size_t)n * n, 0.0), bv(n, 0.0), V, w, cvec(n);
+  for (int j = 0; j < 3; ++j)
+    for (int l = 0; l < L; ++l) {
+      double acc = 0.0;
+      for (int b = l; b < nb; ++b) acc += C[(size_t)(j * nb + b - l) * ncol + 3 * nb + b];
+      bv[j * L + l] = acc;
+      for (int j2 = 0; j2 < 3; ++j2)
+        for (int l2 = 0; l2 < L; ++l2) {
+          double a = 0.0;
+          for (int b = std::max(l, l2); b < nb; ++b) a += C[(size_t)(j * nb + b - l) * ncol + j2 * nb + b - l2];
+          A[(size_t)(j * L + l) * n + j2 * L + l2] = a;
+        }
+    }
+  sym_eig(n, A, V, w);
+  const int kept = truncated_solve(n, V, w, bv.data(), cvec.data(), rel_cut);
+  for (int i = 0; i < n; ++i) c_host[i] = cvec[i];
+  if (rank) *rank = kept;
+  // response to the fitted input and its misfit
+  double* U = U_dev ? U_dev : f.U;
+  HIPC(hipMemcpyAsync(f.c, cvec.data(), n * sizeof(double), hipMemcpyHostToDevice, s));
+  launch_fit_response(green, np, stride, L, n_steps, f.c, U, s);
+  launch_misfit(n_rec, n_steps, U, obs, f.mis, f.out2, s);
+  LAUNCHED();
+  double out2[2];
+  HIPC(hipMemcpyAsync(out2, f.out2, sizeof out2, hipMemcpyDeviceToHost, s));
+  HIPC(hipStreamSynchronize(s));
+  *err = out2[0];
+  if (n_pairs) *n_pairs = (int32_t)out2[1];
+  return SW_OK;
+}
 
 static size_t mlp_layout(Carver& cv, sw_mlp* o) {
   auto th = cv.take<float>(MLP_NP);

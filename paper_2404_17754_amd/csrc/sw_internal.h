@@ -266,6 +266,18 @@ void launch_proj_combine_res(int L, int64_t n, const double* X, const double* Y,
 void launch_proj_store(int64_t n, const double* x, const double* b, const double* r, double* Xs, double* Ys,
                        hipStream_t s);
 
+// ---- input estimation (sw_fit.hip) ----------------------------------------
+
+// w[pair] = 1 / |obs_pair|^2 (zero for silent pairs); o2: n_pairs scratch
+void launch_fit_weights(int n_pairs, int64_t n_steps, const double* obs, double* o2, double* w, hipStream_t s);
+// C (4 nb x 4 nb) = weighted Gram matrix of the stride-m blocks of the three
+// Green's records and the observed record, records [t][pair]
+void launch_fit_gram(const double* const g[3], const double* obs, int n_pairs, int m, int nb, const double* w,
+                     double* C, hipStream_t s);
+// U[t][pair] = sum_{j,l} c[j][l] g_j[t - l m][pair]
+void launch_fit_response(const double* const g[3], int n_pairs, int m, int n_shift, int64_t n_steps,
+                         const double* c, double* U, hipStream_t s);
+
 void launch_fill_f64(int64_t n, double* x, double val, hipStream_t s);
 void launch_fill_f32(int64_t n, float* x, float val, hipStream_t s);
 

@@ -20,7 +20,8 @@ import sqlite3
 import sys
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-KERNEL_SOURCES = ["sw_tile.hip", "sw_elem.h", "sw_device.h", "sw_internal.h", "sw_layout.h", "sw_mesh.cpp"]
+# the sources that define the operator kernels and the layout they read
+KERNEL_SOURCES = ["sw_tile.hip", "sw_elem.h", "sw_device.h", "sw_layout.h", "sw_mesh.cpp"]
 
 
 def kernel_hash():
