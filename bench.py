@@ -184,6 +184,47 @@ def batched_study(sw, cg, ctx, per_mesh, steps, proj_dim):
             "max_true_rel_res": worst}
 
 
+def fit_study(sw, cg, ctx, n_steps, stride, proj_dim):
+    """Section 2's input estimation for one candidate model of the batched
+    workload (300 x 300 x 100 m, 5 m cells, 20 x 20 receivers): the model's
+    three Green's runs (unit Hann impulse along x1, x2, x3) marched as one
+    batch, a reference model driven by the Ricker input as the observation,
+    then the fit (weighted normal equations on the GPU, pseudo-inverse on
+    the host, response and ERR on the GPU)."""
+    import torch
+    cfg = cg.CONFIGS["batch300"]
+    mesh = cg.config_mesh(cfg)
+    gm = sw.Mesh(ctx, mesh)
+    model = cg.make_case(mesh, cfg, seed=cfg.seed, n_steps=n_steps)
+    ref = cg.make_case(mesh, cfg, seed=cfg.seed - 1, n_steps=n_steps)
+    lanes = []
+    for v_in in cg.impulse_inputs(n_steps, stride):
+        c = cg.Case(mat=model.mat, tet_mat=model.tet_mat, rec_node=model.rec_node, v_in=v_in, dt=model.dt,
+                    n_steps=n_steps, ray_alpha=model.ray_alpha, ray_beta=model.ray_beta, meta={})
+        lanes.append(sw.Case(ctx, gm, c, precision="mixed", guess="proj", proj_dim=proj_dim))
+    obs_case = sw.Case(ctx, gm, ref, precision="mixed", guess="proj", proj_dim=proj_dim)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sw.Batch(ctx, lanes + [obs_case]).step(n_steps)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    green = [torch.from_numpy(l.waveforms()).cuda() for l in lanes]
+    obs = torch.from_numpy(obs_case.waveforms()).cuda()
+    n_shift = n_steps // stride
+    sw.fit_input(ctx, green, obs, stride, n_shift)          # warm-up
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    c, e, used, rank = sw.fit_input(ctx, green, obs, stride, n_shift)
+    torch.cuda.synchronize()
+    t3 = time.perf_counter()
+    del lanes, obs_case
+    torch.cuda.empty_cache()
+    return {"mesh": f"batch300: {mesh.n_tets} tets, {3 * mesh.n_nodes} DOF", "steps": n_steps,
+            "receivers": int(obs.shape[1]), "stride_steps": stride, "shifts": n_shift,
+            "runs_s (3 Green's + 1 observation, one batch)": round(t1 - t0, 2),
+            "fit_ms": round(1e3 * (t3 - t2), 2), "err_vs_other_model": round(e, 4), "pairs": used, "rank": rank}
+
+
 def timed_window(sw, ctx, gmesh, case, n, **kw):
     """A fresh case marched `n` steps from rest; ms per step and the step
     log."""
@@ -220,6 +261,8 @@ def main():
     ap.add_argument("--batched", type=int, default=0,
                     help="cases per mesh of an extra batched-vs-sequential study on the 200/300/400 m meshes")
     ap.add_argument("--batched-steps", type=int, default=30)
+    ap.add_argument("--fit-study", type=int, default=0,
+                    help="steps of an extra input-estimation study (Green's runs + fit) on the 300 m mesh (0 = skip)")
     ap.add_argument("--train-cases", type=int, default=4)
     ap.add_argument("--train-steps", type=int, default=150)
     ap.add_argument("--adam-steps", type=int, default=3000)
@@ -355,6 +398,11 @@ def main():
         torch.cuda.empty_cache()
         batched = batched_study(sw, cg, ctx, args.batched, args.batched_steps, args.proj_dim)
 
+    fit = None
+    if args.fit_study > 0:
+        torch.cuda.empty_cache()
+        fit = fit_study(sw, cg, ctx, args.fit_study, 20, args.proj_dim)
+
     cpu = None if args.no_cpu_baseline else cpu_baseline(args.config, dof)
 
     out = {
@@ -374,7 +422,7 @@ def main():
         "learned_guess_training": train_info,
         "kernels_ms": {k: {"total_ms": round(v[0], 3), "launches": v[1], "full_launch_us": round(1e3 * v[2], 1)}
                        for k, v in kernels.items() if v[1]},
-        "roofline": roofline, "compare": compare, "batched": batched, "cpu_baseline": cpu,
+        "roofline": roofline, "compare": compare, "batched": batched, "input_estimation": fit, "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
 
