@@ -375,6 +375,16 @@ def fit_input(ctx: Context, green, obs, stride, n_shift, rel_cut=1e-6, return_re
     return out + (U,) if return_response else out
 
 
+def fit_events(ctx: Context, green, events, stride, n_shift, rel_cut=1e-6):
+    """One model's misfit over several observed events: the Green's records
+    are computed once per model (they do not depend on the event) and the
+    input is estimated per event with sw_fit_input.  Returns the list of
+    (c, ERR, pairs, rank) per event and the largest ERR (the model's worst
+    event)."""
+    fits = [fit_input(ctx, green, obs, stride, n_shift, rel_cut) for obs in events]
+    return fits, max(f[1] for f in fits)
+
+
 class Batch:
     """Several cases marched together (see sw_batch_* in include/sw.h)."""
 

@@ -101,7 +101,9 @@ __global__ __launch_bounds__(FT* FT) void k_fit_gram(FitSrc S, const double* __r
     for (int kk = 0; kk < FK; ++kk) acc += xa[kk][a] * xb[kk][bcol];
     __syncthreads();
   }
-  if (ca < ncol && cb < ncol) {
+  // each symmetric pair written by one thread (in a diagonal tile the
+  // (a, b) and (b, a) threads round differently), so C is deterministic
+  if (ca < ncol && cb < ncol && (tb > ta || bcol >= a)) {
     C[(int64_t)ca * ncol + cb] = acc;
     C[(int64_t)cb * ncol + ca] = acc;
   }
