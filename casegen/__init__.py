@@ -92,22 +92,57 @@ def _kuhn_cell():
     return np.stack(tets)  # (6, 10, 3)
 
 
-def box_mesh(Lx, Ly, Lz, h, jitter=0.0, seed=12345) -> Mesh:
+def graded_levels(Lz, h_top, ratio):
+    """Vertex depths from -Lz up to 0 of layers whose thickness is h_top at
+    the surface and grows by ``ratio`` per layer downwards (the last layer
+    takes what is left, merged into the one above when thinner than half of
+    it): a mesh refined towards the surface, as the paper's are near the
+    soft layer."""
+    th, z = [], 0.0
+    t = h_top
+    while z + t < Lz - 1e-9:
+        th.append(t)
+        z += t
+        t *= ratio
+    rest = Lz - z
+    if th and rest < 0.5 * th[-1]:
+        th[-1] += rest
+    else:
+        th.append(rest)
+    levels = -np.concatenate([[0.0], np.cumsum(th)])      # 0 at the top, downwards
+    return levels[::-1].copy()                             # -Lz .. 0
+
+
+def box_mesh(Lx, Ly, Lz, h, jitter=0.0, seed=12345, z_levels=None) -> Mesh:
     """Structured box [0,Lx]x[0,Ly]x[-Lz,0] of cubic cells of edge h, each
     split into six 10-node tetrahedra (conforming Kuhn split).
 
+    ``z_levels`` (optional): the vertex depths, increasing from -Lz to 0,
+    of layers of varying thickness (x and y spacing stays h), e.g. from
+    graded_levels.
+
     ``jitter`` > 0 moves every interior vertex node by a seeded uniform
-    offset of at most jitter*h per coordinate; every edge node is then put
-    back at the middle of its (straight) edge.  The result is a mesh with no
-    lattice structure left in its geometry, for tests that must not rely on
-    one.
+    offset of at most jitter times the local spacing per coordinate; every
+    edge node is then put back at the middle of its (straight) edge.  The
+    result is a mesh with no lattice structure left in its geometry, for
+    tests that must not rely on one.
     """
-    nx, ny, nz = (int(round(Lx / h)), int(round(Ly / h)), int(round(Lz / h)))
-    assert abs(nx * h - Lx) < 1e-9 and abs(ny * h - Ly) < 1e-9 and abs(nz * h - Lz) < 1e-9
+    nx, ny = int(round(Lx / h)), int(round(Ly / h))
+    assert abs(nx * h - Lx) < 1e-9 and abs(ny * h - Ly) < 1e-9
+    if z_levels is None:
+        nz = int(round(Lz / h))
+        assert abs(nz * h - Lz) < 1e-9
+        zv = -Lz + np.arange(nz + 1, dtype=np.float64) * h
+    else:
+        zv = np.asarray(z_levels, np.float64)
+        nz = len(zv) - 1
+        assert nz >= 1 and abs(zv[0] + Lz) < 1e-9 and abs(zv[-1]) < 1e-9 and np.all(np.diff(zv) > 0)
     NX, NY, NZ = 2 * nx + 1, 2 * ny + 1, 2 * nz + 1
     I = np.arange(NX, dtype=np.float64) * (h / 2)
     J = np.arange(NY, dtype=np.float64) * (h / 2)
-    K = -Lz + np.arange(NZ, dtype=np.float64) * (h / 2)
+    K = np.empty(NZ)
+    K[0::2] = zv
+    K[1::2] = 0.5 * (zv[:-1] + zv[1:])
     xyz = np.empty((NZ, NY, NX, 3), np.float64)
     xyz[..., 0] = I[None, None, :]
     xyz[..., 1] = J[None, :, None]
@@ -131,7 +166,13 @@ def box_mesh(Lx, Ly, Lz, h, jitter=0.0, seed=12345) -> Mesh:
         is_vert = (gi % 2 == 0) & (gj % 2 == 0) & (gk % 2 == 0)
         interior = (gi > 0) & (gi < NX - 1) & (gj > 0) & (gj < NY - 1) & (gk > 0) & (gk < NZ - 1)
         mv = is_vert & interior
-        xyz[mv] += rng.uniform(-jitter * h, jitter * h, (int(mv.sum()), 3))
+        off = rng.uniform(-jitter, jitter, (int(mv.sum()), 3))
+        # local vertical spacing: the thinner of the two layers at the vertex
+        kk = gk[mv] // 2
+        hz = np.minimum(zv[kk] - zv[kk - 1], zv[kk + 1] - zv[kk])
+        off[:, :2] *= h
+        off[:, 2] *= hz
+        xyz[mv] += off
         mid = ~is_vert
         d = np.stack([gi % 2, gj % 2, gk % 2], -1)[mid]
         p = np.stack([gi, gj, gk], -1)[mid]

@@ -128,8 +128,6 @@ struct LaneInfo {
 
 void launch_tile_lanes_f64(const TileLane<double>* lanes, const int2* work, int n_work, int max_tile_nodes,
                            const LaneState* st, int iter, hipStream_t s);
-void launch_tile_lanes_f32(const TileLane<float>* lanes, const int2* work, int n_work, int max_tile_nodes,
-                           const LaneState* st, int iter, hipStream_t s);
 // FP32 CG-iteration pass of every lane, persistent and pipelined over items
 // (lane, tile) listed tile-major with a tile's lanes adjacent; tiles of at
 // most 1280 nodes.

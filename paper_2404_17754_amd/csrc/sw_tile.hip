@@ -564,11 +564,6 @@ void launch_tile_lanes_pipe_f32(const TileLane<float>* lanes, const int2* items,
   hipLaunchKernelGGL((k_tile_lanes_pipe<PIPE_NT, PIPE_NPT>), dim3(pipe_grid(n_items)), dim3(PIPE_NT),
                      tile_lds<float>(max_tile_nodes), s, lanes, items, n_items, max_tile_nodes, st, iter);
 }
-void launch_tile_lanes_f32(const TileLane<float>* lanes, const int2* work, int n_work, int max_tile_nodes,
-                           const LaneState* st, int iter, hipStream_t s) {
-  hipLaunchKernelGGL((k_tile_lanes<float, 256>), dim3(n_work), dim3(256), tile_lds<float>(max_tile_nodes), s, lanes,
-                     work, st, iter);
-}
 
 // ------------------------------------------------------------ geometry
 

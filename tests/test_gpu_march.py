@@ -156,3 +156,16 @@ def test_case_misfit_against_oracle_reference(sw, ctx, small, gmesh):
     e_ref, n_ref = om.err(ref.rec_v, obs)
     assert n == n_ref
     assert abs(e - e_ref) < 1e-5 * e_ref
+
+
+def test_graded_mesh_march(sw, ctx):
+    """A mesh refined towards the surface (layers 2.5 m at the top to ~11 m
+    at the base, jittered): mixed precision with the projection guess
+    against the oracle's exact solves."""
+    mesh = cg.box_mesh(60.0, 40.0, 40.0, 10.0, jitter=0.15, seed=5, z_levels=cg.graded_levels(40.0, 2.5, 1.5))
+    case = cg.make_case(mesh, cg.CONFIGS["small"], n_steps=20, n_rec=2)
+    ref = march.run_case(mesh, case, solver="lu")
+    gc = sw.Case(ctx, sw.Mesh(ctx, mesh), case, precision="mixed", guess="proj")
+    gc.step(case.n_steps)
+    assert _relL2(gc.waveforms(), ref.rec_v) < TOL_WAVE
+    assert gc.stats()["max_true_rel_res"] <= 1e-8 and gc.stats()["flags"] == 0

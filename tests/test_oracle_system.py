@@ -25,9 +25,13 @@ def _rigid_modes(xyz):
     return R
 
 
-@pytest.mark.parametrize("which", ["small", "jitter"])
+def _graded_mesh():
+    return cg.box_mesh(40.0, 30.0, 30.0, 10.0, jitter=0.15, seed=9, z_levels=cg.graded_levels(30.0, 2.5, 1.6))
+
+
+@pytest.mark.parametrize("which", ["small", "jitter", "graded"])
 def test_global_stiffness_rigid_modes(which, small_mesh, small_case, jitter_mesh):
-    mesh = small_mesh if which == "small" else jitter_mesh
+    mesh = {"small": small_mesh, "jitter": jitter_mesh}.get(which) or _graded_mesh()
     tet_mat = small_case.tet_mat if which == "small" else (np.arange(mesh.n_tets) % 2).astype(np.uint8)
     K, M = assemble.stiffness_and_mass(mesh, cg.material_table(), tet_mat)
     kn = abs(K).sum(1).max()
@@ -42,10 +46,11 @@ def test_global_stiffness_rigid_modes(which, small_mesh, small_case, jitter_mesh
     assert abs(t @ M @ t - np.sum(V * mat[tet_mat, 2])) < 1e-12 * np.sum(V * mat[tet_mat, 2])
 
 
-def test_patch_test_linear_field(jitter_mesh):
+@pytest.mark.parametrize("which", ["jitter", "graded"])
+def test_patch_test_linear_field(which, jitter_mesh):
     # one material: a linear displacement then has uniform stress, so the
     # interior nodal forces vanish and the interior solution is exact
-    mesh = jitter_mesh
+    mesh = jitter_mesh if which == "jitter" else _graded_mesh()
     tet_mat = np.zeros(mesh.n_tets, np.uint8)
     K, _ = assemble.stiffness_and_mass(mesh, cg.material_table(), tet_mat)
     rng = np.random.default_rng(11)
