@@ -158,8 +158,8 @@ def batched_study(sw, cg, ctx, per_mesh, steps, proj_dim):
         for k in range(per_mesh):
             cases.append((gm, cg.make_case(m, cfg, seed=cfg.seed + 3 * k + len(cases), n_steps=steps)))
 
-    def run(batched):
-        lanes = [sw.Case(ctx, gm, c, precision="mixed", guess="proj", proj_dim=proj_dim) for gm, c in cases]
+    def run(batched, precision="mixed", guess="proj"):
+        lanes = [sw.Case(ctx, gm, c, precision=precision, guess=guess, proj_dim=proj_dim) for gm, c in cases]
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         if batched:
@@ -177,10 +177,14 @@ def batched_study(sw, cg, ctx, per_mesh, steps, proj_dim):
 
     seq, its_s, _ = run(False)
     bat, its_b, worst = run(True)
+    plain, its_p, _ = run(False, precision="fp64", guess="zero")
     return {"meshes": [f"{n}: {t} tets" for n, t in meshes], "cases": len(cases), "steps": steps,
             "guess": f"proj (L={proj_dim})", "sequential_case_timesteps_per_s": round(seq, 2),
             "batched_case_timesteps_per_s": round(bat, 2), "speedup": round(bat / seq, 3),
-            "cg_iters_per_step": {"sequential": round(its_s, 2), "batched": round(its_b, 2)},
+            "plain_fp64_sequential_case_timesteps_per_s": round(plain, 2),
+            "batched_vs_plain_fp64": round(bat / plain, 3),
+            "cg_iters_per_step": {"sequential": round(its_s, 2), "batched": round(its_b, 2),
+                                  "plain_fp64": round(its_p, 2)},
             "max_true_rel_res": worst}
 
 
