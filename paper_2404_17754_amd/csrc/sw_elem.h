@@ -72,106 +72,111 @@ SW_HD bool tet_geometry(const double x[4][3], Geo<T>& G) {
   return det > 0.0;
 }
 
-// y += sK * K_e w   (w, y: [10][3])
-template <typename T>
-SW_HD void stiffness_apply(const Geo<T>& G, T lam, T mu, T sK, const T w[10][3], T y[10][3]) {
-  T S[4][6];  // symmetric (xx, yy, zz, yz, xz, xy)
-  T sum[6] = {0, 0, 0, 0, 0, 0};
+// f = sK K_e w + sMV (table/420) w (sMV = sM rho V): the stiffness through
+// the vertex stresses S_k, the mass through per-component vertex and edge
+// sums.  Each node's force goes to sink(k, f0, f1, f2) as soon as it is
+// complete, so no 30-value force array is held (fewer live registers in the
+// tile passes, which scatter each force at once).
+template <typename T, typename Sink>
+SW_HD void element_apply(const Geo<T>& G, T lam, T mu, T sK, T sMV, const T w[10][3], Sink&& sink) {
+  const bool stiff = sK != (T)0, mass = sMV != (T)0;
+  T S[4][6];
+  T Ssum[6] = {0, 0, 0, 0, 0, 0};
+  if (stiff) {
+    T sum[6] = {0, 0, 0, 0, 0, 0};
 #pragma unroll
-  for (int k = 0; k < 4; ++k) {
-    T Gm[3][3];  // Gm[c][d] = d u_c / d x_d at vertex k
-#pragma unroll
-    for (int c = 0; c < 3; ++c) {
-#pragma unroll
-      for (int d = 0; d < 3; ++d) Gm[c][d] = (T)3 * w[k][c] * G.g[k][d];
-    }
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      if (j == k) continue;
-      const int e = 4 + (k < j ? tet_edge(k, j) : tet_edge(j, k));
+    for (int k = 0; k < 4; ++k) {
+      T Gm[3][3];
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
-        T W = (T)4 * w[e][c] - w[j][c];
 #pragma unroll
-        for (int d = 0; d < 3; ++d) Gm[c][d] += W * G.g[j][d];
+        for (int d = 0; d < 3; ++d) Gm[c][d] = (T)3 * w[k][c] * G.g[k][d];
+      }
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        if (j == k) continue;
+        const int e = 4 + (k < j ? tet_edge(k, j) : tet_edge(j, k));
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          T W = (T)4 * w[e][c] - w[j][c];
+#pragma unroll
+          for (int d = 0; d < 3; ++d) Gm[c][d] += W * G.g[j][d];
+        }
+      }
+      T tr = Gm[0][0] + Gm[1][1] + Gm[2][2];
+      T l = lam * tr;
+      S[k][0] = l + (T)2 * mu * Gm[0][0];
+      S[k][1] = l + (T)2 * mu * Gm[1][1];
+      S[k][2] = l + (T)2 * mu * Gm[2][2];
+      S[k][3] = mu * (Gm[1][2] + Gm[2][1]);
+      S[k][4] = mu * (Gm[0][2] + Gm[2][0]);
+      S[k][5] = mu * (Gm[0][1] + Gm[1][0]);
+#pragma unroll
+      for (int m = 0; m < 6; ++m) sum[m] += S[k][m];
+    }
+    const T c20 = sK * G.vol / (T)20;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+#pragma unroll
+      for (int m = 0; m < 6; ++m) {
+        S[k][m] = c20 * (S[k][m] + sum[m]);
+        Ssum[m] += S[k][m];
       }
     }
-    T tr = Gm[0][0] + Gm[1][1] + Gm[2][2];
-    T l = lam * tr;
-    S[k][0] = l + (T)2 * mu * Gm[0][0];
-    S[k][1] = l + (T)2 * mu * Gm[1][1];
-    S[k][2] = l + (T)2 * mu * Gm[2][2];
-    S[k][3] = mu * (Gm[1][2] + Gm[2][1]);
-    S[k][4] = mu * (Gm[0][2] + Gm[2][0]);
-    S[k][5] = mu * (Gm[0][1] + Gm[1][0]);
-#pragma unroll
-    for (int m = 0; m < 6; ++m) sum[m] += S[k][m];
   }
-  const T c20 = sK * G.vol / (T)20;
-  T Ssum[6];
+  // mass: per component the vertex sum, edge sum and each vertex's incident-edge sum
+  const T s = sMV / (T)420;
+  T Uv[3], Ue[3], inc[4][3];
 #pragma unroll
-  for (int m = 0; m < 6; ++m) Ssum[m] = (T)0;
-#pragma unroll
-  for (int k = 0; k < 4; ++k) {
-#pragma unroll
-    for (int m = 0; m < 6; ++m) {
-      S[k][m] = c20 * (S[k][m] + sum[m]);
-      Ssum[m] += S[k][m];
-    }
+  for (int c = 0; c < 3; ++c) {
+    Uv[c] = w[0][c] + w[1][c] + w[2][c] + w[3][c];
+    Ue[c] = w[4][c] + w[5][c] + w[6][c] + w[7][c] + w[8][c] + w[9][c];
+    inc[0][c] = w[4][c] + w[6][c] + w[7][c];
+    inc[1][c] = w[4][c] + w[5][c] + w[8][c];
+    inc[2][c] = w[5][c] + w[6][c] + w[9][c];
+    inc[3][c] = w[7][c] + w[8][c] + w[9][c];
   }
-  // sym(6) times vector
-  auto smv = [](const T s[6], const T v[3], T out[3]) {
-    out[0] = s[0] * v[0] + s[5] * v[1] + s[4] * v[2];
-    out[1] = s[5] * v[0] + s[1] * v[1] + s[3] * v[2];
-    out[2] = s[4] * v[0] + s[3] * v[1] + s[2] * v[2];
+  auto smv = [](const T sy[6], const T v[3], T o[3]) {
+    o[0] = sy[0] * v[0] + sy[5] * v[1] + sy[4] * v[2];
+    o[1] = sy[5] * v[0] + sy[1] * v[1] + sy[3] * v[2];
+    o[2] = sy[4] * v[0] + sy[3] * v[1] + sy[2] * v[2];
   };
 #pragma unroll
   for (int i = 0; i < 4; ++i) {
-    T s[6], f[3];
+    T f[3] = {(T)0, (T)0, (T)0};
+    if (stiff) {
+      T sy[6];
 #pragma unroll
-    for (int m = 0; m < 6; ++m) s[m] = (T)4 * S[i][m] - Ssum[m];
-    smv(s, G.g[i], f);
+      for (int m = 0; m < 6; ++m) sy[m] = (T)4 * S[i][m] - Ssum[m];
+      smv(sy, G.g[i], f);
+    }
+    if (mass) {
 #pragma unroll
-    for (int c = 0; c < 3; ++c) y[i][c] += f[c];
+      for (int c = 0; c < 3; ++c) f[c] += s * ((T)5 * w[i][c] + (Uv[c] - (T)6 * Ue[c]) + (T)2 * inc[i][c]);
+    }
+    sink(i, f[0], f[1], f[2]);
   }
+  // edges 01,12,02,03,13,23 and their opposite edges 23,03,13,12,02,01
   const int ea[6] = {0, 1, 0, 0, 1, 2};
   const int eb[6] = {1, 2, 2, 3, 3, 3};
+  const int eo[6] = {5, 3, 4, 1, 2, 0};
 #pragma unroll
   for (int e = 0; e < 6; ++e) {
-    T f1[3], f2[3];
-    smv(S[ea[e]], G.g[eb[e]], f1);
-    smv(S[eb[e]], G.g[ea[e]], f2);
+    T f[3] = {(T)0, (T)0, (T)0};
+    if (stiff) {
+      T f1[3], f2[3];
+      smv(S[ea[e]], G.g[eb[e]], f1);
+      smv(S[eb[e]], G.g[ea[e]], f2);
 #pragma unroll
-    for (int c = 0; c < 3; ++c) y[4 + e][c] += (T)4 * (f1[c] + f2[c]);
-  }
-}
-
-// y += sM * M_e w with M_e = rho V/420 * table (x) I3
-template <typename T>
-SW_HD void mass_apply(T rhoV, T sM, const T w[10][3], T y[10][3]) {
-  const T s = sM * rhoV / (T)420;
+      for (int c = 0; c < 3; ++c) f[c] = (T)4 * (f1[c] + f2[c]);
+    }
+    if (mass) {
 #pragma unroll
-  for (int c = 0; c < 3; ++c) {
-    T Uv = w[0][c] + w[1][c] + w[2][c] + w[3][c];
-    T Ue = w[4][c] + w[5][c] + w[6][c] + w[7][c] + w[8][c] + w[9][c];
-    // edges incident to each vertex (slots 0..5 = edges 01,12,02,03,13,23)
-    T inc0 = w[4][c] + w[6][c] + w[7][c];
-    T inc1 = w[4][c] + w[5][c] + w[8][c];
-    T inc2 = w[5][c] + w[6][c] + w[9][c];
-    T inc3 = w[7][c] + w[8][c] + w[9][c];
-    T base_v = Uv - (T)6 * Ue;
-    y[0][c] += s * ((T)5 * w[0][c] + base_v + (T)2 * inc0);
-    y[1][c] += s * ((T)5 * w[1][c] + base_v + (T)2 * inc1);
-    y[2][c] += s * ((T)5 * w[2][c] + base_v + (T)2 * inc2);
-    y[3][c] += s * ((T)5 * w[3][c] + base_v + (T)2 * inc3);
-    T base_e = (T)16 * Ue - (T)6 * Uv;
-    // edge (a,b), opposite edge: 01<->23, 12<->03, 02<->13
-    y[4][c] += s * (base_e + (T)2 * (w[0][c] + w[1][c]) + (T)16 * w[4][c] - (T)8 * w[9][c]);
-    y[5][c] += s * (base_e + (T)2 * (w[1][c] + w[2][c]) + (T)16 * w[5][c] - (T)8 * w[7][c]);
-    y[6][c] += s * (base_e + (T)2 * (w[0][c] + w[2][c]) + (T)16 * w[6][c] - (T)8 * w[8][c]);
-    y[7][c] += s * (base_e + (T)2 * (w[0][c] + w[3][c]) + (T)16 * w[7][c] - (T)8 * w[5][c]);
-    y[8][c] += s * (base_e + (T)2 * (w[1][c] + w[3][c]) + (T)16 * w[8][c] - (T)8 * w[6][c]);
-    y[9][c] += s * (base_e + (T)2 * (w[2][c] + w[3][c]) + (T)16 * w[9][c] - (T)8 * w[4][c]);
+      for (int c = 0; c < 3; ++c)
+        f[c] += s * (((T)16 * Ue[c] - (T)6 * Uv[c]) + (T)2 * (w[ea[e]][c] + w[eb[e]][c]) + (T)16 * w[4 + e][c] -
+                     (T)8 * w[4 + eo[e]][c]);
+    }
+    sink(4 + e, f[0], f[1], f[2]);
   }
 }
 

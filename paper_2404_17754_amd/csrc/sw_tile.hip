@@ -106,26 +106,22 @@ __device__ __forceinline__ double tile_elements(const MeshDev& m, const uint8_t*
       Geo<T> G;
       elem_geometry(cur, G);
       const MatDev mt = mats[cur.mid];
-      T w[10][3], out[10][3];
+      T w[10][3];
 #pragma unroll
       for (int k = 0; k < 10; ++k) {
 #pragma unroll
-        for (int c = 0; c < 3; ++c) {
-          w[k][c] = xs[3 * ln[k] + c];
-          out[k][c] = (T)0;
-        }
+        for (int c = 0; c < 3; ++c) w[k][c] = xs[3 * ln[k] + c];
       }
-      if (A.sK != (T)0) stiffness_apply<T>(G, (T)mt.lam, (T)mt.mu, A.sK, w, out);
-      if (A.sM != (T)0) mass_apply<T>((T)mt.rho * G.vol, A.sM, w, out);
+      // each node's force goes to the LDS accumulator as soon as it is
+      // complete (no 30-value force array held in registers)
       T eloc = (T)0;
-#pragma unroll
-      for (int k = 0; k < 10; ++k) {
-#pragma unroll
-        for (int c = 0; c < 3; ++c) {
-          atomicAdd(&ys[3 * ln[k] + c], (double)out[k][c]);
-          eloc += w[k][c] * out[k][c];
-        }
-      }
+      element_apply<T>(G, (T)mt.lam, (T)mt.mu, A.sK, A.sM * (T)mt.rho * G.vol, w, [&](int k, T f0, T f1, T f2) {
+        double* yk = &ys[3 * ln[k]];
+        atomicAdd(yk, (double)f0);
+        atomicAdd(yk + 1, (double)f1);
+        atomicAdd(yk + 2, (double)f2);
+        eloc += w[k][0] * f0 + w[k][1] * f1 + w[k][2] * f2;
+      });
       energy += (double)eloc;
     }
   }
