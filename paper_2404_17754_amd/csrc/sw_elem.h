@@ -76,10 +76,14 @@ SW_HD bool tet_geometry(const double x[4][3], Geo<T>& G) {
 // the vertex stresses S_k, the mass through per-component vertex and edge
 // sums.  Each node's force goes to sink(k, f0, f1, f2) as soon as it is
 // complete, so no 30-value force array is held (fewer live registers in the
-// tile passes, which scatter each force at once).
-template <typename T, typename Sink>
+// tile passes, which scatter each force at once).  STIFF / MASS leave out
+// a term whose coefficient the caller knows to be zero; fixed at compile
+// time, they leave the per-node code free of branches.  DYN also skips a
+// term whose coefficient is zero at run time (per element: branches in the
+// per-node code, but a smaller register footprint where that matters more).
+template <typename T, bool STIFF, bool MASS, bool DYN, typename Sink>
 SW_HD void element_apply(const Geo<T>& G, T lam, T mu, T sK, T sMV, const T w[10][3], Sink&& sink) {
-  const bool stiff = sK != (T)0, mass = sMV != (T)0;
+  const bool stiff = STIFF && (!DYN || sK != (T)0), mass = MASS && (!DYN || sMV != (T)0);
   T S[4][6];
   T Ssum[6] = {0, 0, 0, 0, 0, 0};
   if (stiff) {

@@ -77,53 +77,76 @@ __device__ __forceinline__ void elem_geometry(const ElemIn<float>& in, Geo<float
   G.vol = in.geo[9];
 }
 
-// Element and face work of tile t on the values gathered in LDS (xs, node
-// ids gid), accumulated into ys; returns the tile's share of x.A x (only the
-// CG passes use it).  Work-item i takes the tile's element i: the layout
-// has interleaved the elements so that consecutive ones rarely share a node
-// (few LDS atomic collisions) while their loads stay coalesced.  PF: software
+// Element work of tile t on the values gathered in LDS (xs, node ids gid),
+// accumulated into ys; returns the tile's share of x.A x (only the CG passes
+// use it).  Work-item i takes the tile's element i: the layout has
+// interleaved the elements so that consecutive ones rarely share a node (few
+// LDS atomic collisions) while their loads stay coalesced.  PF: software
 // pipeline, the next element's connectivity, geometry and material are
 // loaded before the current one is computed (FP32; in FP64 the registers
-// would halve the occupancy).
+// would halve the occupancy).  STIFF / MASS / DYN: which operator terms are
+// on, and whether each element checks its coefficients (element_apply).
+template <typename T, int NT, bool PF, bool STIFF, bool MASS, bool DYN>
+__device__ __forceinline__ double tile_element_loop(const MeshDev& m, const uint8_t* __restrict__ emat,
+                                                    const MatDev* __restrict__ mats, const TileArgs<T>& A, int t,
+                                                    const int32_t* gid, const T* xs, double* ys) {
+  double energy = 0.0;
+  const int eb = m.tile_elem_off[t];
+  const int n_e = m.tile_elem_off[t + 1] - eb;
+  auto elem_of = [&](int i) { return eb + i; };
+  ElemIn<T> nx;
+  int i = threadIdx.x;
+  if (i < n_e) load_elem(m, gid, emat, elem_of(i), nx);
+  constexpr bool kPrefetch = PF;
+  for (; i < n_e; i += NT) {
+    if (!kPrefetch && i != (int)threadIdx.x) load_elem(m, gid, emat, elem_of(i), nx);
+    const ElemIn<T> cur = nx;
+    if (kPrefetch && i + NT < n_e) load_elem(m, gid, emat, elem_of(i + NT), nx);
+    const int* ln = cur.ln;
+    Geo<T> G;
+    elem_geometry(cur, G);
+    const MatDev mt = mats[cur.mid];
+    T w[10][3];
+#pragma unroll
+    for (int k = 0; k < 10; ++k) {
+#pragma unroll
+      for (int c = 0; c < 3; ++c) w[k][c] = xs[3 * ln[k] + c];
+    }
+    // each node's force goes to the LDS accumulator as soon as it is
+    // complete (no 30-value force array held in registers)
+    T eloc = (T)0;
+    element_apply<T, STIFF, MASS, DYN>(G, (T)mt.lam, (T)mt.mu, A.sK, A.sM * (T)mt.rho * G.vol, w,
+                                  [&](int k, T f0, T f1, T f2) {
+                                    double* yk = &ys[3 * ln[k]];
+                                    atomicAdd(yk, (double)f0);
+                                    atomicAdd(yk + 1, (double)f1);
+                                    atomicAdd(yk + 2, (double)f2);
+                                    eloc += w[k][0] * f0 + w[k][1] * f1 + w[k][2] * f2;
+                                  });
+    energy += (double)eloc;
+  }
+  return energy;
+}
+
+// Element and face work of tile t (see tile_element_loop), plus the
+// boundary faces owned by the tile's elements.
 template <typename T, int NT, bool PF>
 __device__ __forceinline__ double tile_elements(const MeshDev& m, const uint8_t* __restrict__ emat,
                                                 const MatDev* __restrict__ mats, const TileArgs<T>& A, int t,
                                                 const int32_t* gid, const T* xs, double* ys) {
   double energy = 0.0;
-  if (A.sM != (T)0 || A.sK != (T)0) {
-    const int eb = m.tile_elem_off[t];
-    const int n_e = m.tile_elem_off[t + 1] - eb;
-    auto elem_of = [&](int i) { return eb + i; };
-    ElemIn<T> nx;
-    int i = threadIdx.x;
-    if (i < n_e) load_elem(m, gid, emat, elem_of(i), nx);
-    constexpr bool kPrefetch = PF;
-    for (; i < n_e; i += NT) {
-      if (!kPrefetch && i != (int)threadIdx.x) load_elem(m, gid, emat, elem_of(i), nx);
-      const ElemIn<T> cur = nx;
-      if (kPrefetch && i + NT < n_e) load_elem(m, gid, emat, elem_of(i + NT), nx);
-      const int* ln = cur.ln;
-      Geo<T> G;
-      elem_geometry(cur, G);
-      const MatDev mt = mats[cur.mid];
-      T w[10][3];
-#pragma unroll
-      for (int k = 0; k < 10; ++k) {
-#pragma unroll
-        for (int c = 0; c < 3; ++c) w[k][c] = xs[3 * ln[k] + c];
-      }
-      // each node's force goes to the LDS accumulator as soon as it is
-      // complete (no 30-value force array held in registers)
-      T eloc = (T)0;
-      element_apply<T>(G, (T)mt.lam, (T)mt.mu, A.sK, A.sM * (T)mt.rho * G.vol, w, [&](int k, T f0, T f1, T f2) {
-        double* yk = &ys[3 * ln[k]];
-        atomicAdd(yk, (double)f0);
-        atomicAdd(yk + 1, (double)f1);
-        atomicAdd(yk + 2, (double)f2);
-        eloc += w[k][0] * f0 + w[k][1] * f1 + w[k][2] * f2;
-      });
-      energy += (double)eloc;
-    }
+  if constexpr (sizeof(T) == 8) {
+    // FP64: per-element checks (the branch-free form needs more registers
+    // than the FP64 passes can spare; measured slower)
+    if (A.sK != (T)0 || A.sM != (T)0)
+      energy = tile_element_loop<T, NT, PF, true, true, true>(m, emat, mats, A, t, gid, xs, ys);
+  } else {
+    if (A.sK != (T)0 && A.sM != (T)0)
+      energy = tile_element_loop<T, NT, PF, true, true, false>(m, emat, mats, A, t, gid, xs, ys);
+    else if (A.sK != (T)0)
+      energy = tile_element_loop<T, NT, PF, true, false, false>(m, emat, mats, A, t, gid, xs, ys);
+    else if (A.sM != (T)0)
+      energy = tile_element_loop<T, NT, PF, false, true, false>(m, emat, mats, A, t, gid, xs, ys);
   }
   if (A.sC != (T)0 || A.vin != nullptr) {
     const int f1 = m.tile_face_off[t + 1];
