@@ -653,6 +653,7 @@ int apply_f32(sw_case* c, int op, const float* x, float* y, CgCtl* ctl, int iter
   A.a1 = 1.0f;
   A.xf = x;
   A.y = y;
+  A.n_mat = c->n_mat;
   launch_tile_f32(c->mesh->dev, c->emat, c->mats, A, ctl, iter, c->ctx->stream);
   LAUNCHED();
   return SW_OK;

@@ -72,6 +72,7 @@ struct TileArgs {
   const double* vin;   // 3 values or nullptr
   T* y;
   int accumulate;      // interior nodes: 0 overwrite, 1 add
+  int n_mat;           // materials in the table (0: not given)
 };
 
 // ---- several cases marched together (lanes) ------------------------------

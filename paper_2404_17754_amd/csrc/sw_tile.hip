@@ -22,6 +22,15 @@
 
 namespace sw {
 
+// Load through the constant address space: with a uniform index this is a
+// scalar load, which is not counted with the vector loads (those complete
+// in order, so waiting for one waits for every older one).  For the
+// per-tile offsets and counts, constant during a kernel.
+template <typename U>
+__device__ __forceinline__ U ldc(const U* p, int64_t i) {
+  return ((const __attribute__((address_space(4))) U*)p)[i];
+}
+
 // Per-element inputs fetched from global memory: tile-local connectivity,
 // material id, and the geometry.  FP64 recomputes the barycentric gradients
 // from the FP64 vertex coordinates (through the LDS node-id list); FP32
@@ -86,17 +95,24 @@ __device__ __forceinline__ void elem_geometry(const ElemIn<float>& in, Geo<float
 // loaded before the current one is computed (FP32; in FP64 the registers
 // would halve the occupancy).  STIFF / MASS / DYN: which operator terms are
 // on, and whether each element checks its coefficients (element_apply).
-template <typename T, int NT, bool PF, bool STIFF, bool MASS, bool DYN>
+// hook() runs once, right after the first element's loads are issued (the
+// pipelined pass issues its next tile's gather there, behind them).  MATL:
+// the material constants come from an LDS copy (matl: lam, mu, rho per
+// material) rather than from global memory, a load that would wait on the
+// element's material id.
+template <typename T, int NT, bool PF, bool STIFF, bool MASS, bool DYN, bool MATL, typename Hook>
 __device__ __forceinline__ double tile_element_loop(const MeshDev& m, const uint8_t* __restrict__ emat,
-                                                    const MatDev* __restrict__ mats, const TileArgs<T>& A, int t,
-                                                    const int32_t* gid, const T* xs, double* ys) {
+                                                    const MatDev* __restrict__ mats, const float* matl,
+                                                    const TileArgs<T>& A, int t, const int32_t* gid, const T* xs,
+                                                    double* ys, Hook&& hook) {
   double energy = 0.0;
-  const int eb = m.tile_elem_off[t];
-  const int n_e = m.tile_elem_off[t + 1] - eb;
+  const int eb = ldc(m.tile_elem_off, t);
+  const int n_e = ldc(m.tile_elem_off, t + 1) - eb;
   auto elem_of = [&](int i) { return eb + i; };
   ElemIn<T> nx;
   int i = threadIdx.x;
   if (i < n_e) load_elem(m, gid, emat, elem_of(i), nx);
+  hook();
   constexpr bool kPrefetch = PF;
   for (; i < n_e; i += NT) {
     if (!kPrefetch && i != (int)threadIdx.x) load_elem(m, gid, emat, elem_of(i), nx);
@@ -105,7 +121,17 @@ __device__ __forceinline__ double tile_element_loop(const MeshDev& m, const uint
     const int* ln = cur.ln;
     Geo<T> G;
     elem_geometry(cur, G);
-    const MatDev mt = mats[cur.mid];
+    T lam, mu, rho;
+    if constexpr (MATL) {
+      lam = matl[3 * cur.mid];
+      mu = matl[3 * cur.mid + 1];
+      rho = matl[3 * cur.mid + 2];
+    } else {
+      const MatDev& mt = mats[cur.mid];
+      lam = (T)mt.lam;
+      mu = (T)mt.mu;
+      rho = (T)mt.rho;
+    }
     T w[10][3];
 #pragma unroll
     for (int k = 0; k < 10; ++k) {
@@ -115,7 +141,7 @@ __device__ __forceinline__ double tile_element_loop(const MeshDev& m, const uint
     // each node's force goes to the LDS accumulator as soon as it is
     // complete (no 30-value force array held in registers)
     T eloc = (T)0;
-    element_apply<T, STIFF, MASS, DYN>(G, (T)mt.lam, (T)mt.mu, A.sK, A.sM * (T)mt.rho * G.vol, w,
+    element_apply<T, STIFF, MASS, DYN>(G, lam, mu, A.sK, A.sM * rho * G.vol, w,
                                   [&](int k, T f0, T f1, T f2) {
                                     double* yk = &ys[3 * ln[k]];
                                     atomicAdd(yk, (double)f0);
@@ -130,27 +156,32 @@ __device__ __forceinline__ double tile_element_loop(const MeshDev& m, const uint
 
 // Element and face work of tile t (see tile_element_loop), plus the
 // boundary faces owned by the tile's elements.
-template <typename T, int NT, bool PF>
+template <typename T, int NT, bool PF, bool MATL, typename Hook>
 __device__ __forceinline__ double tile_elements(const MeshDev& m, const uint8_t* __restrict__ emat,
-                                                const MatDev* __restrict__ mats, const TileArgs<T>& A, int t,
-                                                const int32_t* gid, const T* xs, double* ys) {
+                                                const MatDev* __restrict__ mats, const float* matl,
+                                                const TileArgs<T>& A, int t, const int32_t* gid, const T* xs,
+                                                double* ys, Hook&& hook) {
   double energy = 0.0;
   if constexpr (sizeof(T) == 8) {
     // FP64: per-element checks (the branch-free form needs more registers
     // than the FP64 passes can spare; measured slower)
     if (A.sK != (T)0 || A.sM != (T)0)
-      energy = tile_element_loop<T, NT, PF, true, true, true>(m, emat, mats, A, t, gid, xs, ys);
+      energy = tile_element_loop<T, NT, PF, true, true, true, MATL>(m, emat, mats, matl, A, t, gid, xs, ys, hook);
+    else
+      hook();
   } else {
     if (A.sK != (T)0 && A.sM != (T)0)
-      energy = tile_element_loop<T, NT, PF, true, true, false>(m, emat, mats, A, t, gid, xs, ys);
+      energy = tile_element_loop<T, NT, PF, true, true, false, MATL>(m, emat, mats, matl, A, t, gid, xs, ys, hook);
     else if (A.sK != (T)0)
-      energy = tile_element_loop<T, NT, PF, true, false, false>(m, emat, mats, A, t, gid, xs, ys);
+      energy = tile_element_loop<T, NT, PF, true, false, false, MATL>(m, emat, mats, matl, A, t, gid, xs, ys, hook);
     else if (A.sM != (T)0)
-      energy = tile_element_loop<T, NT, PF, false, true, false>(m, emat, mats, A, t, gid, xs, ys);
+      energy = tile_element_loop<T, NT, PF, false, true, false, MATL>(m, emat, mats, matl, A, t, gid, xs, ys, hook);
+    else
+      hook();
   }
   if (A.sC != (T)0 || A.vin != nullptr) {
-    const int f1 = m.tile_face_off[t + 1];
-    for (int f = m.tile_face_off[t] + threadIdx.x; f < f1; f += NT) {
+    const int f1 = ldc(m.tile_face_off, t + 1);
+    for (int f = ldc(m.tile_face_off, t) + threadIdx.x; f < f1; f += NT) {
       int ln[6];
       int64_t gn[6];
 #pragma unroll
@@ -206,14 +237,21 @@ __device__ __forceinline__ double tile_elements(const MeshDev& m, const uint8_t*
   return energy;
 }
 
+template <typename T, int NT, bool PF>
+__device__ __forceinline__ double tile_elements(const MeshDev& m, const uint8_t* __restrict__ emat,
+                                                const MatDev* __restrict__ mats, const TileArgs<T>& A, int t,
+                                                const int32_t* gid, const T* xs, double* ys) {
+  return tile_elements<T, NT, PF, false>(m, emat, mats, nullptr, A, t, gid, xs, ys, [] {});
+}
+
 // Results of tile t: interior nodes (one contiguous range) with plain
 // stores, shared nodes with address-sorted global atomics.
 template <typename T, int NT>
 __device__ __forceinline__ void tile_scatter(const MeshDev& m, const TileArgs<T>& A, int t, const int32_t* gid,
                                              const double* ys) {
-  const int nt = m.tile_node_off[t + 1] - m.tile_node_off[t];
-  const int nint = m.tile_nint[t];
-  const int64_t ib3 = 3 * (int64_t)m.tile_int_base[t];
+  const int nt = ldc(m.tile_node_off, t + 1) - ldc(m.tile_node_off, t);
+  const int nint = ldc(m.tile_nint, t);
+  const int64_t ib3 = 3 * (int64_t)ldc(m.tile_int_base, t);
   T* __restrict__ y = A.y;
   for (int k = threadIdx.x; k < 3 * nint; k += NT) {
     if (A.accumulate)
@@ -312,12 +350,19 @@ __global__ __launch_bounds__(NT) void k_tile_lanes(const TileLane<T>* __restrict
   tile_body<T, NT>(L.m, L.emat, L.mats, L.A, L.ctl, iter, w.y, smem_raw, sh);
 }
 
+// Largest material table the pipelined pass copies into LDS.
+constexpr int PIPE_MATS = 32;
+
 // FP32 operator pass of a CG iteration (input scaled by 1, no second input),
 // persistent and software-pipelined.  Each workgroup walks a run of tiles;
-// while it computes tile t it already loads the node ids and input values of
-// its next tile into registers (node by node, 12 contiguous bytes per node),
-// so a tile's gather latency hides behind the element work of the one
-// before.  XCD-aware: workgroup b runs on XCD b mod 8 (workgroups are dealt
+// while it computes tile t it already loads the input values of its next
+// tile into registers (node by node, 12 contiguous bytes per node), so a
+// tile's gather latency hides behind the element work of the one before.
+// Order of the loads, since a wait for a vector load also waits for every
+// older one: the node ids of tile t+1 are loaded at the end of tile t-1;
+// tile t's first element data goes out before the values of tile t+1, so
+// the element work waits only for its own data; per-tile offsets and counts
+// are scalar loads.  XCD-aware: workgroup b runs on XCD b mod 8 (workgroups are dealt
 // to the 8 XCDs round-robin) and takes its tiles from that XCD's contiguous
 // eighth of the tile list, so neighbouring tiles, which share nodes, meet in
 // the same L2.  NPT * NT must cover the largest tile.
@@ -347,9 +392,16 @@ __global__ __launch_bounds__(NT) void k_tile_pipe(MeshDev m, const uint8_t* __re
   int t = lo + slot;
   if (t >= hi) return;
   const float* __restrict__ x = A.x1;
+  // the material table, rounded to FP32, into LDS
+  __shared__ float matl[3 * PIPE_MATS];
+  for (int i = threadIdx.x; i < A.n_mat; i += NT) {
+    matl[3 * i] = (float)mats[i].lam;
+    matl[3 * i + 1] = (float)mats[i].mu;
+    matl[3 * i + 2] = (float)mats[i].rho;
+  }
   {
     // first tile: node ids and values straight into LDS
-    const int n0 = m.tile_node_off[t], nt = m.tile_node_off[t + 1] - n0;
+    const int n0 = ldc(m.tile_node_off, t), nt = ldc(m.tile_node_off, t + 1) - n0;
     for (int j = threadIdx.x; j < nt; j += NT) {
       const int32_t g = m.tile_nodes[n0 + j];
       gid[j] = g;
@@ -359,31 +411,41 @@ __global__ __launch_bounds__(NT) void k_tile_pipe(MeshDev m, const uint8_t* __re
         ys[3 * j + c] = 0.0;
       }
     }
-    __syncthreads();
   }
+  // node ids of tile tn (0 past the tile: a valid index, loaded and unused)
+  int32_t pg[NPT];
+  auto load_ids = [&](int tn, int& ntn) {
+    ntn = 0;
+    int n0 = 0;
+    if (tn < hi) {
+      n0 = ldc(m.tile_node_off, tn);
+      ntn = ldc(m.tile_node_off, tn + 1) - n0;
+    }
+#pragma unroll
+    for (int q = 0; q < NPT; ++q) {
+      const int j = threadIdx.x + q * NT;
+      pg[q] = j < ntn ? m.tile_nodes[n0 + j] : 0;
+    }
+  };
+  int ntn;
+  load_ids(t + slots, ntn);
+  __syncthreads();
   double energy = 0.0;
   for (;;) {
     const int tn = t + slots;
     const bool more = tn < hi;
-    int32_t pg[NPT];
+    // the next tile's values: loaded behind the first element's loads, so
+    // that the element work waits only for its own data
     float px[NPT][3];
-    int ntn = 0;
-    if (more) {
-      const int n0 = m.tile_node_off[tn];
-      ntn = m.tile_node_off[tn + 1] - n0;
-#pragma unroll
-      for (int q = 0; q < NPT; ++q) {
-        const int j = threadIdx.x + q * NT;
-        pg[q] = j < ntn ? m.tile_nodes[n0 + j] : 0;
-      }
+    auto gather_next = [&] {
 #pragma unroll
       for (int q = 0; q < NPT; ++q) {
         const int64_t g3 = 3 * (int64_t)pg[q];
 #pragma unroll
-        for (int c = 0; c < 3; ++c) px[q][c] = (threadIdx.x + q * NT < ntn) ? x[g3 + c] : 0.0f;
+        for (int c = 0; c < 3; ++c) px[q][c] = x[g3 + c];
       }
-    }
-    energy += tile_elements<float, NT, PF>(m, emat, mats, A, t, gid, xs, ys);
+    };
+    energy += tile_elements<float, NT, PF, true>(m, emat, mats, matl, A, t, gid, xs, ys, gather_next);
     __syncthreads();
     tile_scatter<float, NT>(m, A, t, gid, ys);
     __syncthreads();
@@ -400,6 +462,9 @@ __global__ __launch_bounds__(NT) void k_tile_pipe(MeshDev m, const uint8_t* __re
         }
       }
     }
+    // ids of the tile after next: their latency overlaps the barrier and
+    // the next tile's first element loads
+    load_ids(tn + slots, ntn);
     __syncthreads();
     t = tn;
   }
@@ -553,7 +618,7 @@ static void launch_tile(const MeshDev& m, const uint8_t* emat, const MatDev* mat
   const size_t lds = tile_lds<T>(m.max_tile_nodes);
   if constexpr (sizeof(T) == 4) {
     if (iter >= 0 && a.x2 == nullptr && a.a1 == 1.0f && a.accumulate == 0 && a.vin == nullptr &&
-        m.max_tile_nodes <= PIPE_NT * PIPE_NPT) {
+        m.max_tile_nodes <= PIPE_NT * PIPE_NPT && a.n_mat >= 1 && a.n_mat <= PIPE_MATS) {
       hipLaunchKernelGGL((k_tile_pipe<PIPE_NT, PIPE_NPT, SW_PIPE_PF>), dim3(pipe_grid(m.n_tiles)), dim3(PIPE_NT),
                          lds, s, m, emat, mats, a, ctl, iter);
       return;
