@@ -394,6 +394,7 @@ size_t mesh_layout(const HostLayout& L, Carver& cv, MeshDev* md) {
   auto tfo = cv.take<int32_t>(nT + 1);
   auto xyz = cv.take<double>(3 * L.n_nodes);
   auto geo32 = cv.take<float>(10 * L.tet_stride);
+  auto geo64 = cv.take<double>(10 * L.tet_stride);
   auto fconn = cv.take<int32_t>(6 * L.face_stride);
   auto fconn_loc = cv.take<uint16_t>(6 * L.face_stride);
   auto fel = cv.take<int32_t>(L.face_stride);
@@ -419,6 +420,7 @@ size_t mesh_layout(const HostLayout& L, Carver& cv, MeshDev* md) {
     md->tile_face_off = tfo;
     md->xyz = xyz;
     md->geo32 = geo32;
+    md->geo64 = geo64;
     md->fconn = fconn;
     md->fconn_loc = fconn_loc;
     md->face_elem = fel;
@@ -477,7 +479,7 @@ extern "C" int sw_mesh_create(sw_ctx* ctx, const sw_mesh_desc* d, void* ws, size
   HIPC(up(md.node_u2i, L.node_u2i, s));
   HIPC(up(md.node_i2u, L.node_i2u, s));
   HIPC(up(md.inv_valence, L.inv_valence, s));
-  launch_geom32(md, (float*)md.geo32, s);
+  launch_geom(md, (float*)md.geo32, (double*)md.geo64, s);
   HIPC(hipGetLastError());
   HIPC(hipStreamSynchronize(s));
   sw_mesh* m = new sw_mesh{ctx, md, d->n_nodes, d->n_tets, d->n_faces, L.elem_order, L.node_u2i, L.node_i2u};

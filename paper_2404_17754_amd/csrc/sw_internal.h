@@ -49,6 +49,7 @@ struct MeshDev {
   const int32_t* tile_face_off;  // [n_tiles + 1]
   const double* xyz;             // [n_nodes][3]
   const float* geo32;            // [10][tet_stride]: FP32 grad L1..L3 (9) and volume
+  const double* geo64;           // [10][tet_stride]: the same in FP64
   const int32_t* fconn;          // [6][face_stride]
   const uint16_t* fconn_loc;     // [6][face_stride]
   const int32_t* face_elem;      // [n_faces]
@@ -165,7 +166,7 @@ void launch_tile_f64(const MeshDev& m, const uint8_t* emat, const MatDev* mats, 
 void launch_tile_f32(const MeshDev& m, const uint8_t* emat, const MatDev* mats, const TileArgs<float>& a,
                      CgCtl* ctl, int iter, hipStream_t s);
 // FP32 element geometry for the FP32 operator (once per mesh).
-void launch_geom32(const MeshDev& m, float* geo32, hipStream_t s);
+void launch_geom(const MeshDev& m, float* geo32, double* geo64, hipStream_t s);
 // Diagonal 3x3 blocks (6 values per node) of cM M + cK K + cC C_abs.
 void launch_tile_diag(const MeshDev& m, const uint8_t* emat, const MatDev* mats, double cM, double cK, double cC,
                       double* diag6, hipStream_t s);

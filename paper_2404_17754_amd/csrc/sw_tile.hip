@@ -32,50 +32,40 @@ __device__ __forceinline__ U ldc(const U* p, int64_t i) {
 }
 
 // Per-element inputs fetched from global memory: tile-local connectivity,
-// material id, and the geometry.  FP64 recomputes the barycentric gradients
-// from the FP64 vertex coordinates (through the LDS node-id list); FP32
-// streams the precomputed FP32 gradients and volume (coalesced, no
-// dependent gather).
+// material id, and the precomputed barycentric gradients and volume in the
+// pass's precision (coalesced streams, no dependent gather).
 template <typename T>
-struct ElemIn;
-template <>
-struct ElemIn<double> {
+struct ElemIn {
   int ln[10];
-  double X[4][3];
-  int mid;
-};
-template <>
-struct ElemIn<float> {
-  int ln[10];
-  float geo[10];
+  T geo[10];
   int mid;
 };
 
-__device__ __forceinline__ void load_elem(const MeshDev& m, const int32_t* gid, const uint8_t* __restrict__ emat,
-                                          int e, ElemIn<double>& o) {
+template <typename T>
+__device__ __forceinline__ const T* geo_of(const MeshDev& m);
+template <>
+__device__ __forceinline__ const float* geo_of<float>(const MeshDev& m) {
+  return m.geo32;
+}
+template <>
+__device__ __forceinline__ const double* geo_of<double>(const MeshDev& m) {
+  return m.geo64;
+}
+
+template <typename T>
+__device__ __forceinline__ void load_elem(const MeshDev& m, const uint8_t* __restrict__ emat, int e, ElemIn<T>& o) {
+  const T* __restrict__ geo = geo_of<T>(m);
 #pragma unroll
   for (int k = 0; k < 10; ++k) o.ln[k] = m.conn_loc[k * m.tet_stride + e];
 #pragma unroll
-  for (int k = 0; k < 4; ++k) {
-    const int64_t g = gid[o.ln[k]];
-#pragma unroll
-    for (int d = 0; d < 3; ++d) o.X[k][d] = m.xyz[3 * g + d];
-  }
+  for (int k = 0; k < 10; ++k) o.geo[k] = geo[k * m.tet_stride + e];
   o.mid = emat[e];
 }
 
-__device__ __forceinline__ void load_elem(const MeshDev& m, const int32_t*, const uint8_t* __restrict__ emat, int e,
-                                          ElemIn<float>& o) {
-#pragma unroll
-  for (int k = 0; k < 10; ++k) o.ln[k] = m.conn_loc[k * m.tet_stride + e];
-#pragma unroll
-  for (int k = 0; k < 10; ++k) o.geo[k] = m.geo32[k * m.tet_stride + e];
-  o.mid = emat[e];
-}
-
-__device__ __forceinline__ void elem_geometry(const ElemIn<double>& in, Geo<double>& G) { tet_geometry<double>(in.X, G); }
-
-__device__ __forceinline__ void elem_geometry(const ElemIn<float>& in, Geo<float>& G) {
+// g_0 = -(g_1 + g_2 + g_3), summed in the order tet_geometry uses, so the
+// FP64 operator is the one computed from the coordinates bit for bit
+template <typename T>
+__device__ __forceinline__ void elem_geometry(const ElemIn<T>& in, Geo<T>& G) {
 #pragma unroll
   for (int d = 0; d < 3; ++d) {
     G.g[1][d] = in.geo[d];
@@ -111,13 +101,13 @@ __device__ __forceinline__ double tile_element_loop(const MeshDev& m, const uint
   auto elem_of = [&](int i) { return eb + i; };
   ElemIn<T> nx;
   int i = threadIdx.x;
-  if (i < n_e) load_elem(m, gid, emat, elem_of(i), nx);
+  if (i < n_e) load_elem<T>(m, emat, elem_of(i), nx);
   hook();
   constexpr bool kPrefetch = PF;
   for (; i < n_e; i += NT) {
-    if (!kPrefetch && i != (int)threadIdx.x) load_elem(m, gid, emat, elem_of(i), nx);
+    if (!kPrefetch && i != (int)threadIdx.x) load_elem<T>(m, emat, elem_of(i), nx);
     const ElemIn<T> cur = nx;
-    if (kPrefetch && i + NT < n_e) load_elem(m, gid, emat, elem_of(i + NT), nx);
+    if (kPrefetch && i + NT < n_e) load_elem<T>(m, emat, elem_of(i + NT), nx);
     const int* ln = cur.ln;
     Geo<T> G;
     elem_geometry(cur, G);
@@ -293,31 +283,38 @@ __device__ __forceinline__ void tile_body(const MeshDev& m, const uint8_t* __res
       ctl->rr[par ^ 1][threadIdx.x] = 0.0;
     }
   }
-  const int n0 = m.tile_node_off[t];
-  const int nt = m.tile_node_off[t + 1] - n0;
-  const int nint = m.tile_nint[t];
-  const int64_t ib3 = 3 * (int64_t)m.tile_int_base[t];
+  const int n0 = ldc(m.tile_node_off, t);
+  const int nt = ldc(m.tile_node_off, t + 1) - n0;
+  const int nint = ldc(m.tile_nint, t);
+  const int64_t ib3 = 3 * (int64_t)ldc(m.tile_int_base, t);
 
-  // node ids of the tile into LDS
-  for (int j = threadIdx.x; j < nt; j += NT) gid[j] = m.tile_nodes[n0 + j];
-  __syncthreads();
-  // gather xe = a1 x1 + a2 x2 for the tile's nodes; clear the accumulator
-  for (int k = threadIdx.x; k < 3 * nt; k += NT) {
-    int64_t gi;
-    if (k < 3 * nint) {
-      gi = ib3 + k;
-    } else {
-      const int j = k / 3;
-      gi = 3 * (int64_t)gid[j] + (k - 3 * j);
+  // gather xe = a1 x1 + a2 x2 for the tile's nodes and clear the
+  // accumulator, issued behind the first element's loads (the hook of
+  // tile_elements): the interior nodes are one contiguous range; the shared
+  // ones take their ids from the tile's node list (kept in LDS for the
+  // scatter)
+  auto gather = [&] {
+    for (int k = threadIdx.x; k < 3 * nint; k += NT) {
+      T v = A.a1 * A.x1[ib3 + k];
+      if (A.x2 != nullptr) v += A.a2 * A.x2[ib3 + k];
+      xs[k] = v;
+      ys[k] = 0.0;
     }
-    T v = A.a1 * A.x1[gi];
-    if (A.x2 != nullptr) v += A.a2 * A.x2[gi];
-    xs[k] = v;
-    ys[k] = 0.0;
-  }
-  __syncthreads();
-
-  double energy = tile_elements<T, NT, sizeof(T) == 4>(m, emat, mats, A, t, gid, xs, ys);
+    for (int j = nint + threadIdx.x; j < nt; j += NT) {
+      const int32_t g = m.tile_nodes[n0 + j];
+      gid[j] = g;
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        const int64_t gi = 3 * (int64_t)g + c;
+        T v = A.a1 * A.x1[gi];
+        if (A.x2 != nullptr) v += A.a2 * A.x2[gi];
+        xs[3 * j + c] = v;
+        ys[3 * j + c] = 0.0;
+      }
+    }
+    __syncthreads();
+  };
+  double energy = tile_elements<T, NT, sizeof(T) == 4, false>(m, emat, mats, nullptr, A, t, gid, xs, ys, gather);
   __syncthreads();
   tile_scatter<T, NT>(m, A, t, gid, ys);
   if (iter >= 0) {
@@ -651,9 +648,10 @@ void launch_tile_lanes_pipe_f32(const TileLane<float>* lanes, const int2* items,
 
 // ------------------------------------------------------------ geometry
 
-// FP32 barycentric gradients (rows of the inverse Jacobian, L1..L3) and the
-// volume of every element, from the FP64 coordinates: geo32[k][e], k < 10.
-__global__ __launch_bounds__(TPB) void k_geom32(MeshDev m, float* __restrict__ geo32) {
+// Barycentric gradients (rows of the inverse Jacobian, L1..L3) and the volume
+// of every element from the FP64 coordinates, in FP64 (geo64[k][e], k < 10)
+// and rounded to FP32 (geo32).
+__global__ __launch_bounds__(TPB) void k_geom(MeshDev m, float* __restrict__ geo32, double* __restrict__ geo64) {
   __shared__ int32_t gid[TILE_MAX_NODES];
   const int t = blockIdx.x;
   const int n0 = m.tile_node_off[t];
@@ -668,17 +666,19 @@ __global__ __launch_bounds__(TPB) void k_geom32(MeshDev m, float* __restrict__ g
     }
     Geo<double> G;
     tet_geometry<double>(X, G);
-    for (int d = 0; d < 3; ++d) {
-      geo32[(0 + d) * m.tet_stride + e] = (float)G.g[1][d];
-      geo32[(3 + d) * m.tet_stride + e] = (float)G.g[2][d];
-      geo32[(6 + d) * m.tet_stride + e] = (float)G.g[3][d];
+    for (int j = 0; j < 3; ++j) {
+      for (int d = 0; d < 3; ++d) {
+        geo64[(3 * j + d) * m.tet_stride + e] = G.g[1 + j][d];
+        geo32[(3 * j + d) * m.tet_stride + e] = (float)G.g[1 + j][d];
+      }
     }
+    geo64[9 * m.tet_stride + e] = G.vol;
     geo32[9 * m.tet_stride + e] = (float)G.vol;
   }
 }
 
-void launch_geom32(const MeshDev& m, float* geo32, hipStream_t s) {
-  hipLaunchKernelGGL(k_geom32, dim3(m.n_tiles), dim3(TPB), 0, s, m, geo32);
+void launch_geom(const MeshDev& m, float* geo32, double* geo64, hipStream_t s) {
+  hipLaunchKernelGGL(k_geom, dim3(m.n_tiles), dim3(TPB), 0, s, m, geo32, geo64);
 }
 
 // ------------------------------------------------------------ diagonal
