@@ -4,6 +4,8 @@ waveforms as the oracle's exact per-step solves and as each case stepped
 alone; every lane meets the true-residual tolerance on every step; lanes
 keep their own guesses, convergence and fallbacks; degenerate lanes (zero
 input) and bad batches are handled."""
+import dataclasses
+
 import numpy as np
 import pytest
 
@@ -134,3 +136,27 @@ def test_batch_rejects_bad_sets(sw, ctx):
     m = sw.Case(ctx, gm, c, precision="mixed", guess="mlp")
     with pytest.raises(sw.SwError, match="SW_ESTATE"):
         sw.Batch(ctx, [m]).step(1)
+
+
+def test_many_materials(sw, ctx):
+    """A case with more materials than the pipelined FP32 pass keeps in LDS
+    (32) marches on the other FP32 pass, alone and in a batch (the lane
+    pass reads the table from global memory); its extra table rows repeat
+    the bedrock, so its waveforms are those of the two-material case, each
+    within the solver tolerance of the oracle."""
+    cfg = cg.CONFIGS["small"]
+    mesh = cg.config_mesh(cfg)
+    c = cg.make_case(mesh, cfg, n_steps=20)
+    many = dataclasses.replace(c, mat=np.concatenate([c.mat, np.repeat(c.mat[-1:], 31, axis=0)]))
+    gm = sw.Mesh(ctx, mesh)
+    two = sw.Case(ctx, gm, c, precision="mixed", guess="proj")
+    wide = sw.Case(ctx, gm, many, precision="mixed", guess="proj")
+    lane = sw.Case(ctx, gm, many, precision="mixed", guess="proj")
+    two.step(20)
+    wide.step(20)
+    sw.Batch(ctx, [lane]).step(20)
+    ref = march.run_case(mesh, c, solver="lu")
+    for x in (wide, lane):
+        assert x.stats()["max_true_rel_res"] <= 1e-8
+        assert _relL2(x.waveforms(), ref.rec_v) < TOL_WAVE
+        assert _relL2(x.waveforms(), two.waveforms()) < TOL_WAVE
