@@ -916,7 +916,9 @@ int cg_loop(sw_case* c, CgCtl* ctl, int iter_base, int first_chunk, int* iters_o
 }
 
 // FP64 true residual of x: q = A x, r = b - q, rr_true into ctl64.  q keeps
-// A x unless zero_q is set.
+// A x unless zero_q is set; then its shared nodes are cleared, which is all
+// the next operator pass into q needs (it stores the interior nodes and
+// adds into the shared ones).
 int true_residual(sw_case* c, CgCtl* hctl, bool zero_q) {
   hipStream_t s = c->ctx->stream;
   const int64_t nd = 3 * c->mesh->n_nodes;
@@ -924,7 +926,10 @@ int true_residual(sw_case* c, CgCtl* hctl, bool zero_q) {
   int rc = apply_f64(c, SW_OP_A, c->x, c->q, nullptr, -1);
   if (rc) return rc;
   launch_true_residual(nd, c->b, c->q, c->r, c->ctl64, s);
-  if (zero_q) launch_fill_f64(nd, c->q, 0.0, s);
+  if (zero_q) {
+    const int64_t ni3 = 3 * c->mesh->dev.n_interior;
+    launch_fill_f64(nd - ni3, c->q + ni3, 0.0, s);
+  }
   LAUNCHED();
   return read_ctl(c, c->ctl64, hctl);
 }
@@ -1228,12 +1233,10 @@ int solve_step(sw_case* c, int* iters, int* outer, double* relres, int* flags) {
       // needs only a smaller reduction of the current residual
       const double need = c->rtol * std::sqrt(h.bb / h.rr_true);
       const double tol = std::min(0.5, std::max(c->inner_rtol, 0.3 * need));
-      launch_to_f32_scaled(nd, c->r, c->r32, c->ctl64, s);
       launch_fill_f64(sizeof(CgCtl) / 8, (double*)c->ctl32, 0.0, s);
       launch_fill_f64(1, &c->ctl32->bb, 1.0, s);
       launch_ctl_prepare(c->ctl32, tol, s);
-      launch_fill_f32(nd, c->d32, 0.0f, s);
-      launch_cg_init_f32(nn, c->r32, nullptr, c->pinv16, c->r32, c->z32, c->p32, nullptr, c->ctl32, s);
+      launch_ir_begin(nn, c->r, c->pinv16, c->r32, c->z32, c->p32, c->d32, c->ctl64, c->ctl32, s);
       LAUNCHED();
       int it = 0;
       rc = cg_loop<true>(c, c->ctl32, *iters, inner_est - 1, &it);

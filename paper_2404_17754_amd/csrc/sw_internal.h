@@ -199,7 +199,8 @@ void launch_norm2(int64_t n, const double* x, double* out, hipStream_t s);
 // r = b - q, rr_true -> ctl
 void launch_true_residual(int64_t n, const double* b, const double* q, double* r, CgCtl* ctl, hipStream_t s);
 // r32 = r64 / ||r64|| (||r64|| from ctl->rr_true, kept in ctl->scale)
-void launch_to_f32_scaled(int64_t n, const double* r64, float* r32, CgCtl* ctl, hipStream_t s);
+void launch_ir_begin(int64_t n_nodes, const double* r64, const __half* P, float* r32, float* z32, float* p32,
+                     float* d32, CgCtl* ctl64, CgCtl* ctl32, hipStream_t s);
 // x64 += ctl->scale * d32
 void launch_ir_update(int64_t n, double* x64, const float* d32, const CgCtl* ctl, hipStream_t s);
 

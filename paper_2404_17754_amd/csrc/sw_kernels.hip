@@ -55,7 +55,7 @@ __device__ __forceinline__ void bj_apply(const PT* __restrict__ P, int64_t i, co
 // (enough workgroups to fill 256 CUs several times over).
 static inline unsigned vgrid(int64_t n) {
   unsigned g = nblocks(n);
-  return g > 2048 ? 2048 : (g == 0 ? 1 : g);
+  return g > 8192 ? 8192 : (g == 0 ? 1 : g);
 }
 
 // r = b - q, z = P r, p = z, q = 0; rz[0], rr[0]
@@ -152,15 +152,34 @@ __device__ __forceinline__ void cg_dir_body(int64_t n, int par, int iter_abs, in
     if (threadIdx.x < NSLOT) ctl->pAp[threadIdx.x] = 0.0;
   }
   if (stop) return;
-  for (int64_t i = (int64_t)blockIdx.x * TPB + threadIdx.x; i < n; i += (int64_t)gridDim.x * TPB) {
-    T zv[3], pv[3];
-#pragma unroll
-    for (int c = 0; c < 3; ++c) {
-      zv[c] = z[3 * i + c];
-      pv[c] = p[3 * i + c];
+  if constexpr (sizeof(T) == 4) {
+    // elementwise over the 3n values, four at a time (16-byte accesses; the
+    // vectors start 256-byte aligned)
+    const int64_t n3 = 3 * n, n4 = n3 / 4;
+    const float4* __restrict__ z4 = reinterpret_cast<const float4*>(z);
+    float4* __restrict__ p4 = reinterpret_cast<float4*>(p);
+    for (int64_t i = (int64_t)blockIdx.x * TPB + threadIdx.x; i < n4; i += (int64_t)gridDim.x * TPB) {
+      const float4 a = z4[i];
+      float4 b = p4[i];
+      b.x = a.x + beta * b.x;
+      b.y = a.y + beta * b.y;
+      b.z = a.z + beta * b.z;
+      b.w = a.w + beta * b.w;
+      p4[i] = b;
     }
+    for (int64_t i = 4 * n4 + (int64_t)blockIdx.x * TPB + threadIdx.x; i < n3; i += (int64_t)gridDim.x * TPB)
+      p[i] = z[i] + beta * p[i];
+  } else {
+    for (int64_t i = (int64_t)blockIdx.x * TPB + threadIdx.x; i < n; i += (int64_t)gridDim.x * TPB) {
+      T zv[3], pv[3];
 #pragma unroll
-    for (int c = 0; c < 3; ++c) p[3 * i + c] = zv[c] + beta * pv[c];
+      for (int c = 0; c < 3; ++c) {
+        zv[c] = z[3 * i + c];
+        pv[c] = p[3 * i + c];
+      }
+#pragma unroll
+      for (int c = 0; c < 3; ++c) p[3 * i + c] = zv[c] + beta * pv[c];
+    }
   }
 }
 
@@ -260,18 +279,44 @@ void launch_true_residual(int64_t n, const double* b, const double* q, double* r
   hipLaunchKernelGGL(k_true_res, dim3(g), dim3(TPB), 0, s, n, b, q, r, ctl);
 }
 
-__global__ __launch_bounds__(TPB) void k_to_f32(int64_t n, const double* __restrict__ r, float* __restrict__ r32,
-                                                CgCtl* ctl) {
-  const double nr = sqrt(ctl->rr_true);
+// Start of a refinement round in one pass: the FP32 inner system's
+// right-hand side r32 = r / ||r|| (||r||^2 = rr_true of ctl64, kept as its
+// scale), the inner solution d32 = 0, and the CG start z = P r32, p = z
+// with r32.z and r32.r32 into slot ring 0 of ctl32 (cleared beforehand).
+__global__ __launch_bounds__(TPB) void k_ir_begin(int64_t n_nodes, const double* __restrict__ r64,
+                                                  const __half* __restrict__ P, float* __restrict__ r32,
+                                                  float* __restrict__ z32, float* __restrict__ p32,
+                                                  float* __restrict__ d32, CgCtl* ctl64, CgCtl* ctl32) {
+  __shared__ double sh[2 * TPB / 64];
+  const double nr = sqrt(ctl64->rr_true);
   const double inv = nr > 0.0 ? 1.0 / nr : 0.0;
-  if (blockIdx.x == 0 && threadIdx.x == 0) ctl->scale = nr;
-  for (int64_t i = (int64_t)blockIdx.x * TPB + threadIdx.x; i < n; i += (int64_t)gridDim.x * TPB)
-    r32[i] = (float)(r[i] * inv);
+  if (blockIdx.x == 0 && threadIdx.x == 0) ctl64->scale = nr;
+  double rz = 0.0, rr = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * TPB + threadIdx.x; i < n_nodes; i += (int64_t)gridDim.x * TPB) {
+    float rv[3], zv[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) rv[c] = (float)(r64[3 * i + c] * inv);
+    bj_apply<float, __half>(P, i, rv, zv);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      r32[3 * i + c] = rv[c];
+      z32[3 * i + c] = zv[c];
+      p32[3 * i + c] = zv[c];
+      d32[3 * i + c] = 0.0f;
+      rz += (double)rv[c] * (double)zv[c];
+      rr += (double)rv[c] * (double)rv[c];
+    }
+  }
+  block_sum2(rz, rr, sh);
+  if (threadIdx.x == 0) {
+    atomic_add(&ctl32->rz[0][blockIdx.x % NSLOT], rz);
+    atomic_add(&ctl32->rr[0][blockIdx.x % NSLOT], rr);
+  }
 }
-void launch_to_f32_scaled(int64_t n, const double* r64, float* r32, CgCtl* ctl, hipStream_t s) {
-  unsigned g = nblocks(n);
-  if (g > 8192) g = 8192;
-  hipLaunchKernelGGL(k_to_f32, dim3(g), dim3(TPB), 0, s, n, r64, r32, ctl);
+void launch_ir_begin(int64_t n_nodes, const double* r64, const __half* P, float* r32, float* z32, float* p32,
+                     float* d32, CgCtl* ctl64, CgCtl* ctl32, hipStream_t s) {
+  hipLaunchKernelGGL(k_ir_begin, dim3(vgrid(n_nodes)), dim3(TPB), 0, s, n_nodes, r64, P, r32, z32, p32, d32, ctl64,
+                     ctl32);
 }
 
 __global__ __launch_bounds__(TPB) void k_ir_update(int64_t n, double* __restrict__ x, const float* __restrict__ d,
