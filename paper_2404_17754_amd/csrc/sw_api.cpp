@@ -180,6 +180,11 @@ struct sw_case {
   int proj_dim = 0, proj_count = 0, proj_head = -1;
   double *projX = nullptr, *projY = nullptr, *proj_part = nullptr, *proj_out = nullptr, *proj_theta = nullptr;
   std::vector<double> projG, proj_h, proj_th;
+  // slots stored since the last projection whose Gram rows are still to be
+  // computed (with the next projection's pass over the ring), and the host
+  // rows of all but the last of them
+  std::vector<int> proj_pend;
+  std::vector<double> proj_rows;
   // host state
   int64_t step = 0;
   int hist_head = 3, hist_count = 0;
@@ -528,7 +533,7 @@ static size_t case_layout(const sw_mesh* m, const sw_case_desc* d, Carver& cv, s
   if (L > 0) {
     pX = cv.take<double>((size_t)L * nd);
     pY = cv.take<double>((size_t)L * nd);
-    ppart = cv.take<double>((size_t)PROJ_BLOCKS * L);
+    ppart = cv.take<double>((size_t)PROJ_BLOCKS * 2 * L);
     pout = cv.take<double>(2 * L);
     pth = cv.take<double>(L);
   }
@@ -782,6 +787,8 @@ extern "C" int sw_case_create(sw_ctx* ctx, sw_mesh* m, const sw_case_desc* d, vo
     c->projG.assign((size_t)c->proj_dim * c->proj_dim, 0.0);
     c->proj_h.assign(2 * (size_t)c->proj_dim, 0.0);
     c->proj_th.assign(c->proj_dim, 0.0);
+    c->proj_rows.assign((size_t)c->proj_dim * c->proj_dim, 0.0);
+    c->proj_pend.clear();
     HIPX(hipGetLastError());
   }
   if (c->nbh) {
@@ -829,6 +836,7 @@ extern "C" int sw_case_set_state(sw_case* c, const double* u, const double* v, c
   c->nb_head = 3;
   c->proj_count = 0;
   c->proj_head = -1;
+  c->proj_pend.clear();
   if (c->proj_dim > 0) std::fill(c->projG.begin(), c->projG.end(), 0.0);
   return SW_OK;
 }
@@ -1029,13 +1037,30 @@ void psd_solve(int m, const double* G, int ldg, const double* h, double* theta, 
   for (int i = 0; i < m; ++i) theta[i] = d[i] * ts[i];
 }
 
-// Projection guess, first half: X_i . b for the ring, copied to the host.
+// Projection guess, first half: X_i . b for the ring, copied to the host,
+// together with the Gram rows X_i . A X_s = X_i . Y_s of the slots stored
+// since the last projection (the last of them in the same pass over the
+// ring as X_i . b).
 int proj_begin(sw_case* c) {
   hipStream_t s = c->ctx->stream;
+  const int L = c->proj_dim;
   const int64_t nd = 3 * c->mesh->n_nodes;
-  launch_proj_dots(c->proj_dim, nd, c->projX, c->b, nullptr, c->proj_part, c->proj_out, s);
+  const int np = (int)c->proj_pend.size();
+  for (int k = 0; k + 1 < np; ++k) {
+    const int p = c->proj_pend[k];
+    launch_proj_dots(L, nd, c->projX, c->projY + (size_t)p * nd, nullptr, c->proj_part, c->proj_out, s);
+    HIPC(hipMemcpyAsync(c->proj_rows.data() + (size_t)p * L, c->proj_out, L * sizeof(double),
+                        hipMemcpyDeviceToHost, s));
+  }
+  if (np > 0) {
+    const int p = c->proj_pend[np - 1];
+    launch_proj_dots2(L, nd, c->projX, c->b, c->projY + (size_t)p * nd, c->proj_part, c->proj_out, s);
+  } else {
+    launch_proj_dots(L, nd, c->projX, c->b, nullptr, c->proj_part, c->proj_out, s);
+  }
   LAUNCHED();
-  HIPC(hipMemcpyAsync(c->proj_h.data(), c->proj_out, c->proj_dim * sizeof(double), hipMemcpyDeviceToHost, s));
+  HIPC(hipMemcpyAsync(c->proj_h.data(), c->proj_out, (np > 0 ? 2 : 1) * L * sizeof(double), hipMemcpyDeviceToHost,
+                      s));
   return SW_OK;
 }
 
@@ -1046,6 +1071,18 @@ int proj_finish(sw_case* c, bool with_res) {
   hipStream_t s = c->ctx->stream;
   const int L = c->proj_dim;
   const int64_t nd = 3 * c->mesh->n_nodes;
+  // Gram rows and columns of the newly stored slots (A is symmetric and the
+  // images are exact, so X_i . A X_p = X_p . A X_i)
+  const int np = (int)c->proj_pend.size();
+  for (int k = 0; k < np; ++k) {
+    const int p = c->proj_pend[k];
+    const double* row = k + 1 < np ? c->proj_rows.data() + (size_t)p * L : c->proj_h.data() + L;
+    for (int i = 0; i < L; ++i) {
+      c->projG[(size_t)i * L + p] = row[i];
+      c->projG[(size_t)p * L + i] = row[i];
+    }
+  }
+  c->proj_pend.clear();
   int idx[PROJ_MAX];
   const int m = c->proj_count;
   for (int j = 0; j < m; ++j) idx[j] = ((c->proj_head - j) % L + L) % L;
@@ -1068,8 +1105,8 @@ int proj_finish(sw_case* c, bool with_res) {
 }
 
 // After a converged step (x = du, r = b - A du): du and A du = b - r enter
-// the ring, and the new row of the Gram matrix is computed on the device.
-int proj_record_begin(sw_case* c) {
+// the ring; the slot's Gram row waits for the next projection.
+int proj_record(sw_case* c) {
   hipStream_t s = c->ctx->stream;
   const int L = c->proj_dim;
   const int64_t nd = 3 * c->mesh->n_nodes;
@@ -1077,23 +1114,13 @@ int proj_record_begin(sw_case* c) {
   double* Xs = c->projX + (size_t)sl * nd;
   double* Ys = c->projY + (size_t)sl * nd;
   launch_proj_store(nd, c->x, c->b, c->r, Xs, Ys, s);
-  launch_proj_dots(L, nd, c->projX, Ys, nullptr, c->proj_part, c->proj_out, s);
   LAUNCHED();
-  HIPC(hipMemcpyAsync(c->proj_h.data(), c->proj_out, L * sizeof(double), hipMemcpyDeviceToHost, s));
+  auto& pend = c->proj_pend;
+  pend.erase(std::remove(pend.begin(), pend.end(), sl), pend.end());
+  pend.push_back(sl);
   c->proj_head = sl;
   c->proj_count = std::min(c->proj_count + 1, L);
   return SW_OK;
-}
-
-// After the synchronisation: the Gram row and column of the new slot
-// (X_i . A X_s = X_s . A X_i: A is symmetric and the images are exact).
-void proj_record_finish(sw_case* c) {
-  const int L = c->proj_dim, sl = c->proj_head;
-  for (int i = 0; i < L; ++i) {
-    const double g = c->proj_h[i];
-    c->projG[(size_t)i * L + sl] = g;
-    c->projG[(size_t)sl * L + i] = g;
-  }
 }
 
 // Guess kind for the coming step of c.
@@ -1275,7 +1302,7 @@ extern "C" int sw_case_step(sw_case* c, int32_t n) {
       c->samp_rows += c->samp_per_step;
     }
     const bool rec_proj = c->proj_dim > 0 && c->last_bb > 0.0 && !(flags & SW_FLAG_NONFINITE);
-    if (rec_proj && (rc = proj_record_begin(c))) return rc;
+    if (rec_proj && (rc = proj_record(c))) return rc;
     const int head = (c->hist_head + 1) & 3;
     launch_newmark(nd, c->dt, c->x, c->u, c->v, c->a, c->hist + head * nd, s);
     launch_record(c->n_rec, c->rec, c->v, c->wave + c->step * 3 * c->n_rec, s);
@@ -1294,7 +1321,6 @@ extern "C" int sw_case_step(sw_case* c, int32_t n) {
     HIPC(hipMemcpyAsync(c->log_it + c->step, &it32, 4, hipMemcpyHostToDevice, s));
     HIPC(hipMemcpyAsync(c->log_rel + c->step, &rel, 8, hipMemcpyHostToDevice, s));
     HIPC(hipStreamSynchronize(s));
-    if (rec_proj) proj_record_finish(c);
     c->step += 1;
     c->last_iters = std::max(2, iters);
     c->stats.steps += 1;
@@ -1975,7 +2001,6 @@ int batch_step_once(sw_batch* b) {
     LAUNCHED();
   }
   // training samples, projection ring, Newmark update, receivers, logs
-  std::vector<char> rec_proj(n, 0);
   for (int l = 0; l < n; ++l) {
     sw_case* c = b->cases[l];
     if (c->samp && c->hist_count >= 4 && c->nb_count >= 4) {
@@ -1984,8 +2009,8 @@ int batch_step_once(sw_batch* b) {
       c->samp_rows += c->samp_per_step;
     }
     c->last_bb = b->info[l].bb;
-    rec_proj[l] = c->proj_dim > 0 && c->last_bb > 0.0 && !(flags[l] & SW_FLAG_NONFINITE);
-    if (rec_proj[l] && (rc = proj_record_begin(c))) return rc;
+    const bool rec_proj = c->proj_dim > 0 && c->last_bb > 0.0 && !(flags[l] & SW_FLAG_NONFINITE);
+    if (rec_proj && (rc = proj_record(c))) return rc;
     b->st[l].active = 1;
     b->st[l].iters = iters[l];
     b->st[l].rel = rel[l];
@@ -2012,7 +2037,6 @@ int batch_step_once(sw_batch* b) {
   HIPC(hipStreamSynchronize(s));
   for (int l = 0; l < n; ++l) {
     sw_case* c = b->cases[l];
-    if (rec_proj[l]) proj_record_finish(c);
     c->step += 1;
     c->last_iters = std::max(2, iters[l]);
     c->stats.steps += 1;

@@ -258,6 +258,10 @@ constexpr int PROJ_BLOCKS = 1024; // workgroups of a dot-product pass
 // holds PROJ_BLOCKS * L doubles of workgroup partials
 void launch_proj_dots(int L, int64_t n, const double* R, const double* v, const double* w, double* part,
                       double* out, hipStream_t s);
+// out[i] = R_i . v1 and out[L + i] = R_i . v2 in one pass over the ring;
+// part holds PROJ_BLOCKS * 2L doubles
+void launch_proj_dots2(int L, int64_t n, const double* R, const double* v1, const double* v2, double* part,
+                       double* out, hipStream_t s);
 // x = sum_i theta[i] X_i (theta on the device)
 void launch_proj_combine(int L, int64_t n, const double* X, const double* theta, double* x, hipStream_t s);
 // x = sum_i theta[i] X_i, r = b - sum_i theta[i] Y_i, *rr_out = r.r

@@ -48,6 +48,43 @@ __global__ __launch_bounds__(TPB) void k_proj_dots(int64_t n, const double* __re
   }
 }
 
+// The same for two right-hand vectors in one pass over the ring:
+// part[blk * 2L + i] from v1, part[blk * 2L + L + i] from v2.
+template <int L>
+__global__ __launch_bounds__(TPB) void k_proj_dots2(int64_t n, const double* __restrict__ R,
+                                                    const double* __restrict__ v1, const double* __restrict__ v2,
+                                                    double* __restrict__ part) {
+  __shared__ double sh[2 * L][TPB / 64];
+  double a1[L], a2[L];
+#pragma unroll
+  for (int i = 0; i < L; ++i) a1[i] = a2[i] = 0.0;
+  for (int64_t k = (int64_t)blockIdx.x * TPB + threadIdx.x; k < n; k += (int64_t)gridDim.x * TPB) {
+    const double t1 = v1[k], t2 = v2[k];
+#pragma unroll
+    for (int i = 0; i < L; ++i) {
+      const double x = R[(int64_t)i * n + k];
+      a1[i] += x * t1;
+      a2[i] += x * t2;
+    }
+  }
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+#pragma unroll
+  for (int i = 0; i < L; ++i) {
+    const double s1 = wave_sum(a1[i]), s2 = wave_sum(a2[i]);
+    if (lane == 0) {
+      sh[i][wid] = s1;
+      sh[L + i][wid] = s2;
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x < 2 * L) {
+    double s = 0.0;
+#pragma unroll
+    for (int j = 0; j < TPB / 64; ++j) s += sh[threadIdx.x][j];
+    part[(int64_t)blockIdx.x * 2 * L + threadIdx.x] = s;
+  }
+}
+
 // out[i] = sum_b part[b * L + i], one workgroup, fixed order
 __global__ __launch_bounds__(TPB) void k_proj_reduce(int nb, int L, const double* __restrict__ part,
                                                      double* __restrict__ out) {
@@ -137,6 +174,24 @@ void launch_proj_dots(int L, int64_t n, const double* R, const double* v, const 
       return;
   }
   hipLaunchKernelGGL(k_proj_reduce, dim3(1), dim3(TPB), 0, s, (int)g, L, part, out);
+}
+
+void launch_proj_dots2(int L, int64_t n, const double* R, const double* v1, const double* v2, double* part,
+                       double* out, hipStream_t s) {
+  const unsigned g = proj_grid(n);
+  switch (L) {
+#define SW_PROJ_CASE(K)                                                                          \
+  case K:                                                                                        \
+    hipLaunchKernelGGL(k_proj_dots2<K>, dim3(g), dim3(TPB), 0, s, n, R, v1, v2, part);           \
+    break;
+    SW_PROJ_CASE(2) SW_PROJ_CASE(3) SW_PROJ_CASE(4) SW_PROJ_CASE(5) SW_PROJ_CASE(6) SW_PROJ_CASE(7)
+    SW_PROJ_CASE(8) SW_PROJ_CASE(9) SW_PROJ_CASE(10) SW_PROJ_CASE(11) SW_PROJ_CASE(12) SW_PROJ_CASE(13)
+    SW_PROJ_CASE(14) SW_PROJ_CASE(15) SW_PROJ_CASE(16)
+#undef SW_PROJ_CASE
+    default:
+      return;
+  }
+  hipLaunchKernelGGL(k_proj_reduce, dim3(1), dim3(TPB), 0, s, (int)g, 2 * L, part, out);
 }
 
 void launch_proj_combine(int L, int64_t n, const double* X, const double* theta, double* x, hipStream_t s) {
