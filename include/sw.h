@@ -214,7 +214,8 @@ SW_API int sw_case_waveform_device(const sw_case* c, const double** out);
 /* y = op x for device vectors of 3*n_nodes doubles (op: SW_OP_*),
  * synchronous.  For testing and for callers composing their own solvers. */
 SW_API int sw_case_apply(sw_case* c, int32_t op, const double* x_dev, double* y_dev);
-/* Same with the FP32 operator used by the SW_MIXED_FP32 inner solve. */
+/* Same with the FP32 operator used by the SW_MIXED_FP32 inner solve; for
+ * SW_OP_A it runs the very pass an inner CG iteration launches. */
 SW_API int sw_case_apply_f32(sw_case* c, int32_t op, const float* x_dev, float* y_dev);
 /* Right-hand side b of the next step (from the current state) into y_dev. */
 SW_API int sw_case_rhs(sw_case* c, double* y_dev);

@@ -1396,7 +1396,16 @@ extern "C" int sw_case_apply_f32(sw_case* c, int32_t op, const float* x, float* 
   float* yi = (float*)c->z;
   launch_permute_f32(nn, 3, x, c->mesh->dev.node_i2u, xi, s);
   launch_fill_f32(3 * nn, yi, 0.0f, s);
-  int rc = apply_f32(c, op, xi, yi, nullptr, -1);
+  int rc;
+  if (op == SW_OP_A) {
+    // as in an inner CG iteration (past the first): a fresh control block,
+    // so the pass runs in full (the case's inner control block is free
+    // between steps)
+    launch_fill_f64(sizeof(CgCtl) / 8, (double*)c->ctl32, 0.0, s);
+    rc = apply_f32(c, op, xi, yi, c->ctl32, 1);
+  } else {
+    rc = apply_f32(c, op, xi, yi, nullptr, -1);
+  }
   if (rc) return rc;
   launch_permute_f32(nn, 3, yi, c->mesh->dev.node_u2i, y, s);
   LAUNCHED();
