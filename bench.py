@@ -20,7 +20,9 @@ histories that the solver generates for separate training models, 200 x
 as one batch) and the plain FP64 PCG (zero guess), and the CPU oracle on a
 bounded sample of the workload.  --batched K adds a study of K candidate
 models per mesh on the three uneven meshes of the batched workload, marched
-case by case and as one batch.
+case by case and as one batch; --guess-study N marches N held-out models of
+the 300 x 300 x 100 m mesh with the extrapolated, learned and projected
+guesses; --fit-study S runs the input estimation of Section 2.
 
 Prints one JSON line with the metric, the roofline of the dominant kernel
 (algorithmic flops and bytes / HIP-event-timed mean duration of its full
@@ -107,15 +109,15 @@ def cpu_baseline(cfg_name, dof_target, steps=4):
                        f"one thread (BLAS limited to 1), host has {os.cpu_count()} logical CPUs")}
 
 
-def train_network(sw, cg, ctx, cfg, n_cases, n_steps, train_steps, per_step=8192):
-    """Histories of `n_cases` training models (200 x 200 x 100 m boxes with
-    the workload's cells, time step and input; seeded interface fields of
-    amplitude 5-20 m and correlation 50-200 m) marched together as one batch
-    with the polynomial guess, sampled, then Adam on the GPU."""
+def train_network(sw, cg, ctx, cfg, n_cases, n_steps, train_steps, per_step=8192, box=(200.0, 200.0, 100.0)):
+    """Histories of `n_cases` training models (boxes of `box` with the
+    workload's cells, time step and input; seeded interface fields of
+    amplitude 5-20 m and correlation 50-200 m, seeds 500 on) marched together
+    as one batch with the polynomial guess, sampled, then Adam on the GPU."""
     import numpy as np
     import torch
     t0 = time.perf_counter()
-    tcfg = cg.BoxConfig("train", (200.0, 200.0, 100.0), cfg.cell, 30.0, (5.0, 20.0), (50.0, 200.0), cfg.freqs,
+    tcfg = cg.BoxConfig("train", box, cfg.cell, 30.0, (5.0, 20.0), (50.0, 200.0), cfg.freqs,
                         cfg.t0, cfg.dt, n_steps, 4, 500)
     tmesh = cg.config_mesh(tcfg)
     gtm = sw.Mesh(ctx, tmesh)
@@ -132,7 +134,8 @@ def train_network(sw, cg, ctx, cfg, n_cases, n_steps, train_steps, per_step=8192
     losses = net.train(S, steps=train_steps, batch=per_step, lr=2e-3, seed=5)
     torch.cuda.synchronize()
     t2 = time.perf_counter()
-    info = {"training_models": n_cases, "mesh": f"200x200x100 m, {tmesh.n_tets} tets", "steps_each": n_steps,
+    info = {"training_models": n_cases, "mesh": f"{box[0]:.0f}x{box[1]:.0f}x{box[2]:.0f} m, {tmesh.n_tets} tets",
+            "steps_each": n_steps,
             "rows": int(S.shape[0]), "adam_steps": train_steps, "batch": per_step,
             "loss_first20": float(np.mean(losses[:20])), "loss_last20": float(np.mean(losses[-20:])),
             "collect_s": round(t1 - t0, 2), "train_s": round(t2 - t1, 2),
@@ -142,11 +145,13 @@ def train_network(sw, cg, ctx, cfg, n_cases, n_steps, train_steps, per_step=8192
     return net, info
 
 
-def batched_study(sw, cg, ctx, per_mesh, steps, proj_dim):
+def batched_study(sw, cg, ctx, per_mesh, steps, proj_dim, legs=("seq", "batched", "plain")):
     """Candidate models on the three uneven meshes of the batched workload
     (200/300/400 x 100 m boxes, 5 m cells; seeded interface fields), marched
-    `steps` steps from rest with the projection guess: once case by case,
-    once as one batch.  Returns the two rates in case-timesteps/s."""
+    `steps` steps from rest with the projection guess: case by case ("seq"),
+    as one batch ("batched") and case by case with plain FP64 PCG and a zero
+    guess ("plain"), the legs asked for.  Returns the rates in
+    case-timesteps/s."""
     import numpy as np
     import torch
     meshes, cases = [], []
@@ -175,17 +180,67 @@ def batched_study(sw, cg, ctx, per_mesh, steps, proj_dim):
         torch.cuda.empty_cache()
         return len(cases) * steps / dt, its, worst
 
-    seq, its_s, _ = run(False)
-    bat, its_b, worst = run(True)
-    plain, its_p, _ = run(False, precision="fp64", guess="zero")
-    return {"meshes": [f"{n}: {t} tets" for n, t in meshes], "cases": len(cases), "steps": steps,
-            "guess": f"proj (L={proj_dim})", "sequential_case_timesteps_per_s": round(seq, 2),
-            "batched_case_timesteps_per_s": round(bat, 2), "speedup": round(bat / seq, 3),
-            "plain_fp64_sequential_case_timesteps_per_s": round(plain, 2),
-            "batched_vs_plain_fp64": round(bat / plain, 3),
-            "cg_iters_per_step": {"sequential": round(its_s, 2), "batched": round(its_b, 2),
-                                  "plain_fp64": round(its_p, 2)},
-            "max_true_rel_res": worst}
+    out = {"meshes": [f"{n}: {t} tets" for n, t in meshes], "cases": len(cases), "steps": steps,
+           "guess": f"proj (L={proj_dim})", "cg_iters_per_step": {}}
+    worst = 0.0
+    if "seq" in legs:
+        seq, its, w = run(False)
+        out["sequential_case_timesteps_per_s"] = round(seq, 2)
+        out["cg_iters_per_step"]["sequential"] = round(its, 2)
+        worst = max(worst, w)
+    if "batched" in legs:
+        bat, its, w = run(True)
+        out["batched_case_timesteps_per_s"] = round(bat, 2)
+        out["cg_iters_per_step"]["batched"] = round(its, 2)
+        worst = max(worst, w)
+    if "plain" in legs:
+        plain, its, _ = run(False, precision="fp64", guess="zero")
+        out["plain_fp64_sequential_case_timesteps_per_s"] = round(plain, 2)
+        out["cg_iters_per_step"]["plain_fp64"] = round(its, 2)
+    if "seq" in legs and "batched" in legs:
+        out["speedup"] = round(bat / seq, 3)
+    if "plain" in legs and "batched" in legs:
+        out["batched_vs_plain_fp64"] = round(bat / plain, 3)
+    out["max_true_rel_res"] = worst
+    return out
+
+
+def guess_study(sw, cg, ctx, net, n_models, steps, proj_dim):
+    """The learned guess on held-out candidate models: `n_models` models of
+    the 300 x 300 x 100 m mesh (5 m cells; seeded interface fields of the
+    batched workload, seeds unseen in training), each marched `steps` steps
+    from rest once per guess (extrapolation, the trained network, the
+    projection), every guess as one batch.  CG iterations per step (mean,
+    median, 95th percentile over models and steps), the worst true relative
+    residual and the batch's case-timesteps/s."""
+    import numpy as np
+    import torch
+    cfg = cg.CONFIGS["batch300"]
+    mesh = cg.config_mesh(cfg)
+    gm = sw.Mesh(ctx, mesh)
+    models = [cg.make_case(mesh, cfg, seed=2000 + k, n_steps=steps) for k in range(n_models)]
+    out = {"mesh": f"300x300x100 m, {mesh.n_tets} tets, {3 * mesh.n_nodes} DOF", "models": n_models,
+           "seeds": f"2000-{2000 + n_models - 1}", "steps": steps}
+    for g in ("poly", "mlp", "proj"):
+        lanes = [sw.Case(ctx, gm, c, precision="mixed", guess=g, proj_dim=proj_dim) for c in models]
+        if g == "mlp":
+            for lane in lanes:
+                lane.attach_mlp(net)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        sw.Batch(ctx, lanes).step(steps)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        its = np.concatenate([lane.step_log()[0] for lane in lanes]).astype(np.float64)
+        out[g] = {"cg_iters_per_step": round(float(its.mean()), 2), "p50": float(np.percentile(its, 50)),
+                  "p95": float(np.percentile(its, 95)),
+                  "max_true_rel_res": float(max(lane.stats()["max_true_rel_res"] for lane in lanes)),
+                  "fallback_models": int(sum(1 for lane in lanes if lane.stats()["flags"] & 4)),
+                  "case_timesteps_per_s": round(n_models * steps / dt, 2)}
+        del lanes
+        torch.cuda.empty_cache()
+    out["mlp_vs_poly_iters"] = round(out["mlp"]["cg_iters_per_step"] / out["poly"]["cg_iters_per_step"], 4)
+    return out
 
 
 def fit_study(sw, cg, ctx, n_steps, stride, proj_dim):
@@ -265,9 +320,15 @@ def main():
     ap.add_argument("--batched", type=int, default=0,
                     help="cases per mesh of an extra batched-vs-sequential study on the 200/300/400 m meshes")
     ap.add_argument("--batched-steps", type=int, default=30)
+    ap.add_argument("--batched-legs", default="seq,batched,plain",
+                    help="legs of the batched study: seq, batched, plain (comma separated)")
+    ap.add_argument("--guess-study", type=int, default=0,
+                    help="held-out models of the 300 m mesh for the learned-guess study (0: none)")
+    ap.add_argument("--guess-study-steps", type=int, default=100)
     ap.add_argument("--fit-study", type=int, default=0,
                     help="steps of an extra input-estimation study (Green's runs + fit) on the 300 m mesh (0 = skip)")
     ap.add_argument("--train-cases", type=int, default=4)
+    ap.add_argument("--train-box", default="200,200,100", help="training models' box (m)")
     ap.add_argument("--train-steps", type=int, default=150)
     ap.add_argument("--adam-steps", type=int, default=3000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -301,8 +362,9 @@ def main():
     t_up = time.perf_counter() - t_up
 
     net, train_info = None, None
-    if args.guess == "mlp" or (args.compare_steps > 0 and not args.no_mlp_compare):
-        net, train_info = train_network(sw, cg, ctx, cfg, args.train_cases, args.train_steps, args.adam_steps)
+    if args.guess == "mlp" or args.guess_study > 0 or (args.compare_steps > 0 and not args.no_mlp_compare):
+        net, train_info = train_network(sw, cg, ctx, cfg, args.train_cases, args.train_steps, args.adam_steps,
+                                        box=tuple(float(v) for v in args.train_box.split(",")))
 
     # warm-up on a separate copy of the case
     if args.warmup > 0:
@@ -400,7 +462,13 @@ def main():
     if args.batched > 0:
         del gmesh
         torch.cuda.empty_cache()
-        batched = batched_study(sw, cg, ctx, args.batched, args.batched_steps, args.proj_dim)
+        batched = batched_study(sw, cg, ctx, args.batched, args.batched_steps, args.proj_dim,
+                                tuple(args.batched_legs.split(",")))
+
+    gstudy = None
+    if args.guess_study > 0:
+        torch.cuda.empty_cache()
+        gstudy = guess_study(sw, cg, ctx, net, args.guess_study, args.guess_study_steps, args.proj_dim)
 
     fit = None
     if args.fit_study > 0:
@@ -426,7 +494,8 @@ def main():
         "learned_guess_training": train_info,
         "kernels_ms": {k: {"total_ms": round(v[0], 3), "launches": v[1], "full_launch_us": round(1e3 * v[2], 1)}
                        for k, v in kernels.items() if v[1]},
-        "roofline": roofline, "compare": compare, "batched": batched, "input_estimation": fit, "cpu_baseline": cpu,
+        "roofline": roofline, "compare": compare, "batched": batched, "learned_guess_study": gstudy,
+        "input_estimation": fit, "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
 
