@@ -32,7 +32,7 @@ def extrapolation(history, order):
     return sum((-1) ** j * comb(p + 1, j + 1) * history[-1 - j] for j in range(p + 1))
 
 
-def projection(A, X, b, rel_cut=1e-11):
+def projection(A, X, b, rel_cut=1e-16):
     """Galerkin projection of A^-1 b onto span(X): A symmetric positive
     definite (dense or sparse), X (n, L), b (n,)."""
     X = np.asarray(X, float)

@@ -1091,7 +1091,10 @@ int proj_finish(sw_case* c, bool with_res) {
     hs[i] = c->proj_h[idx[i]];
     for (int j = 0; j < m; ++j) Gs[i * m + j] = c->projG[(size_t)idx[i] * L + idx[j]];
   }
-  psd_solve(m, Gs, m, hs, ts, 1e-11);
+  // directions are kept down to FP64 resolution of the unit-diagonal Gram
+  // matrix: the increments of a smooth march are nearly dependent, and the
+  // step's new component lies in the directions of smallest energy
+  psd_solve(m, Gs, m, hs, ts, 1e-16);
   std::fill(c->proj_th.begin(), c->proj_th.end(), 0.0);
   for (int i = 0; i < m; ++i) c->proj_th[idx[i]] = std::isfinite(ts[i]) ? ts[i] : 0.0;
   HIPC(hipMemcpyAsync(c->proj_theta, c->proj_th.data(), L * sizeof(double), hipMemcpyHostToDevice, s));
