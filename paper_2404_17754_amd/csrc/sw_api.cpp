@@ -671,7 +671,9 @@ int apply_f32(sw_case* c, int op, const float* x, float* y, CgCtl* ctl, int iter
 int build_rhs(sw_case* c, double* y) {
   hipStream_t s = c->ctx->stream;
   const int64_t nd = 3 * c->mesh->n_nodes;
-  launch_fill_f64(nd, y, 0.0, s);
+  // the first pass stores the interior nodes and adds into the shared ones
+  const int64_t ni3 = 3 * c->mesh->dev.n_interior;
+  launch_fill_f64(nd - ni3, y + ni3, 0.0, s);
   TileArgs<double> A{};
   A.sM = 1.0;
   A.sK = 0.0;
@@ -1262,7 +1264,7 @@ int solve_step(sw_case* c, int* iters, int* outer, double* relres, int* flags) {
       // inner tolerance: the fixed inner_rtol, or less work when the target
       // needs only a smaller reduction of the current residual
       const double need = c->rtol * std::sqrt(h.bb / h.rr_true);
-      const double tol = std::min(0.5, std::max(c->inner_rtol, 0.3 * need));
+      const double tol = std::min(0.5, std::max(c->inner_rtol, 0.9 * need));
       launch_fill_f64(sizeof(CgCtl) / 8, (double*)c->ctl32, 0.0, s);
       launch_fill_f64(1, &c->ctl32->bb, 1.0, s);
       launch_ctl_prepare(c->ctl32, tol, s);
@@ -1965,7 +1967,7 @@ int batch_step_once(sw_batch* b) {
         continue;
       }
       const double need = c->rtol * std::sqrt(h.bb / h.rr_true);
-      S.tol = std::min(0.5, std::max(c->inner_rtol, 0.3 * need));
+      S.tol = std::min(0.5, std::max(c->inner_rtol, 0.9 * need));
       S.iter_base = iters[l];
       S.active = 1;
       any_inner = any_open = true;
