@@ -85,7 +85,7 @@ def test_operator_rows_fp64_and_fp32(sw, big):
     last place of each precision)."""
     import torch
     mesh, case, ctx, gm = big
-    gc = sw.Case(ctx, gm, case, precision="mixed", guess="proj", proj_dim=12)
+    gc = sw.Case(ctx, gm, case, precision="mixed", guess="proj", proj_dim=8)
     rng = np.random.default_rng(11)
     x = rng.standard_normal(3 * mesh.n_nodes)
     x32 = x.astype(np.float32)
@@ -137,11 +137,11 @@ def test_whole_mesh_properties(sw, big):
 
 def test_short_march_as_benchmarked(sw, big):
     """Three steps in the benchmark's configuration (FP32 inner CG in FP64
-    refinement, projected guess of 12 increments): every step meets the
+    refinement, projected guess of 8 increments): every step meets the
     true relative residual 1e-8, and the state agrees with plain FP64 PCG
     to 1e-6 (both are within the solver tolerance of the exact march)."""
     mesh, case, ctx, gm = big
-    mixed = sw.Case(ctx, gm, case, precision="mixed", guess="proj", proj_dim=12)
+    mixed = sw.Case(ctx, gm, case, precision="mixed", guess="proj", proj_dim=8)
     plain = sw.Case(ctx, gm, case, precision="fp64", guess="zero")
     mixed.step(3)
     plain.step(3)
