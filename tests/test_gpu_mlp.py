@@ -189,8 +189,15 @@ def _train_and_compare(sw, ctx, n_train=3, n_test=2, steps=60, size=(100.0, 100.
 
 
 def test_trained_network_gain_over_extrapolation(sw, ctx):
+    """What the trained network gains over the method without it: on
+    held-out models with a 4 Hz input (a regime where extrapolation from
+    the last increments leaves a sizeable error), the learned guess needs
+    fewer CG iterations per step than quadratic extrapolation (measured
+    about 6 % fewer; asserted at least 2 %).  At 2 Hz on the batched
+    workload's meshes extrapolation is already close and the network does
+    not gain; the benchmark's guess study reports that case."""
     res, losses = _train_and_compare(sw, ctx)
     print(f"learned guess: CG iterations/step poly {res['poly']:.2f} -> mlp {res['mlp']:.2f}; "
           f"training loss {losses[:20].mean():.3e} -> {losses[-20:].mean():.3e}", flush=True)
     assert losses[-20:].mean() < 0.5 * losses[:20].mean()
-    assert res["mlp"] <= res["poly"] * 1.05
+    assert res["mlp"] <= res["poly"] * 0.98
