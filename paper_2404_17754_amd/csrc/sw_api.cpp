@@ -586,7 +586,8 @@ static int validate_case(const sw_mesh* m, const sw_case_desc* d) {
   if (!(d->ray_alpha >= 0.0) || !(d->ray_beta >= 0.0)) return fail(SW_EINVAL, "Rayleigh coefficients must be >= 0");
   if (!(d->rtol > 0.0 && d->rtol < 1.0)) return fail(SW_EINVAL, "rtol must be in (0, 1)");
   if (d->max_iter <= 0) return fail(SW_EINVAL, "max_iter must be > 0");
-  if (d->precision != SW_FP64 && d->precision != SW_MIXED_FP32) return fail(SW_EINVAL, "unknown precision %d", d->precision);
+  if (d->precision != SW_FP64 && d->precision != SW_MIXED_FP32)
+    return fail(SW_EINVAL, "unknown precision %d", d->precision);
   if (d->guess != SW_GUESS_ZERO && d->guess != SW_GUESS_POLY && d->guess != SW_GUESS_MLP &&
       d->guess != SW_GUESS_PROJ)
     return fail(SW_EINVAL, "unknown guess kind %d", d->guess);

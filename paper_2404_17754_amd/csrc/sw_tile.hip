@@ -359,10 +359,11 @@ constexpr int PIPE_MATS = 32;
 // older one: the node ids of tile t+1 are loaded at the end of tile t-1;
 // tile t's first element data goes out before the values of tile t+1, so
 // the element work waits only for its own data; per-tile offsets and counts
-// are scalar loads.  XCD-aware: workgroup b runs on XCD b mod 8 (workgroups are dealt
-// to the 8 XCDs round-robin) and takes its tiles from that XCD's contiguous
-// eighth of the tile list, so neighbouring tiles, which share nodes, meet in
-// the same L2.  NPT * NT must cover the largest tile.
+// are scalar loads; the material constants come from an LDS copy.
+// XCD-aware: workgroup b runs on XCD b mod 8 (workgroups are dealt to the 8
+// XCDs round-robin) and takes its tiles from that XCD's contiguous eighth of
+// the tile list, so neighbouring tiles, which share nodes, meet in the same
+// L2.  NPT * NT must cover the largest tile; at most PIPE_MATS materials.
 template <int NT, int NPT, bool PF>
 __global__ __launch_bounds__(NT) void k_tile_pipe(MeshDev m, const uint8_t* __restrict__ emat,
                                                    const MatDev* __restrict__ mats, TileArgs<float> A, CgCtl* ctl,
@@ -481,9 +482,9 @@ __global__ __launch_bounds__(NT) void k_tile_pipe(MeshDev m, const uint8_t* __re
 // the lanes (LDS layout).
 
 template <int NT, int NPT>
-__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(3, 3))) void k_tile_lanes_pipe(const TileLane<float>* __restrict__ lanes,
-                                                         const int2* __restrict__ items, int n_items, int nmax,
-                                                         const LaneState* __restrict__ st, int iter) {
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(3, 3))) void k_tile_lanes_pipe(
+    const TileLane<float>* __restrict__ lanes, const int2* __restrict__ items, int n_items, int nmax,
+    const LaneState* __restrict__ st, int iter) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   __shared__ double sh[NT / 64];
   double* ys = reinterpret_cast<double*>(smem_raw);
