@@ -18,9 +18,10 @@ guess, the learned guess (a network trained before timing on solution
 histories that the solver generates for separate training models, 200 x
 200 x 100 m boxes of the same cells, time step and input, marched together
 as one batch) and the plain FP64 PCG (zero guess), and the CPU oracle on a
-bounded sample of the workload.  --batched K adds a study of K candidate
-models per mesh on the three uneven meshes of the batched workload, marched
-case by case and as one batch; --guess-study N marches N held-out models of
+bounded sample of the workload.  --batched K (default 8) adds a study of K
+candidate models per mesh on the three uneven meshes of the batched
+workload, marched case by case, as one batch and case by case with plain
+FP64 PCG; --guess-study N marches N held-out models of
 the 300 x 300 x 100 m mesh with the extrapolated, learned and projected
 guesses; --fit-study S runs the input estimation of Section 2.
 
@@ -317,8 +318,8 @@ def main():
     ap.add_argument("--compare-steps", type=int, default=100,
                     help="window (from rest) on which the other guesses and plain FP64 PCG are timed (0 = skip)")
     ap.add_argument("--no-mlp-compare", action="store_true", help="leave the trained-network leg out")
-    ap.add_argument("--batched", type=int, default=0,
-                    help="cases per mesh of an extra batched-vs-sequential study on the 200/300/400 m meshes")
+    ap.add_argument("--batched", type=int, default=8,
+                    help="cases per mesh of the batched study on the 200/300/400 m meshes (0: none)")
     ap.add_argument("--batched-steps", type=int, default=30)
     ap.add_argument("--batched-legs", default="seq,batched,plain",
                     help="legs of the batched study: seq, batched, plain (comma separated)")
