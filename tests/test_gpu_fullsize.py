@@ -14,11 +14,9 @@ import numpy as np
 import pytest
 
 import casegen as cg
-from oracle import assemble, fem
+from sampled_rows import check_rows
 
 pytestmark = pytest.mark.gpu
-
-N_SAMPLE = 16      # random sample nodes, plus nodes of side and base faces
 
 
 @pytest.fixture(scope="module")
@@ -38,66 +36,15 @@ def big(sw):
     return mesh, case, ctx, gm
 
 
-def _coefficients(case):
-    # A = 4/dt^2 M + 2/dt (alpha M + beta K + C_abs) + K
-    dt = case.dt
-    return 4.0 / dt ** 2 + 2.0 * case.ray_alpha / dt, 1.0 + 2.0 * case.ray_beta / dt, 2.0 / dt
-
-
-def _sample_nodes(mesh):
-    rng = np.random.default_rng(7)
-    nodes = list(rng.choice(mesh.n_nodes, N_SAMPLE, replace=False))
-    for role in (1, 2):
-        f = np.nonzero(mesh.face_role == role)[0]
-        tri = mesh.tri6[rng.choice(f, 2, replace=False)]
-        nodes += [int(tri[0, 0]), int(tri[1, 4])]      # a vertex and an edge node
-    return np.unique(np.asarray(nodes, dtype=np.int64))
-
-
-def _oracle_rows(mesh, case, nodes, x):
-    """Rows of A x at `nodes` from the oracle's element and face matrices
-    (and the same rows of |A| |x|, the scale of the rounding)."""
-    cM, cK, cC = _coefficients(case)
-    y = np.zeros((len(nodes), 3))
-    s = np.zeros((len(nodes), 3))
-    hit = np.isin(mesh.tet10, nodes).any(axis=1)
-    tets = np.nonzero(hit)[0]
-    Ke, Me = assemble.element_matrices(mesh, case.mat, case.tet_mat, tets)
-    Ae = cM * Me + cK * Ke
-    fsel = np.nonzero(np.isin(mesh.tri6, nodes).any(axis=1) & np.isin(mesh.face_role, (1, 2)))[0]
-    vp, vs, rho = (a[fsel] for a in assemble.face_materials(mesh, case.mat, case.tet_mat))
-    Cf = cC * fem.face_dashpot(mesh.xyz[mesh.tri6[fsel, :3]], vp, vs, rho)
-    for k, n in enumerate(nodes):
-        for mats, conn in ((Ae, mesh.tet10[tets]), (Cf, mesh.tri6[fsel])):
-            for j in np.nonzero((conn == n).any(axis=1))[0]:
-                loc = int(np.nonzero(conn[j] == n)[0][0])
-                xe = x[(3 * conn[j][:, None] + np.arange(3)).ravel()]
-                rows = mats[j][3 * loc:3 * loc + 3]
-                y[k] += rows @ xe
-                s[k] += np.abs(rows) @ np.abs(xe)
-    return y, s
-
-
 def test_operator_rows_fp64_and_fp32(sw, big):
     """y = A x at the sample nodes against the oracle: the FP64 pass (true
     residuals, right-hand sides) to 1e-13 and the FP32 pass of the inner CG
     iterations to 2e-6, relative to |A| |x| of the row (a few units of the
     last place of each precision)."""
-    import torch
     mesh, case, ctx, gm = big
     gc = sw.Case(ctx, gm, case, precision="mixed", guess="proj", proj_dim=8)
-    rng = np.random.default_rng(11)
-    x = rng.standard_normal(3 * mesh.n_nodes)
-    x32 = x.astype(np.float32)
-    nodes = _sample_nodes(mesh)
-    dofs = (3 * nodes[:, None] + np.arange(3)).ravel()
-    y64 = gc.apply("A", torch.from_numpy(x)).cpu().numpy()[dofs].reshape(-1, 3)
-    y32 = gc.apply_f32("A", torch.from_numpy(x32)).cpu().numpy()[dofs].reshape(-1, 3).astype(np.float64)
-    ref64, s64 = _oracle_rows(mesh, case, nodes, x)
-    ref32, s32 = _oracle_rows(mesh, case, nodes, x32.astype(np.float64))
-    e64 = np.max(np.abs(y64 - ref64) / s64)
-    e32 = np.max(np.abs(y32 - ref32) / s32)
-    print(f"sampled rows ({len(nodes)} nodes): FP64 {e64:.2e}, FP32 {e32:.2e}", flush=True)
+    e64, e32, n = check_rows(gc, mesh, case)
+    print(f"sampled rows ({n} nodes): FP64 {e64:.2e}, FP32 {e32:.2e}", flush=True)
     assert e64 < 1e-13
     assert e32 < 2e-6
 
