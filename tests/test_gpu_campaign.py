@@ -74,10 +74,11 @@ def _check_lane(sw, ctx, gm, mesh, case, lane, v0, n, tag):
 
 
 def _check_residuals(lanes, n):
-    # flag 4 (a projected guess replaced by zero because its residual was
-    # the larger) is allowed: from a rough initial velocity field the
-    # projection over the first increments can leave a larger residual norm
-    # than zero does, though never a larger A-norm error
+    # flag 4 (a projected guess whose residual norm exceeds ||b||, that of
+    # the zero guess, replaced by extrapolation for the step) is allowed:
+    # from a rough initial velocity field the projection over the first
+    # increments can leave the larger residual norm, though never the
+    # larger A-norm error
     for k, lane in enumerate(lanes):
         st = lane.stats()
         _, rel = lane.step_log()
