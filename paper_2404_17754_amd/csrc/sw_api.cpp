@@ -896,11 +896,10 @@ int cg_loop(sw_case* c, CgCtl* ctl, int iter_base, int first_chunk, int* iters_o
         prof_end(cx, ev);
         if (rc) return rc;
         ev = prof_begin(cx, SW_PROF_UPDATE_F32);
-        launch_cg_update_f32(nn, c->mesh->dev.n_interior, i & 1, c->pinv16, c->d32, c->r32, c->z32, c->p32, c->q32,
-                             ctl, s);
+        launch_cg_update_f32(nn, c->mesh->dev.n_interior, i & 1, c->pinv16, c->r32, c->z32, c->q32, ctl, s);
         prof_end(cx, ev);
         ev = prof_begin(cx, SW_PROF_DIR_F32);
-        launch_cg_dir_f32(nn, i & 1, iter_base + i, c->max_iter, c->z32, c->p32, ctl, s);
+        launch_cg_dir_f32(nn, i & 1, iter_base + i, c->max_iter, c->z32, c->p32, c->d32, ctl, s);
         prof_end(cx, ev);
       } else {
         int ev = prof_begin(cx, SW_PROF_TILE_F64);
@@ -908,10 +907,10 @@ int cg_loop(sw_case* c, CgCtl* ctl, int iter_base, int first_chunk, int* iters_o
         prof_end(cx, ev);
         if (rc) return rc;
         ev = prof_begin(cx, SW_PROF_UPDATE_F64);
-        launch_cg_update_f64(nn, i & 1, c->pinv64, c->x, c->r, c->z, c->p, c->q, ctl, s);
+        launch_cg_update_f64(nn, i & 1, c->pinv64, c->r, c->z, c->q, ctl, s);
         prof_end(cx, ev);
         ev = prof_begin(cx, SW_PROF_DIR_F64);
-        launch_cg_dir_f64(nn, i & 1, iter_base + i, c->max_iter, c->z, c->p, ctl, s);
+        launch_cg_dir_f64(nn, i & 1, iter_base + i, c->max_iter, c->z, c->p, c->x, ctl, s);
         prof_end(cx, ev);
       }
     }

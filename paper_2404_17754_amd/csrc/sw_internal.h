@@ -28,9 +28,12 @@ struct CgCtl {
   double tol2;     // stop when rr <= tol2
   double rr_true;  // ||b - A x||^2 recomputed in FP64
   double scale;    // mixed precision: residual scaling of the inner system
+  double alpha;    // step length of the last update kernel's iteration
   int32_t done;    // 1 once converged or capped
   int32_t iters;   // iterations of the current solve
-  int32_t pad[2];
+  int32_t live;    // 1 when the last update kernel ran its iteration (the
+                   // direction kernel after it applies x += alpha p)
+  int32_t pad;
 };
 
 // Tiled mesh in device memory (internal element and node numbering; see
@@ -181,15 +184,18 @@ void launch_cg_init_f64(int64_t n_nodes, const double* b, const double* q, const
                         double* p, double* qz, CgCtl* ctl, hipStream_t s);
 void launch_cg_init_f32(int64_t n_nodes, const float* b, const float* q, const __half* pinv, float* r, float* z,
                         float* p, float* qz, CgCtl* ctl, hipStream_t s);
-void launch_cg_update_f64(int64_t n_nodes, int par, const double* pinv, double* x, double* r, double* z,
-                          const double* p, double* q, CgCtl* ctl, hipStream_t s);
+// update: r -= alpha q, z = P r, dot products; direction: x += alpha p,
+// then p = z + beta p unless the solve stops (each iteration launches the
+// update, then the direction kernel)
+void launch_cg_update_f64(int64_t n_nodes, int par, const double* pinv, double* r, double* z, double* q, CgCtl* ctl,
+                          hipStream_t s);
 // q is cleared only for nodes >= n_interior (the next operator pass
 // overwrites interior nodes)
-void launch_cg_update_f32(int64_t n_nodes, int64_t n_interior, int par, const __half* pinv, float* x, float* r,
-                          float* z, const float* p, float* q, CgCtl* ctl, hipStream_t s);
-void launch_cg_dir_f64(int64_t n_nodes, int par, int iter_abs, int max_iter, const double* z, double* p,
+void launch_cg_update_f32(int64_t n_nodes, int64_t n_interior, int par, const __half* pinv, float* r, float* z,
+                          float* q, CgCtl* ctl, hipStream_t s);
+void launch_cg_dir_f64(int64_t n_nodes, int par, int iter_abs, int max_iter, const double* z, double* p, double* x,
                        CgCtl* ctl, hipStream_t s);
-void launch_cg_dir_f32(int64_t n_nodes, int par, int iter_abs, int max_iter, const float* z, float* p,
+void launch_cg_dir_f32(int64_t n_nodes, int par, int iter_abs, int max_iter, const float* z, float* p, float* x,
                        CgCtl* ctl, hipStream_t s);
 
 // ctl setup: bb must already be in ctl; sets tol2 = rtol^2 bb, clears the rest

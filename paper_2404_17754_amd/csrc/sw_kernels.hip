@@ -87,34 +87,39 @@ __device__ __forceinline__ void cg_init_body(int64_t n, const T* __restrict__ b,
   }
 }
 
-// alpha = rz[par] / pAp; x += alpha p; r -= alpha q; z = P r; q = 0;
-// rz[par^1] += r.z, rr[par^1] += r.r
+// alpha = rz[par] / pAp; r -= alpha q; z = P r; q = 0 (shared nodes);
+// rz[par^1] += r.z, rr[par^1] += r.r.  The solution update x += alpha p is
+// left to the direction kernel, which reads p anyway: alpha and whether this
+// iteration ran go to ctl->alpha and ctl->live (the direction kernel cannot
+// take that from ctl->done, which its own first workgroup may set while the
+// others still run).
 template <typename T, typename PT>
 __device__ __forceinline__ void cg_update_body(int64_t n, int64_t n_int, int par, const PT* __restrict__ P,
-                                               T* __restrict__ x, T* __restrict__ r, T* __restrict__ z,
-                                               const T* __restrict__ p, T* __restrict__ q, CgCtl* ctl) {
+                                               T* __restrict__ r, T* __restrict__ z, T* __restrict__ q,
+                                               CgCtl* ctl) {
   __shared__ double sh[2 * TPB / 64];
-  if (ctl->done) return;
+  const bool lead = blockIdx.x == 0 && threadIdx.x == 0;
+  if (ctl->done) {
+    if (lead) ctl->live = 0;
+    return;
+  }
   const T alpha = (T)(slot_sum<NSLOT>(ctl->rz[par]) / slot_sum<NSLOT>(ctl->pAp));
+  if (lead) {
+    ctl->alpha = (double)alpha;
+    ctl->live = 1;
+  }
   double rz = 0.0, rr = 0.0;
   for (int64_t i = (int64_t)blockIdx.x * TPB + threadIdx.x; i < n; i += (int64_t)gridDim.x * TPB) {
     // every load of the node first (12-byte accesses), then the stores
-    T xv[3], pv[3], rv[3], qv[3], zv[3];
+    T rv[3], qv[3], zv[3];
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
-      xv[c] = x[3 * i + c];
-      pv[c] = p[3 * i + c];
       rv[c] = r[3 * i + c];
       qv[c] = q[3 * i + c];
     }
 #pragma unroll
-    for (int c = 0; c < 3; ++c) {
-      xv[c] += alpha * pv[c];
-      rv[c] -= alpha * qv[c];
-    }
+    for (int c = 0; c < 3; ++c) rv[c] -= alpha * qv[c];
     bj_apply<T, PT>(P, i, rv, zv);
-#pragma unroll
-    for (int c = 0; c < 3; ++c) x[3 * i + c] = xv[c];
 #pragma unroll
     for (int c = 0; c < 3; ++c) r[3 * i + c] = rv[c];
 #pragma unroll
@@ -136,13 +141,16 @@ __device__ __forceinline__ void cg_update_body(int64_t n, int64_t n_int, int par
   }
 }
 
-// convergence test, then p = z + beta p with beta = rz[par^1] / rz[par]
+// After a live update: x += alpha p with the update's alpha, the convergence
+// test, then (unless the solve stops here) p = z + beta p with
+// beta = rz[par^1] / rz[par].
 template <typename T>
 __device__ __forceinline__ void cg_dir_body(int64_t n, int par, int iter_abs, int max_iter, const T* __restrict__ z,
-                                            T* __restrict__ p, CgCtl* ctl) {
-  if (ctl->done) return;
+                                            T* __restrict__ p, T* __restrict__ x, CgCtl* ctl) {
+  if (!ctl->live) return;
   const double rr = slot_sum<NSLOT>(ctl->rr[par ^ 1]);
   const bool stop = !(rr > ctl->tol2) || (iter_abs + 1 >= max_iter);  // NaN stops too
+  const T alpha = (T)ctl->alpha;
   const T beta = (T)(slot_sum<NSLOT>(ctl->rz[par ^ 1]) / slot_sum<NSLOT>(ctl->rz[par]));
   if (blockIdx.x == 0) {
     if (threadIdx.x == 0) {
@@ -151,34 +159,52 @@ __device__ __forceinline__ void cg_dir_body(int64_t n, int par, int iter_abs, in
     }
     if (threadIdx.x < NSLOT) ctl->pAp[threadIdx.x] = 0.0;
   }
-  if (stop) return;
   if constexpr (sizeof(T) == 4) {
     // elementwise over the 3n values, four at a time (16-byte accesses; the
     // vectors start 256-byte aligned)
     const int64_t n3 = 3 * n, n4 = n3 / 4;
     const float4* __restrict__ z4 = reinterpret_cast<const float4*>(z);
     float4* __restrict__ p4 = reinterpret_cast<float4*>(p);
+    float4* __restrict__ x4 = reinterpret_cast<float4*>(x);
     for (int64_t i = (int64_t)blockIdx.x * TPB + threadIdx.x; i < n4; i += (int64_t)gridDim.x * TPB) {
-      const float4 a = z4[i];
-      float4 b = p4[i];
-      b.x = a.x + beta * b.x;
-      b.y = a.y + beta * b.y;
-      b.z = a.z + beta * b.z;
-      b.w = a.w + beta * b.w;
-      p4[i] = b;
+      const float4 pv = p4[i];
+      float4 xv = x4[i];
+      float4 zv = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+      if (!stop) zv = z4[i];
+      xv.x += alpha * pv.x;
+      xv.y += alpha * pv.y;
+      xv.z += alpha * pv.z;
+      xv.w += alpha * pv.w;
+      x4[i] = xv;
+      if (!stop) {
+        float4 pn;
+        pn.x = zv.x + beta * pv.x;
+        pn.y = zv.y + beta * pv.y;
+        pn.z = zv.z + beta * pv.z;
+        pn.w = zv.w + beta * pv.w;
+        p4[i] = pn;
+      }
     }
-    for (int64_t i = 4 * n4 + (int64_t)blockIdx.x * TPB + threadIdx.x; i < n3; i += (int64_t)gridDim.x * TPB)
-      p[i] = z[i] + beta * p[i];
+    for (int64_t i = 4 * n4 + (int64_t)blockIdx.x * TPB + threadIdx.x; i < n3; i += (int64_t)gridDim.x * TPB) {
+      const float pv = p[i];
+      x[i] += alpha * pv;
+      if (!stop) p[i] = z[i] + beta * pv;
+    }
   } else {
     for (int64_t i = (int64_t)blockIdx.x * TPB + threadIdx.x; i < n; i += (int64_t)gridDim.x * TPB) {
-      T zv[3], pv[3];
+      T zv[3], pv[3], xv[3];
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
-        zv[c] = z[3 * i + c];
         pv[c] = p[3 * i + c];
+        xv[c] = x[3 * i + c];
+        zv[c] = stop ? (T)0 : z[3 * i + c];
       }
 #pragma unroll
-      for (int c = 0; c < 3; ++c) p[3 * i + c] = zv[c] + beta * pv[c];
+      for (int c = 0; c < 3; ++c) x[3 * i + c] = xv[c] + alpha * pv[c];
+      if (!stop) {
+#pragma unroll
+        for (int c = 0; c < 3; ++c) p[3 * i + c] = zv[c] + beta * pv[c];
+      }
     }
   }
 }
@@ -189,14 +215,14 @@ __global__ __launch_bounds__(TPB) void k_cg_init(int64_t n, const T* b, const T*
   cg_init_body<T, PT>(n, b, q, P, r, z, p, qz, ctl);
 }
 template <typename T, typename PT>
-__global__ __launch_bounds__(TPB) void k_cg_update(int64_t n, int64_t n_int, int par, const PT* P, T* x, T* r, T* z,
-                                                   const T* p, T* q, CgCtl* ctl) {
-  cg_update_body<T, PT>(n, n_int, par, P, x, r, z, p, q, ctl);
+__global__ __launch_bounds__(TPB) void k_cg_update(int64_t n, int64_t n_int, int par, const PT* P, T* r, T* z, T* q,
+                                                   CgCtl* ctl) {
+  cg_update_body<T, PT>(n, n_int, par, P, r, z, q, ctl);
 }
 template <typename T>
 __global__ __launch_bounds__(TPB) void k_cg_dir(int64_t n, int par, int iter_abs, int max_iter, const T* z, T* p,
-                                                CgCtl* ctl) {
-  cg_dir_body<T>(n, par, iter_abs, max_iter, z, p, ctl);
+                                                T* x, CgCtl* ctl) {
+  cg_dir_body<T>(n, par, iter_abs, max_iter, z, p, x, ctl);
 }
 
 void launch_cg_init_f64(int64_t n, const double* b, const double* q, const double* P, double* r, double* z, double* p,
@@ -207,23 +233,22 @@ void launch_cg_init_f32(int64_t n, const float* b, const float* q, const __half*
                         float* qz, CgCtl* ctl, hipStream_t s) {
   hipLaunchKernelGGL((k_cg_init<float, __half>), dim3(vgrid(n)), dim3(TPB), 0, s, n, b, q, P, r, z, p, qz, ctl);
 }
-void launch_cg_update_f64(int64_t n, int par, const double* P, double* x, double* r, double* z, const double* p,
-                          double* q, CgCtl* ctl, hipStream_t s) {
-  hipLaunchKernelGGL((k_cg_update<double, double>), dim3(vgrid(n)), dim3(TPB), 0, s, n, (int64_t)0, par, P, x, r,
-                     z, p, q, ctl);
+void launch_cg_update_f64(int64_t n, int par, const double* P, double* r, double* z, double* q, CgCtl* ctl,
+                          hipStream_t s) {
+  hipLaunchKernelGGL((k_cg_update<double, double>), dim3(vgrid(n)), dim3(TPB), 0, s, n, (int64_t)0, par, P, r, z, q,
+                     ctl);
 }
-void launch_cg_update_f32(int64_t n, int64_t n_int, int par, const __half* P, float* x, float* r, float* z,
-                          const float* p, float* q, CgCtl* ctl, hipStream_t s) {
-  hipLaunchKernelGGL((k_cg_update<float, __half>), dim3(vgrid(n)), dim3(TPB), 0, s, n, n_int, par, P, x, r, z, p,
-                     q, ctl);
+void launch_cg_update_f32(int64_t n, int64_t n_int, int par, const __half* P, float* r, float* z, float* q,
+                          CgCtl* ctl, hipStream_t s) {
+  hipLaunchKernelGGL((k_cg_update<float, __half>), dim3(vgrid(n)), dim3(TPB), 0, s, n, n_int, par, P, r, z, q, ctl);
 }
-void launch_cg_dir_f64(int64_t n, int par, int iter_abs, int max_iter, const double* z, double* p, CgCtl* ctl,
-                       hipStream_t s) {
-  hipLaunchKernelGGL(k_cg_dir<double>, dim3(vgrid(n)), dim3(TPB), 0, s, n, par, iter_abs, max_iter, z, p, ctl);
+void launch_cg_dir_f64(int64_t n, int par, int iter_abs, int max_iter, const double* z, double* p, double* x,
+                       CgCtl* ctl, hipStream_t s) {
+  hipLaunchKernelGGL(k_cg_dir<double>, dim3(vgrid(n)), dim3(TPB), 0, s, n, par, iter_abs, max_iter, z, p, x, ctl);
 }
-void launch_cg_dir_f32(int64_t n, int par, int iter_abs, int max_iter, const float* z, float* p, CgCtl* ctl,
-                       hipStream_t s) {
-  hipLaunchKernelGGL(k_cg_dir<float>, dim3(vgrid(n)), dim3(TPB), 0, s, n, par, iter_abs, max_iter, z, p, ctl);
+void launch_cg_dir_f32(int64_t n, int par, int iter_abs, int max_iter, const float* z, float* p, float* x,
+                       CgCtl* ctl, hipStream_t s) {
+  hipLaunchKernelGGL(k_cg_dir<float>, dim3(vgrid(n)), dim3(TPB), 0, s, n, par, iter_abs, max_iter, z, p, x, ctl);
 }
 
 // ------------------------------------------------------------ scalars
@@ -610,15 +635,14 @@ __global__ __launch_bounds__(TPB) void k_lane_cg(const LaneDev* __restrict__ lan
   const int par = iter & 1;
   if constexpr (sizeof(T) == 4) {
     if constexpr (DIR)
-      cg_dir_body<float>(L.n_nodes, par, st[l].iter_base + iter, L.max_iter, L.z32, L.p32, L.ctl32);
+      cg_dir_body<float>(L.n_nodes, par, st[l].iter_base + iter, L.max_iter, L.z32, L.p32, L.d32, L.ctl32);
     else
-      cg_update_body<float, __half>(L.n_nodes, L.n_interior, par, L.pinv16, L.d32, L.r32, L.z32, L.p32, L.q32,
-                                    L.ctl32);
+      cg_update_body<float, __half>(L.n_nodes, L.n_interior, par, L.pinv16, L.r32, L.z32, L.q32, L.ctl32);
   } else {
     if constexpr (DIR)
-      cg_dir_body<double>(L.n_nodes, par, st[l].iter_base + iter, L.max_iter, L.z, L.p, L.ctl64);
+      cg_dir_body<double>(L.n_nodes, par, st[l].iter_base + iter, L.max_iter, L.z, L.p, L.x, L.ctl64);
     else
-      cg_update_body<double, double>(L.n_nodes, 0, par, L.pinv64, L.x, L.r, L.z, L.p, L.q, L.ctl64);
+      cg_update_body<double, double>(L.n_nodes, 0, par, L.pinv64, L.r, L.z, L.q, L.ctl64);
   }
 }
 
