@@ -126,6 +126,12 @@ enum {
  * context stream (a few microseconds of overhead per launch) and reset the
  * totals; 0: stop.  Synchronises the stream. */
 SW_API int sw_ctx_profile(sw_ctx* ctx, int32_t enable);
+/* The same for the kernel classes whose bits (1 << SW_PROF_*) are set in
+ * `mask` only (0: stop), and for one launch in `every` (>= 1) of each such
+ * class (the first, then every `every`-th), so that the events add little to
+ * the timed work.  Bits at or above SW_PROF_KINDS or every < 1 are
+ * SW_EINVAL. */
+SW_API int sw_ctx_profile_kinds(sw_ctx* ctx, uint32_t mask, int32_t every);
 /* Total device time (ms) and launch count of one kernel class since the last
  * sw_ctx_profile call, and (optional, may be NULL) the mean duration and
  * count of its full launches: those lasting at least half the longest, which

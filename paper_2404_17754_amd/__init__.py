@@ -59,9 +59,16 @@ class Context:
         L.check(self.lib.sw_ctx_create(device, C.c_void_p(stream.cuda_stream), C.byref(h)))
         self.h = h
 
-    def profile(self, enable=True):
-        """Start (reset) or stop per-kernel HIP-event timing of the CG kernels."""
-        L.check(self.lib.sw_ctx_profile(self.h, 1 if enable else 0))
+    def profile(self, enable=True, kinds=None, every=1):
+        """Start (reset) or stop per-kernel HIP-event timing of the CG kernels:
+        all classes, or only those named in `kinds` (see profile_read), one
+        launch in `every` of each."""
+        if kinds is None and every == 1:
+            L.check(self.lib.sw_ctx_profile(self.h, 1 if enable else 0))
+        else:
+            names = L.PROF_KINDS if kinds is None else kinds
+            mask = sum(1 << L.PROF_KINDS[k] for k in names) if enable else 0
+            L.check(self.lib.sw_ctx_profile_kinds(self.h, mask, int(every)))
 
     def profile_read(self, kind):
         """(total ms, launches, mean ms of full launches, full launches) of one

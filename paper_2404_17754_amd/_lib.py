@@ -56,6 +56,7 @@ SIGNATURES = {
     "sw_ctx_create": (C.c_int, VP, PP),
     "sw_ctx_destroy": (VP,),
     "sw_ctx_profile": (VP, I32),
+    "sw_ctx_profile_kinds": (VP, C.c_uint32, I32),
     "sw_ctx_profile_read": (VP, I32, C.POINTER(F64), C.POINTER(I64), C.POINTER(F64), C.POINTER(I64)),
     "sw_mesh_workspace_bytes": (C.POINTER(MeshDesc), C.POINTER(SZ)),
     "sw_mesh_create": (VP, C.POINTER(MeshDesc), VP, SZ, PP),

@@ -79,11 +79,15 @@ inline int64_t pad64(int64_t n) { return (n + 63) / 64 * 64; }
 // ------------------------------------------------------------ objects
 
 // Optional per-kernel timing with HIP events on the context stream: each
-// profiled launch is bracketed by two events; elapsed times are collected at
-// the next host synchronisation point.
+// profiled launch is bracketed by two events; elapsed times are collected
+// when the event pool is full (one host synchronisation per kPool / 2
+// profiled launches) and when they are read.
 struct KernelProfiler {
-  static constexpr int kPool = 512;
+  static constexpr int kPool = 4096;
   bool on = false;
+  uint32_t mask = 0;      // kernel classes profiled (bit SW_PROF_*)
+  int every = 1;          // one launch in `every` of each class is timed
+  int64_t seen[SW_PROF_KINDS] = {};  // launches of each class since the start
   std::vector<hipEvent_t> ev;
   std::vector<int> kind;  // per event pair
   int next = 0;           // next free event
@@ -117,7 +121,8 @@ int prof_flush(sw_ctx* ctx) {
 // returns the event index of the start marker, or -1 when not profiling
 int prof_begin(sw_ctx* ctx, int kind) {
   KernelProfiler& P = ctx->prof;
-  if (!P.on) return -1;
+  if (!P.on || !((P.mask >> kind) & 1u)) return -1;
+  if (P.seen[kind]++ % P.every != 0) return -1;
   if (P.next + 2 > KernelProfiler::kPool && prof_flush(ctx) != SW_OK) return -1;
   const int i = P.next;
   P.kind[i / 2] = kind;
@@ -248,7 +253,15 @@ extern "C" int sw_ctx_destroy(sw_ctx* ctx) {
 }
 
 extern "C" int sw_ctx_profile(sw_ctx* ctx, int32_t enable) {
+  return sw_ctx_profile_kinds(ctx, enable ? (1u << SW_PROF_KINDS) - 1u : 0u, 1);
+}
+
+extern "C" int sw_ctx_profile_kinds(sw_ctx* ctx, uint32_t mask, int32_t every) {
   if (!ctx) return fail(SW_EINVAL, "NULL context");
+  if (mask >> SW_PROF_KINDS) return fail(SW_EINVAL, "profile mask 0x%x has bits past the %d kernel classes", mask,
+                                         (int)SW_PROF_KINDS);
+  if (every < 1) return fail(SW_EINVAL, "profile sampling every %d launches", (int)every);
+  const bool enable = mask != 0;
   HIPC(hipSetDevice(ctx->device));
   KernelProfiler& P = ctx->prof;
   if (enable && P.ev.empty()) {
@@ -263,8 +276,11 @@ extern "C" int sw_ctx_profile(sw_ctx* ctx, int32_t enable) {
     P.total_ms[k] = 0.0;
     P.count[k] = 0;
     P.each[k].clear();
+    P.seen[k] = 0;
   }
-  P.on = enable != 0;
+  P.on = enable;
+  P.mask = mask;
+  P.every = every;
   return SW_OK;
 }
 
