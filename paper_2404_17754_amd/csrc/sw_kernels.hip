@@ -110,18 +110,22 @@ __device__ __forceinline__ void cg_update_body(int64_t n, int64_t n_int, int par
   }
   double rz = 0.0, rr = 0.0;
   for (int64_t i = (int64_t)blockIdx.x * TPB + threadIdx.x; i < n; i += (int64_t)gridDim.x * TPB) {
-    // every load of the node first (12-byte accesses), then the stores
+    // every load of the node first (12-byte accesses), then the stores; r
+    // and q are not read again before the next iteration's operator pass
+    // and update, so they go through the caches non-temporally (z, read by
+    // the direction kernel right after, and the preconditioner blocks, read
+    // every iteration, stay cached)
     T rv[3], qv[3], zv[3];
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
-      rv[c] = r[3 * i + c];
-      qv[c] = q[3 * i + c];
+      rv[c] = __builtin_nontemporal_load(&r[3 * i + c]);
+      qv[c] = __builtin_nontemporal_load(&q[3 * i + c]);
     }
 #pragma unroll
     for (int c = 0; c < 3; ++c) rv[c] -= alpha * qv[c];
     bj_apply<T, PT>(P, i, rv, zv);
 #pragma unroll
-    for (int c = 0; c < 3; ++c) r[3 * i + c] = rv[c];
+    for (int c = 0; c < 3; ++c) __builtin_nontemporal_store(rv[c], &r[3 * i + c]);
 #pragma unroll
     for (int c = 0; c < 3; ++c) z[3 * i + c] = zv[c];
     if (i >= n_int) {
@@ -161,29 +165,22 @@ __device__ __forceinline__ void cg_dir_body(int64_t n, int par, int iter_abs, in
   }
   if constexpr (sizeof(T) == 4) {
     // elementwise over the 3n values, four at a time (16-byte accesses; the
-    // vectors start 256-byte aligned)
+    // vectors start 256-byte aligned).  x and z are not read again before
+    // the next iteration rewrites them: non-temporal accesses keep them from
+    // displacing p, which the next operator pass gathers, in the caches
+    typedef float f32x4 __attribute__((ext_vector_type(4)));
     const int64_t n3 = 3 * n, n4 = n3 / 4;
-    const float4* __restrict__ z4 = reinterpret_cast<const float4*>(z);
-    float4* __restrict__ p4 = reinterpret_cast<float4*>(p);
-    float4* __restrict__ x4 = reinterpret_cast<float4*>(x);
+    const f32x4* __restrict__ z4 = reinterpret_cast<const f32x4*>(z);
+    f32x4* __restrict__ p4 = reinterpret_cast<f32x4*>(p);
+    f32x4* __restrict__ x4 = reinterpret_cast<f32x4*>(x);
     for (int64_t i = (int64_t)blockIdx.x * TPB + threadIdx.x; i < n4; i += (int64_t)gridDim.x * TPB) {
-      const float4 pv = p4[i];
-      float4 xv = x4[i];
-      float4 zv = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-      if (!stop) zv = z4[i];
-      xv.x += alpha * pv.x;
-      xv.y += alpha * pv.y;
-      xv.z += alpha * pv.z;
-      xv.w += alpha * pv.w;
-      x4[i] = xv;
-      if (!stop) {
-        float4 pn;
-        pn.x = zv.x + beta * pv.x;
-        pn.y = zv.y + beta * pv.y;
-        pn.z = zv.z + beta * pv.z;
-        pn.w = zv.w + beta * pv.w;
-        p4[i] = pn;
-      }
+      const f32x4 pv = p4[i];
+      f32x4 xv = __builtin_nontemporal_load(x4 + i);
+      f32x4 zv = {0.0f, 0.0f, 0.0f, 0.0f};
+      if (!stop) zv = __builtin_nontemporal_load(z4 + i);
+      xv += alpha * pv;
+      __builtin_nontemporal_store(xv, x4 + i);
+      if (!stop) p4[i] = zv + beta * pv;
     }
     for (int64_t i = 4 * n4 + (int64_t)blockIdx.x * TPB + threadIdx.x; i < n3; i += (int64_t)gridDim.x * TPB) {
       const float pv = p[i];
