@@ -12,7 +12,7 @@ whole analysis (400 steps from rest by default).  Inputs are synthetic
 starts.
 
 Each step starts by default from the projection guess: the Galerkin
-projection of its solution onto the span of the last 8 increments.  The
+projection of its solution onto the span of the last 6 increments.  The
 same run times, on a common window of steps from rest, the polynomial
 guess, the learned guess (a network trained before timing on solution
 histories that the solver generates for separate training models, 200 x
@@ -315,7 +315,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3, help="untimed steps on a separate copy of the case")
     ap.add_argument("--config", default="large")
     ap.add_argument("--guess", default="proj", choices=["zero", "poly", "mlp", "proj"])
-    ap.add_argument("--proj-dim", type=int, default=8, help="past increments spanned by the projection guess")
+    ap.add_argument("--proj-dim", type=int, default=6, help="past increments spanned by the projection guess")
     ap.add_argument("--inner-rtol", type=float, default=0.0,
                     help="floor of the inner FP32 CG tolerance (0 = the library default)")
     ap.add_argument("--compare-steps", type=int, default=100,

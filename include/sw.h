@@ -178,7 +178,7 @@ typedef struct {
   const int32_t* rec_node; /* host, n_rec node ids */
   int64_t n_steps;       /* capacity of the march (steps 1..n_steps) */
   const double* v_in;    /* host, (n_steps + 1) x 3 incident velocity at t = n dt */
-  int32_t proj_dim;      /* SW_GUESS_PROJ: increments spanned, 2..16 (0 = 8) */
+  int32_t proj_dim;      /* SW_GUESS_PROJ: increments spanned, 2..16 (0 = 6) */
 } sw_case_desc;
 
 SW_API int sw_case_workspace_bytes(const sw_mesh* mesh, const sw_case_desc* desc, size_t* bytes);

@@ -117,7 +117,7 @@ class Case:
     v_in ((n_steps+1) x 3), dt, ray_alpha, ray_beta (and n_steps)."""
 
     def __init__(self, ctx: Context, mesh: Mesh, c, rtol=1e-8, max_iter=10000, precision="fp64",
-                 guess="zero", poly_order=2, inner_rtol=0.0, n_steps=None, proj_dim=8):
+                 guess="zero", poly_order=2, inner_rtol=0.0, n_steps=None, proj_dim=6):
         self.ctx, self.mesh = ctx, mesh
         lib = ctx.lib
         v_in = np.ascontiguousarray(c.v_in, np.float64)

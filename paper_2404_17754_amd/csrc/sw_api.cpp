@@ -545,7 +545,7 @@ static size_t case_layout(const sw_mesh* m, const sw_case_desc* d, Carver& cv, s
     node_mat = cv.take<float>(2 * nn);
   }
   double *pX = nullptr, *pY = nullptr, *ppart = nullptr, *pout = nullptr, *pth = nullptr;
-  const int L = d->guess == SW_GUESS_PROJ ? (d->proj_dim > 0 ? d->proj_dim : 8) : 0;
+  const int L = d->guess == SW_GUESS_PROJ ? (d->proj_dim > 0 ? d->proj_dim : 6) : 0;
   if (L > 0) {
     pX = cv.take<double>((size_t)L * nd);
     pY = cv.take<double>((size_t)L * nd);

@@ -49,7 +49,7 @@ def _relL2(a, b):
 
 
 def _case(sw, ctx, gm, case, v0):
-    gc = sw.Case(ctx, gm, case, precision="mixed", guess="proj", proj_dim=8)
+    gc = sw.Case(ctx, gm, case, precision="mixed", guess="proj", proj_dim=6)
     gc.set_state(v=v0)
     return gc
 

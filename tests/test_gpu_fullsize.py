@@ -42,7 +42,7 @@ def test_operator_rows_fp64_and_fp32(sw, big):
     iterations to 2e-6, relative to |A| |x| of the row (a few units of the
     last place of each precision)."""
     mesh, case, ctx, gm = big
-    gc = sw.Case(ctx, gm, case, precision="mixed", guess="proj", proj_dim=8)
+    gc = sw.Case(ctx, gm, case, precision="mixed", guess="proj", proj_dim=6)
     e64, e32, n = check_rows(gc, mesh, case)
     print(f"sampled rows ({n} nodes): FP64 {e64:.2e}, FP32 {e32:.2e}", flush=True)
     assert e64 < 1e-13
@@ -84,11 +84,11 @@ def test_whole_mesh_properties(sw, big):
 
 def test_short_march_as_benchmarked(sw, big):
     """Three steps in the benchmark's configuration (FP32 inner CG in FP64
-    refinement, projected guess of 8 increments): every step meets the
+    refinement, projected guess of 6 increments): every step meets the
     true relative residual 1e-8, and the state agrees with plain FP64 PCG
     to 1e-6 (both are within the solver tolerance of the exact march)."""
     mesh, case, ctx, gm = big
-    mixed = sw.Case(ctx, gm, case, precision="mixed", guess="proj", proj_dim=8)
+    mixed = sw.Case(ctx, gm, case, precision="mixed", guess="proj", proj_dim=6)
     plain = sw.Case(ctx, gm, case, precision="fp64", guess="zero")
     mixed.step(3)
     plain.step(3)

@@ -176,14 +176,14 @@ def test_long_march_as_benchmarked(sw, ctx):
     """400 steps of the small model (4 s: the wave crosses the box, reflects
     at the free surface and leaves through the dashpots) in the benchmark's
     configuration (FP32 inner CG in FP64 refinement, projection guess over
-    8 increments): receiver waveforms within 1e-6 of the oracle's exact
+    6 increments): receiver waveforms within 1e-6 of the oracle's exact
     solves over the whole record, and the true residual of every step
     within 1e-8, so neither the projection nor the refinement drifts."""
     cfg = cg.CONFIGS["small"]
     mesh = cg.config_mesh(cfg)
     case = cg.make_case(mesh, cfg, n_steps=400)
     ref = march.run_case(mesh, case, solver="lu")
-    gc = sw.Case(ctx, sw.Mesh(ctx, mesh), case, precision="mixed", guess="proj", proj_dim=8)
+    gc = sw.Case(ctx, sw.Mesh(ctx, mesh), case, precision="mixed", guess="proj", proj_dim=6)
     gc.step(400)
     it, rel = gc.step_log()
     err = _relL2(gc.waveforms(), ref.rec_v)
