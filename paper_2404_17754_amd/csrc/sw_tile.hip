@@ -494,10 +494,20 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(3, 3))) void
   const int xcd = blockIdx.x & 7, slots = gridDim.x >> 3, slot = blockIdx.x >> 3;
   const int lo = (int)(((int64_t)n_items * xcd) >> 3);
   const int hi = (int)(((int64_t)n_items * (xcd + 1)) >> 3);
+  // work item k, the same in every lane of the workgroup: readfirstlane
+  // tells the compiler so, which keeps the item's lane and tile indices and
+  // the lane's pointers in scalar registers (without it the kernel spilled
+  // 29 vector registers)
+  auto item = [&](int k) {
+    int2 w = items[k];
+    w.x = __builtin_amdgcn_readfirstlane(w.x);
+    w.y = __builtin_amdgcn_readfirstlane(w.y);
+    return w;
+  };
   // next item at or after k (in steps of slots) that is not skipped (hi if none)
   auto next_live = [&](int k) {
     for (; k < hi; k += slots) {
-      const int2 w = items[k];
+      const int2 w = item(k);
       if (st != nullptr && !st[w.x].active) continue;
       CgCtl* c = lanes[w.x].ctl;
       if (c->done) continue;
@@ -509,9 +519,9 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(3, 3))) void
     }
     return k;
   };
-  int k = next_live(lo + slot);
+  int k = __builtin_amdgcn_readfirstlane(next_live(lo + slot));
   if (k >= hi) return;
-  int2 w = items[k];
+  int2 w = item(k);
   {
     const TileLane<float>& L = lanes[w.x];
     const int n0 = L.m.tile_node_off[w.y], nt = L.m.tile_node_off[w.y + 1] - n0;
@@ -536,14 +546,14 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(3, 3))) void
       L.ctl->rz[par ^ 1][threadIdx.x] = 0.0;
       L.ctl->rr[par ^ 1][threadIdx.x] = 0.0;
     }
-    const int kn = next_live(k + slots);
+    const int kn = __builtin_amdgcn_readfirstlane(next_live(k + slots));
     const bool more = kn < hi;
     int2 wn = make_int2(0, 0);
     int32_t pg[NPT];
     float px[NPT][3];
     int ntn = 0;
     if (more) {
-      wn = items[kn];
+      wn = item(kn);
       const TileLane<float>& Ln = lanes[wn.x];
       const int n0 = Ln.m.tile_node_off[wn.y];
       ntn = Ln.m.tile_node_off[wn.y + 1] - n0;
