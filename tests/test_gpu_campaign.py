@@ -113,7 +113,7 @@ def test_uneven_campaign_full_size(sw, ctx):
 
 
 def test_sweep_batch_of_32(sw, ctx):
-    """32 models of the 1000 x 1000 x 100 m box in one batch (about 190 GB
+    """32 models of the 1000 x 1000 x 100 m box in one batch (about 170 GB
     of device memory with the projection rings)."""
     n = 6
     cfg = cg.CONFIGS["sweep"]
