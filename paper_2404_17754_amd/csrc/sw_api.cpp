@@ -1312,6 +1312,9 @@ extern "C" int sw_case_step(sw_case* c, int32_t n) {
   HIPC(hipSetDevice(c->ctx->device));
   hipStream_t s = c->ctx->stream;
   const int64_t nd = 3 * c->mesh->n_nodes;
+  // the steps follow each other on the stream without a host
+  // synchronisation between them (the solves synchronise where they read
+  // their control blocks); the call returns once the last step is done
   for (int k = 0; k < n; ++k) {
     int iters, outer, flags;
     double rel;
@@ -1338,10 +1341,8 @@ extern "C" int sw_case_step(sw_case* c, int32_t n) {
       c->nb_head = nh;
       c->nb_count = std::min(c->nb_count + 1, 4);
     }
-    const int32_t it32 = iters;
-    HIPC(hipMemcpyAsync(c->log_it + c->step, &it32, 4, hipMemcpyHostToDevice, s));
-    HIPC(hipMemcpyAsync(c->log_rel + c->step, &rel, 8, hipMemcpyHostToDevice, s));
-    HIPC(hipStreamSynchronize(s));
+    launch_log_step(c->log_it + c->step, iters, c->log_rel + c->step, rel, s);
+    LAUNCHED();
     c->step += 1;
     c->last_iters = std::max(2, iters);
     c->stats.steps += 1;
@@ -1350,6 +1351,7 @@ extern "C" int sw_case_step(sw_case* c, int32_t n) {
     c->stats.max_true_rel_res = std::max(c->stats.max_true_rel_res, rel);
     c->stats.flags |= flags;
   }
+  HIPC(hipStreamSynchronize(s));
   return SW_OK;
 }
 

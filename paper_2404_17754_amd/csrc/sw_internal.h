@@ -217,6 +217,9 @@ void launch_guess_poly(int64_t n, const double* hist, int head, int order, doubl
 void launch_newmark(int64_t n, double dt, const double* du, double* u, double* v, double* a, double* hist_slot,
                     hipStream_t s);
 void launch_record(int n_rec, const int32_t* rec, const double* v, double* wave_row, hipStream_t s);
+// one step's log entry (iterations, true relative residual), written by a
+// kernel so that the step needs no host synchronisation
+void launch_log_step(int32_t* it_dst, int32_t iters, double* rel_dst, double rel, hipStream_t s);
 
 void launch_misfit(int n_rec, int64_t n_steps, const double* U, const double* obs, double* pair_buf,
                    double* out2, hipStream_t s);

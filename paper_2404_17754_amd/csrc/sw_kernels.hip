@@ -409,6 +409,16 @@ void launch_newmark(int64_t n, double dt, const double* du, double* u, double* v
   hipLaunchKernelGGL(k_newmark, dim3(g), dim3(TPB), 0, s, n, dt, du, u, v, a, hist_slot);
 }
 
+__global__ void k_log_step(int32_t* it_dst, int32_t iters, double* rel_dst, double rel) {
+  if (threadIdx.x == 0) {
+    *it_dst = iters;
+    *rel_dst = rel;
+  }
+}
+void launch_log_step(int32_t* it_dst, int32_t iters, double* rel_dst, double rel, hipStream_t s) {
+  hipLaunchKernelGGL(k_log_step, dim3(1), dim3(64), 0, s, it_dst, iters, rel_dst, rel);
+}
+
 __global__ void k_record(int n_rec, const int32_t* __restrict__ rec, const double* __restrict__ v,
                          double* __restrict__ row) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
