@@ -26,5 +26,5 @@ Modules:
   mlp      FP64 forward/backward of the initial-guess network
 
 Every function is pinned by a CPU test against closed forms, invariants or
-exact solutions (tests/test_oracle_*.py); the pins are listed in the design doc.
+exact solutions: the tests in tests/test_oracle_*.py.
 """
