@@ -340,7 +340,7 @@ def main():
                     help="copy a buffer of this size once before timing (reference for HBM counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU: the analyses of different candidate models are "
+        print(json.dumps({"error": "the solver runs on one GPU: the analyses of different candidate models are "
                                    "independent, so N GPUs would each march their own share of cases; "
                                    "only --gpus 1 is measured"}))
         sys.exit(2)
