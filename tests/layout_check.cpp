@@ -1,0 +1,111 @@
+// CPU check of the host-side tiled mesh layout (sw::build_layout): builds the
+// layout of a caller's mesh and verifies every property the operator kernels
+// rely on.  Compiled with g++ together with sw_mesh.cpp by tests/test_layout.py;
+// returns 0, or the number of the first property that fails.  plant != 0
+// first plants one mistake in the built layout (a test that the checks see
+// it): 1 a wrong tile-local index, 2 an interior node id out of its range,
+// 3 a wrong inverse valence, 4 a face moved to another tile's element.
+#include <algorithm>
+#include <cmath>
+#include <cstdint>
+#include <vector>
+
+#include "sw_layout.h"
+
+using sw::HostLayout;
+
+extern "C" int check_layout(int64_t nn, int64_t nt, int64_t nf, const double* xyz, const int32_t* tet10,
+                            const int32_t* tri6, const int32_t* face_tet, const uint8_t* face_role,
+                            int32_t plant, int64_t* stats) {
+  HostLayout L;
+  sw::build_layout(nn, nt, nf, xyz, tet10, tri6, face_tet, face_role, L);
+  if (plant == 1) std::swap(L.conn_loc[0], L.conn_loc[L.tet_stride]);
+  if (plant == 2) L.tile_nodes[L.tile_node_off[0]] += 1;
+  if (plant == 3) L.inv_valence[nn / 2] *= 0.5f;
+  if (plant == 4 && nf > 0) {
+    const int t = L.tile_face_off[1] > 0 ? 0 : 1;  // a tile that owns a face
+    L.face_elem[L.tile_face_off[t]] = L.tile_elem_off[t + 1];
+  }
+  // 1-2: element and node numberings are permutations, 3: tile size caps
+  std::vector<int> seen(nt, 0);
+  for (int32_t e : L.elem_order)
+    if (e < 0 || e >= nt || seen[e]++) return 1;
+  for (int64_t i = 0; i < nn; ++i)
+    if (L.node_u2i[i] < 0 || L.node_u2i[i] >= nn || L.node_i2u[L.node_u2i[i]] != i) return 2;
+  if (L.max_tile_nodes > sw::TILE_MAX_NODES) return 3;
+  // 4: coordinates follow the node numbering
+  for (int64_t i = 0; i < nn; ++i)
+    for (int d = 0; d < 3; ++d)
+      if (L.xyz[3 * (int64_t)L.node_u2i[i] + d] != xyz[3 * i + d]) return 4;
+  std::vector<int> touched_by(nn, 0), last(nn, -1), valence(nn, 0);
+  int64_t shared_total = 0, tile_nodes_total = 0, max_elems = 0, next_interior = 0;
+  for (int t = 0; t < L.n_tiles; ++t) {
+    const int n0 = L.tile_node_off[t], ntn = L.tile_node_off[t + 1] - n0, nint = L.tile_nint[t];
+    const int ne = L.tile_elem_off[t + 1] - L.tile_elem_off[t];
+    // 5: caps per tile; 6: the interior ranges are consecutive in tile order
+    if (ntn > sw::TILE_MAX_NODES || ne > sw::TILE_MAX_ELEMS || nint < 0 || nint > ntn) return 5;
+    if (L.tile_int_base[t] != next_interior) return 6;
+    next_interior += nint;
+    // 7: interior nodes first, as one contiguous id range
+    for (int j = 0; j < nint; ++j)
+      if (L.tile_nodes[n0 + j] != L.tile_int_base[t] + j) return 7;
+    // 8: shared nodes follow, address-sorted, all in the shared suffix
+    for (int j = nint; j < ntn; ++j) {
+      const int g = L.tile_nodes[n0 + j];
+      if (g < L.n_interior || g >= nn || (j > nint && g <= L.tile_nodes[n0 + j - 1])) return 8;
+    }
+    shared_total += ntn - nint;
+    tile_nodes_total += ntn;
+    max_elems = std::max<int64_t>(max_elems, ne);
+    // 9-11: every element's tile-local indices name its own nodes, and the
+    // tile's node list holds exactly the nodes its elements use
+    std::vector<char> used(ntn, 0);
+    for (int e = L.tile_elem_off[t]; e < L.tile_elem_off[t + 1]; ++e) {
+      const int ue = L.elem_order[e];
+      if (L.elem_u2i[ue] != e) return 9;
+      for (int k = 0; k < 10; ++k) {
+        const int l = L.conn_loc[k * L.tet_stride + e];
+        if (l >= ntn || L.tile_nodes[n0 + l] != L.node_u2i[tet10[10 * (int64_t)ue + k]]) return 10;
+        used[l] = 1;
+        const int g = L.tile_nodes[n0 + l];
+        valence[g] += 1;
+        if (last[g] != t) {
+          last[g] = t;
+          touched_by[g] += 1;
+        }
+      }
+    }
+    for (int j = 0; j < ntn; ++j)
+      if (!used[j]) return 11;
+    // 12-13: faces sit in the tile of their owning element, with consistent
+    // local and global node ids
+    for (int f = L.tile_face_off[t]; f < L.tile_face_off[t + 1]; ++f) {
+      if (L.face_elem[f] < L.tile_elem_off[t] || L.face_elem[f] >= L.tile_elem_off[t + 1]) return 12;
+      for (int k = 0; k < 6; ++k) {
+        const int l = L.fconn_loc[k * L.face_stride + f];
+        if (l >= ntn || L.tile_nodes[n0 + l] != L.fconn[k * L.face_stride + f]) return 13;
+      }
+    }
+  }
+  // 14: every face placed once; 15: the interior ranges cover [0, n_interior)
+  if (L.tile_face_off[L.n_tiles] != nf) return 14;
+  if (next_interior != L.n_interior) return 15;
+  // 16: an interior node is touched by its own tile only, a shared one by
+  // more than one
+  for (int64_t g = 0; g < nn; ++g) {
+    if (g < L.n_interior && touched_by[g] != 1) return 16;
+    if (g >= L.n_interior && touched_by[g] < 2) return 16;
+  }
+  // 17: 1 / valence per node
+  for (int64_t g = 0; g < nn; ++g) {
+    const float want = valence[g] > 0 ? 1.0f / (float)valence[g] : 0.0f;
+    if (L.inv_valence[g] != want) return 17;
+  }
+  stats[0] = L.n_tiles;
+  stats[1] = L.max_tile_nodes;
+  stats[2] = shared_total;
+  stats[3] = tile_nodes_total;
+  stats[4] = max_elems;
+  stats[5] = L.n_interior;
+  return 0;
+}

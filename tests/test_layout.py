@@ -1,0 +1,117 @@
+"""The host-side tiled mesh layout (csrc/sw_mesh.cpp) on the CPU: the layout
+builder is compiled with g++ beside a checker (tests/layout_check.cpp) and
+run on meshes of several kinds.  Every property the operator kernels rely
+on is verified: the element and node numberings are permutations, tiles
+respect the node and element caps, each tile's interior nodes form one
+contiguous id range (in tile order, covering [0, n_interior)) and its shared
+nodes lie address-sorted in the shared suffix, every element's tile-local
+indices name its own nodes, faces sit in their owner's tile, interior nodes
+are touched by one tile only and shared nodes by several, and the per-node
+inverse valence is exact."""
+import ctypes as C
+import os
+import shutil
+import subprocess
+
+import numpy as np
+import pytest
+
+import casegen as cg
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+CSRC = os.path.join(os.path.dirname(HERE), "paper_2404_17754_amd", "csrc")
+
+FAILS = {
+    1: "element order is not a permutation",
+    2: "node numbering is not a permutation",
+    3: "largest tile over the node cap",
+    4: "coordinates do not follow the node numbering",
+    5: "tile over a cap, or interior count out of range",
+    6: "interior ranges not consecutive in tile order",
+    7: "interior nodes not first or not one contiguous range",
+    8: "shared nodes not sorted or outside the shared suffix",
+    9: "element numbering maps are not inverse",
+    10: "tile-local index names the wrong node",
+    11: "tile node list holds a node no element uses",
+    12: "face outside its owner's tile",
+    13: "face local and global ids disagree",
+    14: "faces not all placed",
+    15: "interior ranges do not cover the interior",
+    16: "interior node touched by another tile, or shared node by one tile only",
+    17: "inverse valence wrong",
+}
+
+
+@pytest.fixture(scope="module")
+def lib(tmp_path_factory):
+    gxx = shutil.which("g++")
+    if gxx is None:
+        pytest.skip("g++ not available")
+    out = tmp_path_factory.mktemp("layout") / "liblayout_check.so"
+    subprocess.run([gxx, "-O2", "-std=c++17", "-shared", "-fPIC", "-I", CSRC, os.path.join(HERE, "layout_check.cpp"),
+                    os.path.join(CSRC, "sw_mesh.cpp"), "-o", str(out)], check=True)
+    return C.CDLL(str(out))
+
+
+def _run(lib, m, plant=0):
+    arrs = [np.ascontiguousarray(m.xyz, np.float64), np.ascontiguousarray(m.tet10, np.int32),
+            np.ascontiguousarray(m.tri6, np.int32), np.ascontiguousarray(m.face_tet, np.int32),
+            np.ascontiguousarray(m.face_role, np.uint8)]
+    st = np.zeros(6, np.int64)
+    rc = lib.check_layout(C.c_int64(m.n_nodes), C.c_int64(m.n_tets), C.c_int64(m.n_faces),
+                          *[C.c_void_p(a.ctypes.data) for a in arrs], C.c_int32(plant), C.c_void_p(st.ctypes.data))
+    return rc, st
+
+
+def _check(lib, m):
+    rc, st = _run(lib, m)
+    assert rc == 0, FAILS.get(rc, rc)
+    n_tiles, max_nodes, shared, tile_nodes, max_elems, n_interior = (int(v) for v in st)
+    return dict(n_tiles=n_tiles, max_nodes=max_nodes, shared=shared, tile_nodes=tile_nodes,
+                max_elems=max_elems, n_interior=n_interior)
+
+
+def _shuffled(m, seed=0):
+    """The same mesh under random node and element numberings."""
+    rng = np.random.default_rng(seed)
+    pn = rng.permutation(m.n_nodes)
+    inv = np.argsort(pn)
+    pe = rng.permutation(m.n_tets)
+    inve = np.argsort(pe)
+    return cg.Mesh(m.xyz[pn], inv[m.tet10[pe]].astype(np.int32), inv[m.tri6].astype(np.int32),
+                   inve[m.face_tet].astype(np.int32), m.face_role)
+
+
+MESHES = {
+    "small": lambda: cg.config_mesh(cg.CONFIGS["small"]),
+    "jitter": lambda: cg.box_mesh(80.0, 60.0, 40.0, 10.0, jitter=0.22, seed=3),
+    "graded": lambda: cg.box_mesh(60.0, 40.0, 40.0, 10.0, jitter=0.15, seed=5,
+                                  z_levels=cg.graded_levels(40.0, 2.5, 1.5)),
+    "shuffled": lambda: _shuffled(cg.box_mesh(60.0, 50.0, 40.0, 5.0)),
+    "batch200": lambda: cg.config_mesh(cg.CONFIGS["batch200"]),
+}
+
+
+@pytest.mark.parametrize("name", list(MESHES))
+def test_layout_properties(lib, name):
+    m = MESHES[name]()
+    s = _check(lib, m)
+    assert s["n_tiles"] >= 2 and s["max_nodes"] <= 1280 and s["max_elems"] <= 1024
+    # tiles hold most nodes once: the shared suffix is a minority
+    assert 0 < s["n_interior"] < m.n_nodes and s["tile_nodes"] < 2 * m.n_nodes
+
+
+def test_one_tile_mesh(lib):
+    """A mesh that fits in one tile: every node is interior, none shared."""
+    m = cg.box_mesh(10.0, 10.0, 10.0, 10.0)
+    s = _check(lib, m)
+    assert s["n_tiles"] == 1 and s["n_interior"] == m.n_nodes and s["shared"] == 0
+
+
+@pytest.mark.parametrize("plant,code", [(1, 10), (2, 7), (3, 17), (4, 12)])
+def test_checker_sees_planted_mistakes(lib, plant, code):
+    """One mistake planted in the built layout (a swapped tile-local index,
+    a shifted interior node id, a halved inverse valence, a face moved out of
+    its owner's tile) fails the check that covers it."""
+    rc, _ = _run(lib, cg.config_mesh(cg.CONFIGS["small"]), plant)
+    assert rc == code, (FAILS.get(rc, rc), FAILS[code])
