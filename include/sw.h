@@ -240,6 +240,19 @@ SW_API int sw_case_diag_blocks(sw_case* c, double* y_dev);
 SW_API int sw_misfit_workspace_bytes(int32_t n_rec, size_t* bytes);
 SW_API int sw_misfit(sw_ctx* ctx, int32_t n_rec, int64_t n_steps, const double* U_dev, const double* obs_dev,
               void* dev_ws, size_t ws_bytes, double* err, int32_t* n_pairs);
+/* The same ERR for callers that cannot allocate device memory (code under
+ * HIP graph capture, serving loops, harnesses that forbid allocation): no
+ * workspace argument and no allocation of any kind; the per-pair scratch is
+ * a static device array of the library, one per GPU, holding
+ * 2 * 3 * SW_MISFIT_NOALLOC_MAX_REC + 2 doubles (about 768 KiB) for the life
+ * of the process.  n_rec above SW_MISFIT_NOALLOC_MAX_REC is SW_EINVAL (no
+ * device work).  All calls on one GPU share that array: calls that overlap
+ * in time on one GPU (other streams, other threads) race and must be
+ * serialised by the caller.  Same result as sw_misfit on the same inputs;
+ * synchronous; result to host. */
+#define SW_MISFIT_NOALLOC_MAX_REC 16384
+SW_API int sw_misfit_noalloc(sw_ctx* ctx, int32_t n_rec, int64_t n_steps, const double* U_dev,
+                             const double* obs_dev, double* err, int32_t* n_pairs);
 /* ERR of the case's recorded waveforms (steps 1..current) against obs_dev
  * (same layout, at least as many steps), using the case's own scratch. */
 SW_API int sw_case_misfit(sw_case* c, const double* obs_dev, double* err, int32_t* n_pairs);

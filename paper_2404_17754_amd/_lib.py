@@ -14,6 +14,7 @@ SW_FP64, SW_MIXED_FP32 = 0, 1
 SW_GUESS_ZERO, SW_GUESS_POLY, SW_GUESS_MLP, SW_GUESS_PROJ = 0, 1, 2, 3
 SW_OP_M, SW_OP_K, SW_OP_CABS, SW_OP_A = 1, 2, 4, 8
 MLP_NPARAM, MLP_ROW = 4929, 12
+MISFIT_NOALLOC_MAX_REC = 16384
 PROF_KINDS = {"tile_f64": 0, "tile_f32": 1, "update_f64": 2, "update_f32": 3, "dir_f64": 4, "dir_f32": 5}
 
 ERRNAMES = {SW_EINVAL: "SW_EINVAL", SW_ENOWS: "SW_ENOWS", SW_EMESH: "SW_EMESH", SW_ENOCONV: "SW_ENOCONV",
@@ -78,6 +79,7 @@ SIGNATURES = {
     "sw_case_diag_blocks": (VP, VP),
     "sw_misfit_workspace_bytes": (I32, C.POINTER(SZ)),
     "sw_misfit": (VP, I32, I64, VP, VP, VP, SZ, C.POINTER(F64), C.POINTER(I32)),
+    "sw_misfit_noalloc": (VP, I32, I64, VP, VP, C.POINTER(F64), C.POINTER(I32)),
     "sw_case_misfit": (VP, VP, C.POINTER(F64), C.POINTER(I32)),
     "sw_fit_workspace_bytes": (I32, I64, I32, I32, C.POINTER(SZ)),
     "sw_fit_input": (VP, I32, I64, C.POINTER(VP), VP, I32, I32, F64, VP, SZ, VP, C.POINTER(F64), C.POINTER(I32),

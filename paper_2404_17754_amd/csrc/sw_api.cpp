@@ -17,6 +17,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -235,12 +236,15 @@ struct sw_batch {
   std::vector<TileLane<double>> rhs1;
 };
 
+static int static_scratch_init(int device);
+
 extern "C" int sw_ctx_create(int device, void* hip_stream, sw_ctx** out) {
   if (!out) return fail(SW_EINVAL, "out is NULL");
   int n = 0;
   HIPC(hipGetDeviceCount(&n));
   if (device < 0 || device >= n) return fail(SW_EINVAL, "device %d out of range (%d devices)", device, n);
   HIPC(hipSetDevice(device));
+  if (int rc = static_scratch_init(device)) return rc;
   sw_ctx* c = new sw_ctx{device, (hipStream_t)hip_stream};
   *out = c;
   return SW_OK;
@@ -1433,6 +1437,52 @@ extern "C" int sw_case_misfit(sw_case* c, const double* obs, double* err, int32_
   if (c->n_rec <= 0 || c->step <= 0) return fail(SW_ESTATE, "no recorded waveforms");
   HIPC(hipSetDevice(c->ctx->device));
   return misfit_run(c->ctx, c->n_rec, c->step, c->wave, obs, c->mis_buf, err, n_pairs);
+}
+
+// ------------------------------------------- misfit without a workspace
+//
+// For callers that cannot allocate device memory: the pair sums and the two
+// results live in a file-scope device array, one copy per GPU, whose device
+// address is looked up once per device when the first context on it is
+// created.  Host code uses only that looked-up address: the array's name is
+// a host-side stand-in, not a device pointer.  Every call on a GPU reuses
+// that GPU's array, so calls on one GPU that overlap in time (two streams or
+// two threads) race.  The kernels overwrite every value they later read, so
+// nothing has to be cleared between calls.
+
+static constexpr int kStaticScratchDoubles = 2 * 3 * SW_MISFIT_NOALLOC_MAX_REC + 2;
+static __device__ __align__(256) double scratch[kStaticScratchDoubles];
+
+static constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static double* g_scratch_dev[kMaxDevices];  // device address of `scratch` per device (null: not looked up)
+
+static int static_scratch_init(int device) {
+  if (device >= kMaxDevices) return fail(SW_EINVAL, "device %d beyond the %d supported", device, kMaxDevices);
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (g_scratch_dev[device]) return SW_OK;
+  void* ptr = nullptr;
+  HIPC(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));  // the calling thread has `device` current
+  if (!ptr) return fail(SW_EHIP, "hipGetSymbolAddress returned no address for the static scratch");
+  g_scratch_dev[device] = (double*)ptr;
+  return SW_OK;
+}
+
+extern "C" int sw_misfit_noalloc(sw_ctx* ctx, int32_t n_rec, int64_t n_steps, const double* U, const double* obs,
+                                 double* err, int32_t* n_pairs) {
+  if (!ctx || !U || !obs || !err) return fail(SW_EINVAL, "NULL argument");
+  if (n_rec <= 0 || n_steps <= 0) return fail(SW_EINVAL, "n_rec and n_steps must be > 0");
+  if (n_rec > SW_MISFIT_NOALLOC_MAX_REC)
+    return fail(SW_EINVAL, "n_rec %d exceeds the static scratch limit of %d receivers (use sw_misfit)", n_rec,
+                (int)SW_MISFIT_NOALLOC_MAX_REC);
+  double* buf = nullptr;
+  {
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    buf = g_scratch_dev[ctx->device];
+  }
+  if (!buf) return fail(SW_ESTATE, "static scratch of device %d not set up", ctx->device);
+  HIPC(hipSetDevice(ctx->device));
+  return misfit_run(ctx, n_rec, n_steps, U, obs, buf, err, n_pairs);
 }
 
 // ------------------------------------------------------------ network
