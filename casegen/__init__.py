@@ -421,6 +421,23 @@ def make_case(mesh: Mesh, cfg: BoxConfig, seed=None, n_steps=None, xi=0.02, damp
                 meta=dict(seed=seed, amp=amp, corr=corr, h0=cfg.h0))
 
 
+def smooth_field(mesh: Mesh, seed, corr, amp, nmodes=32, chunk=1 << 18):
+    """Seeded smooth random vector field at the nodes (3 * n_nodes values,
+    node-major): per component a sum of random Fourier features in 3D with
+    Gaussian covariance exp(-r^2/corr^2), scaled so that its largest
+    magnitude over the nodes is ``amp``.  Used as an initial velocity that
+    sets every element of a large mesh in motion from the first step."""
+    rng = np.random.default_rng([seed, 11])
+    out = np.empty((mesh.n_nodes, 3))
+    for c in range(3):
+        k = rng.normal(0.0, math.sqrt(2.0) / corr, (nmodes, 3))
+        ph = rng.uniform(0.0, 2.0 * math.pi, nmodes)
+        for s in range(0, mesh.n_nodes, chunk):
+            out[s:s + chunk, c] = np.cos(mesh.xyz[s:s + chunk] @ k.T + ph[None]).sum(1)
+    out *= amp / max(np.abs(out).max(), 1e-300)
+    return out.ravel()
+
+
 def random_vector(n, seed, dtype=np.float64):
     """Seeded standard-normal vector for operator parity tests."""
     return np.random.default_rng(seed).standard_normal(n).astype(dtype)

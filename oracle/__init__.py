@@ -22,6 +22,9 @@ Modules:
   fem      element and boundary-face matrices by numerical quadrature
   assemble global sparse matrices
   march    Newmark time march
+  bsr      the same system assembled as symmetric 3x3 block-sparse FP64
+           matrices and marched with block-Jacobi CG (C++/OpenMP,
+           native/bsr_march.cpp), for meshes too large for SciPy
   misfit   ERR of Eq. (eqerr)
   mlp      FP64 forward/backward of the initial-guess network
 
