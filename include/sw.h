@@ -113,6 +113,13 @@ SW_API const char* sw_version(void);
 SW_API int sw_ctx_create(int device, void* hip_stream, sw_ctx** out);
 SW_API int sw_ctx_destroy(sw_ctx* ctx);
 
+/* Workgroup count of the persistent FP32 operator passes (single case and
+ * batch lanes) of objects on this context: 0 (default) = three per compute
+ * unit, else at most max_workgroups (a positive multiple of 8, one run per
+ * XCD), so that each workgroup walks more tiles.  A tuning and test knob;
+ * results are the same to rounding.  SW_EINVAL for other values. */
+SW_API int sw_ctx_set_grid_cap(sw_ctx* ctx, int32_t max_workgroups);
+
 /* Kernel classes timed by the optional profiler: the matrix-free operator
  * (tile kernel) and the two CG vector kernels, per precision, as launched
  * inside the CG iterations of sw_case_step. */
@@ -149,6 +156,9 @@ typedef struct {
   const int32_t* tri6;        /* host, n_faces x 6 */
   const int32_t* face_tet;    /* host, n_faces: the tet each face belongs to */
   const uint8_t* face_role;   /* host, n_faces: 1 side, 2 base */
+  int32_t tile_max_nodes;     /* tile capacity of the device layout: distinct nodes per tile,
+                                 64..1280 (0 = 1280) */
+  int32_t tile_max_elems;     /* elements per tile, 16..1024 (0 = 1024) */
 } sw_mesh_desc;
 
 /* Device workspace needed by sw_mesh_create for this mesh. */
@@ -157,6 +167,9 @@ SW_API int sw_mesh_workspace_bytes(const sw_mesh_desc* desc, size_t* bytes);
  * midpoints to 1e-9 relative, faces being faces of their owning tet),
  * builds the device layout and uploads it into dev_ws. */
 SW_API int sw_mesh_create(sw_ctx* ctx, const sw_mesh_desc* desc, void* dev_ws, size_t ws_bytes, sw_mesh** out);
+/* Tiles of the device layout and the largest tile's node count (either
+ * pointer may be NULL). */
+SW_API int sw_mesh_info(const sw_mesh* mesh, int32_t* n_tiles, int32_t* max_tile_nodes);
 SW_API int sw_mesh_destroy(sw_mesh* mesh);
 
 /* ----------------------------------------------------------------- case */
@@ -345,6 +358,22 @@ SW_API int sw_fit_input(sw_ctx* ctx, int32_t n_rec, int64_t n_steps, const doubl
                         int32_t stride, int32_t n_shift, double rel_cut, void* dev_ws, size_t ws_bytes,
                         double* c_host, double* err, int32_t* n_pairs, int32_t* rank, double* U_dev);
 
+/* Several observed events of one model (Section 3: the records of several
+ * earthquakes at the same site, Table of events; Section 2: the model is
+ * judged by its misfit): the Green's records are the model's and are
+ * computed once; the input of each event is estimated on its own exactly as
+ * sw_fit_input does (the same workspace, reused event after event), and
+ * the model's misfit is the largest ERR over its events (its worst event).
+ * obs: host array of n_events device pointers, each [n_steps][n_rec][3].
+ * Outputs (host): c_host (n_events x 3 x n_shift), err (n_events),
+ * n_pairs and rank (n_events each, optional), err_max (the largest ERR; NaN
+ * when an event has no usable pair, which is then the worst) and worst (its
+ * event index, optional).  Synchronises the context stream. */
+SW_API int sw_fit_events(sw_ctx* ctx, int32_t n_rec, int64_t n_steps, const double* const* green, int32_t n_events,
+                         const double* const* obs, int32_t stride, int32_t n_shift, double rel_cut, void* dev_ws,
+                         size_t ws_bytes, double* c_host, double* err, int32_t* n_pairs, int32_t* rank,
+                         double* err_max, int32_t* worst);
+
 /* ----------------------------------------------------------------- batch */
 
 /* A batch marches many candidate models together: the repeated analyses of
@@ -365,12 +394,25 @@ SW_API int sw_fit_input(sw_ctx* ctx, int32_t n_rec, int64_t n_steps, const doubl
  * sw_batch_workspace_bytes gives (lane tables and work list), borrowed until
  * sw_batch_destroy.  sw_batch_step advances every case n_steps steps
  * (SW_ESTATE if one would pass its capacity or lacks its network) and
- * synchronises the context stream; statistics, logs and waveforms are read
- * per case. */
+ * synchronises the context stream: each refinement round of a step decides
+ * on the host, from the lanes' FP64 true residuals, which lanes run another
+ * inner solve and to what tolerance, and the projection guess solves its
+ * small Gram system on the host.  sw_batch_stats gives every lane's
+ * statistics in lane order; logs and waveforms are read per case. */
 SW_API int sw_batch_workspace_bytes(sw_case* const* cases, int32_t n, size_t* bytes);
 SW_API int sw_batch_create(sw_ctx* ctx, sw_case* const* cases, int32_t n, void* dev_ws, size_t ws_bytes,
                     sw_batch** out);
 SW_API int sw_batch_step(sw_batch* b, int32_t n_steps);
+/* Statistics of every lane (out: n entries, lane order; as
+ * sw_case_stats_get of each case). */
+SW_API int sw_batch_stats(const sw_batch* b, sw_case_stats* out);
+/* y[l] = A_l x[l] for every lane l through the batch's FP32 lane pass, the
+ * very launch an inner CG iteration of sw_batch_step makes (A_l: lane l's
+ * step operator; x, y: host arrays of n device pointers to 3 * n_nodes
+ * floats of that lane's mesh, caller's node order).  Uses the lanes'
+ * inner-solve vectors, which are free between steps.  For testing the lane
+ * pass.  Synchronous. */
+SW_API int sw_batch_apply_f32(sw_batch* b, const float* const* x, float* const* y);
 SW_API int sw_batch_destroy(sw_batch* b);
 
 #ifdef __cplusplus

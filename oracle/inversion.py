@@ -72,6 +72,17 @@ def fit(G, obs, stride, n_shift, rel_cut=1e-6):
     return c.reshape(3, n_shift), U, e, used, int(keep.sum())
 
 
+def fit_events(G, events, stride, n_shift, rel_cut=1e-6):
+    """Several observed events of one model (Section 3, the events recorded
+    at one site): the Green's records G are the model's, each event's input
+    is fitted on its own (fit), and the model's misfit is its worst event's
+    ERR.  Returns (list of fit results per event, largest ERR, its event)."""
+    fits = [fit(G, obs, stride, n_shift, rel_cut) for obs in events]
+    errs = [f[2] for f in fits]
+    worst = int(np.argmax(errs))
+    return fits, errs[worst], worst
+
+
 def objective(G, obs, stride, c):
     """J(c) = sum_{k,i} |U - obs|^2 / |obs|^2 over the non-silent pairs."""
     c = np.asarray(c, float)

@@ -59,6 +59,10 @@ class Context:
         L.check(self.lib.sw_ctx_create(device, C.c_void_p(stream.cuda_stream), C.byref(h)))
         self.h = h
 
+    def set_grid_cap(self, max_workgroups):
+        """Cap the workgroups of the persistent FP32 passes (0: default)."""
+        L.check(self.lib.sw_ctx_set_grid_cap(self.h, int(max_workgroups)))
+
     def profile(self, enable=True, kinds=None, every=1):
         """Start (reset) or stop per-kernel HIP-event timing of the CG kernels:
         all classes, or only those named in `kinds` (see profile_read), one
@@ -87,7 +91,10 @@ class Context:
 
 
 class Mesh:
-    def __init__(self, ctx: Context, m):
+    """Device layout of a mesh (sw_mesh_create).  tile_nodes / tile_elems:
+    tile capacity (0 = the library's default 1280 / 1024)."""
+
+    def __init__(self, ctx: Context, m, tile_nodes=0, tile_elems=0):
         self.ctx = ctx
         lib = ctx.lib
         self._xyz = np.ascontiguousarray(m.xyz, np.float64)
@@ -97,7 +104,7 @@ class Mesh:
         self._fr = np.ascontiguousarray(m.face_role, np.uint8)
         self.n_nodes, self.n_tets, self.n_faces = len(self._xyz), len(self._tet), len(self._tri)
         d = L.MeshDesc(self.n_nodes, self.n_tets, self.n_faces, _ptr(self._xyz), _ptr(self._tet),
-                       _ptr(self._tri), _ptr(self._ft), _ptr(self._fr))
+                       _ptr(self._tri), _ptr(self._ft), _ptr(self._fr), tile_nodes, tile_elems)
         nb = C.c_size_t()
         L.check(lib.sw_mesh_workspace_bytes(C.byref(d), C.byref(nb)))
         self.ws = _workspace(nb.value, ctx.device)
@@ -105,6 +112,12 @@ class Mesh:
         L.check(lib.sw_mesh_create(ctx.h, C.byref(d), C.c_void_p(self.ws.data_ptr()), nb.value, C.byref(h)))
         self.h = h
         del self._xyz, self._tet, self._tri, self._ft, self._fr
+
+    def info(self):
+        """(tiles, largest tile's node count) of the device layout."""
+        nt, mx = C.c_int32(), C.c_int32()
+        L.check(self.ctx.lib.sw_mesh_info(self.h, C.byref(nt), C.byref(mx)))
+        return nt.value, mx.value
 
     def __del__(self):
         if getattr(self, "h", None):
@@ -383,13 +396,34 @@ def fit_input(ctx: Context, green, obs, stride, n_shift, rel_cut=1e-6, return_re
 
 
 def fit_events(ctx: Context, green, events, stride, n_shift, rel_cut=1e-6):
-    """One model's misfit over several observed events: the Green's records
-    are computed once per model (they do not depend on the event) and the
-    input is estimated per event with sw_fit_input.  Returns the list of
-    (c, ERR, pairs, rank) per event and the largest ERR (the model's worst
-    event)."""
-    fits = [fit_input(ctx, green, obs, stride, n_shift, rel_cut) for obs in events]
-    return fits, max(f[1] for f in fits)
+    """One model's misfit over several observed events (sw_fit_events): the
+    Green's records are the model's, the input is estimated per event, and
+    the model's misfit is its worst event's.  Returns the list of
+    (c (3, n_shift), ERR, pairs, rank) per event, the largest ERR and the
+    index of that event."""
+    torch = _torch()
+    green = [g.to(ctx.device, torch.float64).contiguous() for g in green]
+    events = [o.to(ctx.device, torch.float64).contiguous() for o in events]
+    n_steps, n_rec = int(events[0].shape[0]), int(events[0].shape[1])
+    for t in green + events:
+        if tuple(t.shape) != (n_steps, n_rec, 3):
+            raise ValueError("Green's and observed records must all have the same (n_steps, n_rec, 3) shape")
+    ne = len(events)
+    nb = C.c_size_t()
+    L.check(ctx.lib.sw_fit_workspace_bytes(n_rec, n_steps, int(stride), int(n_shift), C.byref(nb)))
+    ws = _workspace(nb.value, ctx.device)
+    gp = (C.c_void_p * 3)(*[g.data_ptr() for g in green])
+    op = (C.c_void_p * ne)(*[o.data_ptr() for o in events])
+    c = np.zeros((ne, 3, int(n_shift)))
+    err = np.zeros(ne)
+    used = np.zeros(ne, np.int32)
+    rank = np.zeros(ne, np.int32)
+    emax, worst = C.c_double(), C.c_int32()
+    L.check(ctx.lib.sw_fit_events(ctx.h, n_rec, n_steps, gp, ne, op, int(stride), int(n_shift), float(rel_cut),
+                                  C.c_void_p(ws.data_ptr()), nb.value, _ptr(c), _ptr(err), _ptr(used), _ptr(rank),
+                                  C.byref(emax), C.byref(worst)))
+    fits = [(c[e], float(err[e]), int(used[e]), int(rank[e])) for e in range(ne)]
+    return fits, emax.value, worst.value
 
 
 class Batch:
@@ -408,6 +442,23 @@ class Batch:
 
     def step(self, n=1):
         L.check(self.ctx.lib.sw_batch_step(self.h, int(n)))
+
+    def stats(self):
+        """Statistics of every lane (sw_batch_stats), in lane order."""
+        out = (L.CaseStats * len(self.cases))()
+        L.check(self.ctx.lib.sw_batch_stats(self.h, out))
+        return [{"steps": s.steps, "cg_iters": s.cg_iters, "ir_outer": s.ir_outer,
+                 "max_true_rel_res": s.max_true_rel_res, "flags": s.flags} for s in out]
+
+    def apply_f32(self, xs):
+        """Lane pass y_l = A_l x_l (FP32 device vectors, one per case)."""
+        torch = _torch()
+        xs = [c._vec(x, torch.float32) for c, x in zip(self.cases, xs)]
+        ys = [torch.empty_like(x) for x in xs]
+        xa = (C.c_void_p * len(xs))(*[x.data_ptr() for x in xs])
+        ya = (C.c_void_p * len(ys))(*[y.data_ptr() for y in ys])
+        L.check(self.ctx.lib.sw_batch_apply_f32(self.h, xa, ya))
+        return ys
 
     def __del__(self):
         if getattr(self, "h", None):

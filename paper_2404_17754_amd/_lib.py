@@ -30,7 +30,8 @@ class SwError(RuntimeError):
 class MeshDesc(C.Structure):
     _fields_ = [("n_nodes", C.c_int64), ("n_tets", C.c_int64), ("n_faces", C.c_int64),
                 ("xyz", C.c_void_p), ("tet10", C.c_void_p), ("tri6", C.c_void_p),
-                ("face_tet", C.c_void_p), ("face_role", C.c_void_p)]
+                ("face_tet", C.c_void_p), ("face_role", C.c_void_p), ("tile_max_nodes", C.c_int32),
+                ("tile_max_elems", C.c_int32)]
 
 
 class CaseDesc(C.Structure):
@@ -56,11 +57,13 @@ SIGNATURES = {
     "sw_version": (),
     "sw_ctx_create": (C.c_int, VP, PP),
     "sw_ctx_destroy": (VP,),
+    "sw_ctx_set_grid_cap": (VP, I32),
     "sw_ctx_profile": (VP, I32),
     "sw_ctx_profile_kinds": (VP, C.c_uint32, I32),
     "sw_ctx_profile_read": (VP, I32, C.POINTER(F64), C.POINTER(I64), C.POINTER(F64), C.POINTER(I64)),
     "sw_mesh_workspace_bytes": (C.POINTER(MeshDesc), C.POINTER(SZ)),
     "sw_mesh_create": (VP, C.POINTER(MeshDesc), VP, SZ, PP),
+    "sw_mesh_info": (VP, C.POINTER(I32), C.POINTER(I32)),
     "sw_mesh_destroy": (VP,),
     "sw_case_workspace_bytes": (VP, C.POINTER(CaseDesc), C.POINTER(SZ)),
     "sw_case_create": (VP, VP, C.POINTER(CaseDesc), VP, SZ, PP),
@@ -84,6 +87,8 @@ SIGNATURES = {
     "sw_fit_workspace_bytes": (I32, I64, I32, I32, C.POINTER(SZ)),
     "sw_fit_input": (VP, I32, I64, C.POINTER(VP), VP, I32, I32, F64, VP, SZ, VP, C.POINTER(F64), C.POINTER(I32),
                      C.POINTER(I32), VP),
+    "sw_fit_events": (VP, I32, I64, C.POINTER(VP), I32, C.POINTER(VP), I32, I32, F64, VP, SZ, VP, VP, VP, VP,
+                      C.POINTER(F64), C.POINTER(I32)),
     "sw_mlp_init_params": (C.c_uint64, VP),
     "sw_mlp_workspace_bytes": (C.POINTER(SZ),),
     "sw_mlp_create": (VP, VP, VP, SZ, PP),
@@ -98,6 +103,8 @@ SIGNATURES = {
     "sw_batch_workspace_bytes": (C.POINTER(VP), I32, C.POINTER(SZ)),
     "sw_batch_create": (VP, C.POINTER(VP), I32, VP, SZ, PP),
     "sw_batch_step": (VP, I32),
+    "sw_batch_stats": (VP, C.POINTER(CaseStats)),
+    "sw_batch_apply_f32": (VP, C.POINTER(VP), C.POINTER(VP)),
     "sw_batch_destroy": (VP,),
 }
 

@@ -102,6 +102,7 @@ struct sw_ctx {
   int device;
   hipStream_t stream;
   KernelProfiler prof;
+  int grid_cap = 0;  // workgroup cap of the persistent FP32 passes (0: none)
 };
 
 namespace {
@@ -245,7 +246,7 @@ extern "C" int sw_ctx_create(int device, void* hip_stream, sw_ctx** out) {
   if (device < 0 || device >= n) return fail(SW_EINVAL, "device %d out of range (%d devices)", device, n);
   HIPC(hipSetDevice(device));
   if (int rc = static_scratch_init(device)) return rc;
-  sw_ctx* c = new sw_ctx{device, (hipStream_t)hip_stream};
+  sw_ctx* c = new sw_ctx{device, (hipStream_t)hip_stream, {}, 0};
   *out = c;
   return SW_OK;
 }
@@ -254,6 +255,14 @@ extern "C" int sw_ctx_destroy(sw_ctx* ctx) {
   if (ctx)
     for (hipEvent_t e : ctx->prof.ev) (void)hipEventDestroy(e);
   delete ctx;
+  return SW_OK;
+}
+
+extern "C" int sw_ctx_set_grid_cap(sw_ctx* ctx, int32_t max_workgroups) {
+  if (!ctx) return fail(SW_EINVAL, "NULL context");
+  if (max_workgroups < 0 || max_workgroups % 8)
+    return fail(SW_EINVAL, "grid cap %d is not 0 or a positive multiple of 8", max_workgroups);
+  ctx->grid_cap = max_workgroups;
   return SW_OK;
 }
 
@@ -323,6 +332,10 @@ static int validate_mesh(const sw_mesh_desc* d) {
   if (d->n_nodes > (int64_t)INT32_MAX / 3) return fail(SW_EINVAL, "too many nodes for int32 indexing");
   if (!d->xyz || !d->tet10 || (d->n_faces > 0 && (!d->tri6 || !d->face_tet || !d->face_role)))
     return fail(SW_EINVAL, "NULL mesh array");
+  if (d->tile_max_nodes != 0 && (d->tile_max_nodes < 64 || d->tile_max_nodes > TILE_MAX_NODES))
+    return fail(SW_EINVAL, "tile_max_nodes %d outside 64..%d (0: default)", d->tile_max_nodes, TILE_MAX_NODES);
+  if (d->tile_max_elems != 0 && (d->tile_max_elems < 16 || d->tile_max_elems > TILE_MAX_ELEMS))
+    return fail(SW_EINVAL, "tile_max_elems %d outside 16..%d (0: default)", d->tile_max_elems, TILE_MAX_ELEMS);
   for (int64_t i = 0; i < 3 * d->n_nodes; ++i)
     if (!std::isfinite(d->xyz[i])) return fail(SW_EMESH, "non-finite coordinate at node %lld", (long long)(i / 3));
   static const int EA[6] = {0, 1, 0, 0, 1, 2}, EB[6] = {1, 2, 2, 3, 3, 3};
@@ -380,28 +393,55 @@ static int validate_mesh(const sw_mesh_desc* d) {
 
 namespace {
 
+// FNV-1a-style digest (over 8-byte words, then the tail bytes) of a mesh's
+// arrays: the layout cache below is keyed by the contents, not by the
+// addresses, which a freed and reallocated array of the same size can take
+// again.
+uint64_t mesh_digest(const sw_mesh_desc* d) {
+  uint64_t h = 1469598103934665603ull;
+  auto mix = [&](const void* p, size_t n) {
+    const uint8_t* b = (const uint8_t*)p;
+    size_t i = 0;
+    for (; i + 8 <= n; i += 8) {
+      uint64_t w;
+      std::memcpy(&w, b + i, 8);
+      h = (h ^ w) * 1099511628211ull;
+    }
+    for (; i < n; ++i) h = (h ^ b[i]) * 1099511628211ull;
+  };
+  mix(d->xyz, 24 * (size_t)d->n_nodes);
+  mix(d->tet10, 40 * (size_t)d->n_tets);
+  if (d->n_faces > 0) {
+    mix(d->tri6, 24 * (size_t)d->n_faces);
+    mix(d->face_tet, 4 * (size_t)d->n_faces);
+    mix(d->face_role, (size_t)d->n_faces);
+  }
+  return h;
+}
+
 // The tiled layout of the last mesh sized by sw_mesh_workspace_bytes, so the
 // create call that normally follows does not rebuild it.
 struct LayoutCache {
-  const void* xyz = nullptr;
-  const void* tet10 = nullptr;
-  const void* tri6 = nullptr;
+  uint64_t digest = 0;
   int64_t n_nodes = -1, n_tets = -1, n_faces = -1;
+  int32_t cap_nodes = -1, cap_elems = -1;
   HostLayout L;
-  bool matches(const sw_mesh_desc* d) const {
-    return xyz == d->xyz && tet10 == d->tet10 && tri6 == d->tri6 && n_nodes == d->n_nodes && n_tets == d->n_tets &&
-           n_faces == d->n_faces;
+  bool matches(const sw_mesh_desc* d, uint64_t dig) const {
+    return digest == dig && n_nodes == d->n_nodes && n_tets == d->n_tets && n_faces == d->n_faces &&
+           cap_nodes == d->tile_max_nodes && cap_elems == d->tile_max_elems;
   }
 };
 thread_local LayoutCache g_layout;
 
 const HostLayout& layout_for(const sw_mesh_desc* d) {
-  if (!g_layout.matches(d)) {
+  const uint64_t dig = mesh_digest(d);
+  if (!g_layout.matches(d, dig)) {
     build_layout(d->n_nodes, d->n_tets, d->n_faces, d->xyz, d->tet10, d->tri6, d->face_tet, d->face_role,
-                 g_layout.L);
-    g_layout.xyz = d->xyz;
-    g_layout.tet10 = d->tet10;
-    g_layout.tri6 = d->tri6;
+                 g_layout.L, d->tile_max_nodes ? d->tile_max_nodes : TILE_MAX_NODES,
+                 d->tile_max_elems ? d->tile_max_elems : TILE_MAX_ELEMS);
+    g_layout.cap_nodes = d->tile_max_nodes;
+    g_layout.cap_elems = d->tile_max_elems;
+    g_layout.digest = dig;
     g_layout.n_nodes = d->n_nodes;
     g_layout.n_tets = d->n_tets;
     g_layout.n_faces = d->n_faces;
@@ -510,6 +550,13 @@ extern "C" int sw_mesh_create(sw_ctx* ctx, const sw_mesh_desc* d, void* ws, size
   HIPC(hipStreamSynchronize(s));
   sw_mesh* m = new sw_mesh{ctx, md, d->n_nodes, d->n_tets, d->n_faces, L.elem_order, L.node_u2i, L.node_i2u};
   *out = m;
+  return SW_OK;
+}
+
+extern "C" int sw_mesh_info(const sw_mesh* m, int32_t* n_tiles, int32_t* max_tile_nodes) {
+  if (!m) return fail(SW_EINVAL, "NULL mesh");
+  if (n_tiles) *n_tiles = (int32_t)m->dev.n_tiles;
+  if (max_tile_nodes) *max_tile_nodes = (int32_t)m->dev.max_tile_nodes;
   return SW_OK;
 }
 
@@ -683,7 +730,7 @@ int apply_f32(sw_case* c, int op, const float* x, float* y, CgCtl* ctl, int iter
   A.xf = x;
   A.y = y;
   A.n_mat = c->n_mat;
-  launch_tile_f32(c->mesh->dev, c->emat, c->mats, A, ctl, iter, c->ctx->stream);
+  launch_tile_f32(c->mesh->dev, c->emat, c->mats, A, ctl, iter, c->ctx->grid_cap, c->ctx->stream);
   LAUNCHED();
   return SW_OK;
 }
@@ -1532,6 +1579,10 @@ extern "C" int sw_fit_workspace_bytes(int32_t n_rec, int64_t n_steps, int32_t st
   return SW_OK;
 }
 
+static int fit_one(sw_ctx* ctx, int32_t n_rec, int64_t n_steps, const double* const* green, const double* obs,
+                   int32_t stride, int32_t n_shift, double rel_cut, void* ws, double* c_host, double* err,
+                   int32_t* n_pairs, int32_t* rank, double* U_dev);
+
 extern "C" int sw_fit_input(sw_ctx* ctx, int32_t n_rec, int64_t n_steps, const double* const* green,
                             const double* obs, int32_t stride, int32_t n_shift, double rel_cut, void* ws,
                             size_t ws_bytes, double* c_host, double* err, int32_t* n_pairs, int32_t* rank,
@@ -1549,6 +1600,56 @@ extern "C" int sw_fit_input(sw_ctx* ctx, int32_t n_rec, int64_t n_steps, const d
       return fail(SW_ENOWS, "fit workspace needs %zu bytes, 256-byte aligned", need);
   }
   HIPC(hipSetDevice(ctx->device));
+  return fit_one(ctx, n_rec, n_steps, green, obs, stride, n_shift, rel_cut, ws, c_host, err, n_pairs, rank, U_dev);
+}
+
+extern "C" int sw_fit_events(sw_ctx* ctx, int32_t n_rec, int64_t n_steps, const double* const* green,
+                             int32_t n_events, const double* const* obs, int32_t stride, int32_t n_shift,
+                             double rel_cut, void* ws, size_t ws_bytes, double* c_host, double* err,
+                             int32_t* n_pairs, int32_t* rank, double* err_max, int32_t* worst) {
+  if (!ctx || !green || !obs || !c_host || !err || !err_max) return fail(SW_EINVAL, "NULL argument");
+  if (n_events < 1) return fail(SW_EINVAL, "n_events must be >= 1");
+  for (int j = 0; j < 3; ++j)
+    if (!green[j]) return fail(SW_EINVAL, "Green's record %d is NULL", j);
+  for (int e = 0; e < n_events; ++e)
+    if (!obs[e]) return fail(SW_EINVAL, "observed record of event %d is NULL", e);
+  int rc = fit_check(n_rec, n_steps, stride, n_shift);
+  if (rc) return rc;
+  if (!(rel_cut >= 0.0 && rel_cut < 1.0)) return fail(SW_EINVAL, "rel_cut must be in [0, 1)");
+  {
+    Carver dry(nullptr);
+    const size_t need = fit_layout(n_rec, n_steps, stride, dry, nullptr);
+    if (!ws || ((uintptr_t)ws & 255) || ws_bytes < need)
+      return fail(SW_ENOWS, "fit workspace needs %zu bytes, 256-byte aligned", need);
+  }
+  HIPC(hipSetDevice(ctx->device));
+  // the Green's records are the model's; each event is fitted on its own
+  // (the weights 1/|obs|^2 of the normal equations are the event's), and
+  // the model's misfit is that of its worst event
+  int w = -1;
+  double mx = 0.0;
+  for (int e = 0; e < n_events; ++e) {
+    rc = fit_one(ctx, n_rec, n_steps, green, obs[e], stride, n_shift, rel_cut, ws, c_host + (size_t)e * 3 * n_shift,
+                 err + e, n_pairs ? n_pairs + e : nullptr, rank ? rank + e : nullptr, nullptr);
+    if (rc) return rc;
+    if (err[e] != err[e]) {  // an event with no usable pair: the model's misfit is undefined
+      w = e;
+      mx = err[e];
+      break;
+    }
+    if (w < 0 || err[e] > mx) {
+      w = e;
+      mx = err[e];
+    }
+  }
+  *err_max = mx;
+  if (worst) *worst = w;
+  return SW_OK;
+}
+
+static int fit_one(sw_ctx* ctx, int32_t n_rec, int64_t n_steps, const double* const* green, const double* obs,
+                   int32_t stride, int32_t n_shift, double rel_cut, void* ws, double* c_host, double* err,
+                   int32_t* n_pairs, int32_t* rank, double* U_dev) {
   hipStream_t s = ctx->stream;
   FitWs f;
   Carver cv(ws);
@@ -1974,7 +2075,8 @@ int batch_step_once(sw_batch* b) {
       for (int k = 0; k < chunk; ++k) {
         const int i = it + k;
         int ev = prof_begin(cx, SW_PROF_TILE_F32);
-        launch_tile_lanes_pipe_f32(b->d_cg32, b->d_items, b->n_items, b->max_tile_nodes, b->d_st, i, s);
+        launch_tile_lanes_pipe_f32(b->d_cg32, b->d_items, b->n_items, b->max_tile_nodes, b->d_st, i,
+                                   b->ctx->grid_cap, s);
         prof_end(cx, ev);
         ev = prof_begin(cx, SW_PROF_UPDATE_F32);
         launch_lanes_cg(true, false, n, b->max_nodes, b->d_lanes, b->d_st, i, s);
@@ -2179,6 +2281,47 @@ extern "C" int sw_batch_create(sw_ctx* ctx, sw_case* const* cases, int32_t n, vo
     return rc;
   }
   *out = b;
+  return SW_OK;
+}
+
+extern "C" int sw_batch_apply_f32(sw_batch* b, const float* const* x, float* const* y) {
+  if (!b || !x || !y) return fail(SW_EINVAL, "NULL argument");
+  for (int l = 0; l < b->n; ++l)
+    if (!x[l] || !y[l]) return fail(SW_EINVAL, "NULL vector of lane %d", l);
+  HIPC(hipSetDevice(b->ctx->device));
+  hipStream_t s = b->ctx->stream;
+  // every lane's inner-solve vectors and control block are free between
+  // steps: the input goes into p32, q32 is cleared whole, and a fresh
+  // control block makes every work item run in full (an iteration past the
+  // first, as in an inner CG iteration)
+  for (int l = 0; l < b->n; ++l) {
+    sw_case* c = b->cases[l];
+    const int64_t nn = c->mesh->n_nodes;
+    launch_permute_f32(nn, 3, x[l], c->mesh->dev.node_i2u, c->p32, s);
+    launch_fill_f32(3 * nn, c->q32, 0.0f, s);
+    launch_fill_f64(sizeof(CgCtl) / 8, (double*)c->ctl32, 0.0, s);
+    b->st[l].active = 1;
+  }
+  LAUNCHED();
+  int rc = batch_upload(b, b->d_st, b->st.data(), b->n * sizeof(LaneState));
+  if (rc) return rc;
+  launch_tile_lanes_pipe_f32(b->d_cg32, b->d_items, b->n_items, b->max_tile_nodes, b->d_st, 1, b->ctx->grid_cap,
+                             s);
+  for (int l = 0; l < b->n; ++l) {
+    sw_case* c = b->cases[l];
+    launch_permute_f32(c->mesh->n_nodes, 3, c->q32, c->mesh->dev.node_u2i, y[l], s);
+  }
+  LAUNCHED();
+  HIPC(hipStreamSynchronize(s));
+  return SW_OK;
+}
+
+extern "C" int sw_batch_stats(const sw_batch* b, sw_case_stats* out) {
+  if (!b || !out) return fail(SW_EINVAL, "NULL argument");
+  for (int l = 0; l < b->n; ++l) {
+    int rc = sw_case_stats_get(b->cases[l], out + l);
+    if (rc) return rc;
+  }
   return SW_OK;
 }
 

@@ -137,7 +137,7 @@ void launch_tile_lanes_f64(const TileLane<double>* lanes, const int2* work, int 
 // (lane, tile) listed tile-major with a tile's lanes adjacent; tiles of at
 // most 1280 nodes.
 void launch_tile_lanes_pipe_f32(const TileLane<float>* lanes, const int2* items, int n_items, int max_tile_nodes,
-                                const LaneState* st, int iter, hipStream_t s);
+                                const LaneState* st, int iter, int grid_cap, hipStream_t s);
 
 // Lane kernels (sw_kernels.hip): one launch covers every lane, grid
 // (blocks per lane, lanes); st == nullptr means every lane.
@@ -166,8 +166,10 @@ void launch_lanes_cg(bool f32, bool dir, int n_lanes, int64_t max_nodes, const L
 // ctl (early exit when done, p.Ap accumulated into ctl); iter < 0: plain.
 void launch_tile_f64(const MeshDev& m, const uint8_t* emat, const MatDev* mats, const TileArgs<double>& a,
                      CgCtl* ctl, int iter, hipStream_t s);
+// grid_cap > 0 limits the workgroups of the persistent FP32 pass (a multiple
+// of 8); 0 keeps three per compute unit.
 void launch_tile_f32(const MeshDev& m, const uint8_t* emat, const MatDev* mats, const TileArgs<float>& a,
-                     CgCtl* ctl, int iter, hipStream_t s);
+                     CgCtl* ctl, int iter, int grid_cap, hipStream_t s);
 // FP32 element geometry for the FP32 operator (once per mesh).
 void launch_geom(const MeshDev& m, float* geo32, double* geo64, hipStream_t s);
 // Diagonal 3x3 blocks (6 values per node) of cM M + cK K + cC C_abs.

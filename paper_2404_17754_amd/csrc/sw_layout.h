@@ -41,7 +41,10 @@ struct HostLayout {
   std::vector<float> inv_valence;      // [n_nodes] 1 / elements containing the node (0 if none)
 };
 
+// Tiles close at max_nodes distinct nodes or max_elems elements (at most
+// TILE_MAX_NODES / TILE_MAX_ELEMS; smaller tiles are a tuning and test knob).
 void build_layout(int64_t n_nodes, int64_t n_tets, int64_t n_faces, const double* xyz, const int32_t* tet10,
-                  const int32_t* tri6, const int32_t* face_tet, const uint8_t* face_role, HostLayout& L);
+                  const int32_t* tri6, const int32_t* face_tet, const uint8_t* face_role, HostLayout& L,
+                  int max_nodes = TILE_MAX_NODES, int max_elems = TILE_MAX_ELEMS);
 
 }  // namespace sw

@@ -37,7 +37,8 @@ static inline uint64_t spread3(uint64_t v) {
 }
 
 void build_layout(int64_t n_nodes, int64_t n_tets, int64_t n_faces, const double* xyz, const int32_t* tet10,
-                  const int32_t* tri6, const int32_t* face_tet, const uint8_t* face_role, HostLayout& L) {
+                  const int32_t* tri6, const int32_t* face_tet, const uint8_t* face_role, HostLayout& L,
+                  int max_nodes, int max_elems) {
   L = HostLayout();
   L.n_nodes = n_nodes;
   L.n_tets = n_tets;
@@ -76,7 +77,7 @@ void build_layout(int64_t n_nodes, int64_t n_tets, int64_t n_faces, const double
       for (int j = 0; j < k && !dup; ++j) dup = tet10[10 * (int64_t)e + j] == n;
       add += dup ? 0 : 1;
     }
-    if (tile_elems > 0 && (tile_nodes + add > TILE_MAX_NODES || tile_elems + 1 > TILE_MAX_ELEMS)) {
+    if (tile_elems > 0 && (tile_nodes + add > max_nodes || tile_elems + 1 > max_elems)) {
       L.tile_elem_off.push_back((int32_t)i);
       ++tile;
       tile_nodes = 0;

@@ -596,8 +596,9 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(3, 3))) void
 }
 
 // Workgroups of the persistent pass: three per compute unit (the LDS and
-// register budget of the FP32 tile pass), a multiple of 8 (one run per XCD).
-static unsigned pipe_grid(int n_tiles) {
+// register budget of the FP32 tile pass), a multiple of 8 (one run per XCD),
+// at most `cap` when cap > 0 (fewer workgroups, each walking more tiles).
+static unsigned pipe_grid(int n_tiles, int cap) {
   static int n_cu = 0;
   if (n_cu == 0) {
     int dev = 0, v = 0;
@@ -607,7 +608,8 @@ static unsigned pipe_grid(int n_tiles) {
     else
       n_cu = 256;
   }
-  const int per_xcd = std::max(1, std::min((n_tiles + 7) / 8, 3 * n_cu / 8));
+  int per_xcd = std::max(1, std::min((n_tiles + 7) / 8, 3 * n_cu / 8));
+  if (cap > 0) per_xcd = std::max(1, std::min(per_xcd, cap / 8));
   return (unsigned)(8 * per_xcd);
 }
 
@@ -622,12 +624,12 @@ static_assert(PIPE_NT * PIPE_NPT >= TILE_MAX_NODES, "the pipelined pass must cov
 
 template <typename T>
 static void launch_tile(const MeshDev& m, const uint8_t* emat, const MatDev* mats, const TileArgs<T>& a, CgCtl* ctl,
-                        int iter, hipStream_t s) {
+                        int iter, hipStream_t s, int grid_cap = 0) {
   const size_t lds = tile_lds<T>(m.max_tile_nodes);
   if constexpr (sizeof(T) == 4) {
     if (iter >= 0 && a.x2 == nullptr && a.a1 == 1.0f && a.accumulate == 0 && a.vin == nullptr &&
         m.max_tile_nodes <= PIPE_NT * PIPE_NPT && a.n_mat >= 1 && a.n_mat <= PIPE_MATS) {
-      hipLaunchKernelGGL((k_tile_pipe<PIPE_NT, PIPE_NPT, SW_PIPE_PF>), dim3(pipe_grid(m.n_tiles)), dim3(PIPE_NT),
+      hipLaunchKernelGGL((k_tile_pipe<PIPE_NT, PIPE_NPT, SW_PIPE_PF>), dim3(pipe_grid(m.n_tiles, grid_cap)), dim3(PIPE_NT),
                          lds, s, m, emat, mats, a, ctl, iter);
       return;
     }
@@ -642,8 +644,8 @@ void launch_tile_f64(const MeshDev& m, const uint8_t* emat, const MatDev* mats, 
   launch_tile<double>(m, emat, mats, a, ctl, iter, s);
 }
 void launch_tile_f32(const MeshDev& m, const uint8_t* emat, const MatDev* mats, const TileArgs<float>& a,
-                     CgCtl* ctl, int iter, hipStream_t s) {
-  launch_tile<float>(m, emat, mats, a, ctl, iter, s);
+                     CgCtl* ctl, int iter, int grid_cap, hipStream_t s) {
+  launch_tile<float>(m, emat, mats, a, ctl, iter, s, grid_cap);
 }
 
 void launch_tile_lanes_f64(const TileLane<double>* lanes, const int2* work, int n_work, int max_tile_nodes,
@@ -652,8 +654,8 @@ void launch_tile_lanes_f64(const TileLane<double>* lanes, const int2* work, int 
                      work, st, iter);
 }
 void launch_tile_lanes_pipe_f32(const TileLane<float>* lanes, const int2* items, int n_items, int max_tile_nodes,
-                                const LaneState* st, int iter, hipStream_t s) {
-  hipLaunchKernelGGL((k_tile_lanes_pipe<PIPE_NT, PIPE_NPT>), dim3(pipe_grid(n_items)), dim3(PIPE_NT),
+                                const LaneState* st, int iter, int grid_cap, hipStream_t s) {
+  hipLaunchKernelGGL((k_tile_lanes_pipe<PIPE_NT, PIPE_NPT>), dim3(pipe_grid(n_items, grid_cap)), dim3(PIPE_NT),
                      tile_lds<float>(max_tile_nodes), s, lanes, items, n_items, max_tile_nodes, st, iter);
 }
 

@@ -41,6 +41,26 @@ def test_fit_matches_oracle_on_seeded_records(sw, ctx):
     assert abs(e - e_or) <= 1e-10
 
 
+def test_fit_events_matches_oracle_on_seeded_records(sw, ctx):
+    """Per-event fits and the worst event through sw_fit_events against the
+    oracle's fit of each event: one event in the model's span (ERR 0), two
+    not, one with a silent pair."""
+    rng = np.random.default_rng(6)
+    G = rng.standard_normal((3, 160, 4, 3))
+    ev = [(inv.design(G, 8, 12) @ rng.standard_normal(36)).reshape(160, 4, 3),
+          rng.standard_normal((160, 4, 3)), rng.standard_normal((160, 4, 3))]
+    ev[2][:, 1, 2] = 0.0
+    fits, emax, worst = sw.fit_events(ctx, [_dev(g) for g in G], [_dev(o) for o in ev], 8, 12)
+    fits_or, emax_or, worst_or = inv.fit_events(G, ev, 8, 12)
+    assert worst == worst_or and worst != 0
+    assert abs(emax - emax_or) <= 1e-10 and emax == max(f[1] for f in fits)
+    assert fits[0][1] <= 1e-12
+    for (c, e, used, rank), (c_or, _, e_or, used_or, rank_or) in zip(fits, fits_or):
+        assert used == used_or and rank == rank_or
+        assert np.abs(c - c_or).max() <= 1e-9 * np.abs(c_or).max()
+        assert abs(e - e_or) <= 1e-10
+
+
 def test_fit_recovers_coefficients_in_span(sw, ctx):
     rng = np.random.default_rng(2)
     G = rng.standard_normal((3, 120, 4, 3))
@@ -155,7 +175,7 @@ def test_events_reuse_green_records(sw, ctx):
     worst = []
     for cand in cands:
         green = [torch.from_numpy(l.waveforms()).cuda() for l in _green_runs(sw, ctx, gm, cand, n, stride)]
-        fits, w = sw.fit_events(ctx, green, events, stride, L)
+        fits, w, _ = sw.fit_events(ctx, green, events, stride, L)
         single = sw.fit_input(ctx, green, events[1], stride, L)
         assert abs(fits[1][1] - single[1]) <= 1e-14 and np.array_equal(fits[1][0], single[0])
         worst.append(w)

@@ -94,3 +94,19 @@ def test_march_is_superposition_of_delayed_green_records():
     c2, _, e, _, _ = inv.fit(np.array(G), direct, stride, 5)
     assert e <= 1e-8
     assert np.abs(c2 - c).max() <= 1e-6 * np.abs(c).max()
+
+
+def test_fit_events_takes_the_worst_event():
+    """The model's misfit over events is its worst event's (Section 3):
+    an event in the span of the model (ERR 0) never decides it, and each
+    event's fit is the single-event fit."""
+    rng = np.random.default_rng(12)
+    G = rng.standard_normal((3, 60, 3, 3))
+    in_span = (inv.design(G, 6, 10) @ rng.standard_normal(30)).reshape(60, 3, 3)
+    noisy = in_span + 0.3 * rng.standard_normal(in_span.shape)
+    other = rng.standard_normal((60, 3, 3))
+    fits, emax, worst = inv.fit_events(G, [in_span, noisy, other], 6, 10)
+    assert fits[0][2] < 1e-12
+    assert worst == 2 and emax == fits[2][2] > fits[1][2] > 0
+    single = inv.fit(G, noisy, 6, 10)
+    assert np.array_equal(fits[1][0], single[0]) and fits[1][2] == single[2]
