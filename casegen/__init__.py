@@ -186,6 +186,94 @@ def box_mesh(Lx, Ly, Lz, h, jitter=0.0, seed=12345, z_levels=None) -> Mesh:
                 box=(float(Lx), float(Ly), float(Lz)), cell=float(h), ncell=(nx, ny, nz))
 
 
+def refined_levels(Lz, z_int, h_fine, h_coarse, ratio=1.5):
+    """Vertex depths from -Lz to 0: spacing h_fine at depth z_int (below the
+    surface), growing by ``ratio`` per layer upwards and downwards up to
+    h_coarse: layers refined towards a layer interface."""
+    up, down = [], []
+    h, z = h_fine, -z_int
+    while z + h < -1e-9:
+        z += h
+        up.append(z)
+        h = min(h * ratio, h_coarse)
+    h, z = h_fine, -z_int
+    while z - h > -Lz + 1e-9:
+        z -= h
+        down.append(z)
+        h = min(h * ratio, h_coarse)
+    return np.array(sorted([-Lz] + down + [-z_int] + up + [0.0]))
+
+
+def delaunay_mesh(Lx, Ly, Lz, z_int, h_fine, h_coarse, ratio=1.5, jitter=0.3, seed=0) -> Mesh:
+    """Unstructured 10-node tetrahedral mesh of the box [0,Lx]x[0,Ly]x[-Lz,0],
+    refined towards depth z_int (e.g. a layer interface): seeded points on
+    layers of refined_levels, each layer a grid whose spacing is the local
+    layer thickness, every point moved by a seeded uniform offset of up to
+    ``jitter`` times the local spacing (points on a box face stay on it),
+    tetrahedralised by scipy.spatial.Delaunay; edge nodes at the edge
+    midpoints.  Element sizes vary about fourfold and no lattice is left
+    in the connectivity.  ncell is (0, 0, 0) (no cell grid)."""
+    from scipy.spatial import Delaunay
+    rng = np.random.default_rng([seed, 5])
+    zl = refined_levels(Lz, z_int, h_fine, h_coarse, ratio)
+    dz = np.diff(zl)
+    pts = []
+    for k, z in enumerate(zl):
+        hz = min(dz[max(k - 1, 0)], dz[min(k, len(dz) - 1)])
+        nx, ny = max(1, int(round(Lx / hz))), max(1, int(round(Ly / hz)))
+        X, Y = np.meshgrid(np.linspace(0.0, Lx, nx + 1), np.linspace(0.0, Ly, ny + 1), indexing="ij")
+        P = np.stack([X.ravel(), Y.ravel(), np.full(X.size, z)], 1)
+        off = rng.uniform(-jitter, jitter, P.shape) * np.array([Lx / nx, Ly / ny, hz])
+        off[(np.abs(P[:, 0]) < 1e-9) | (np.abs(P[:, 0] - Lx) < 1e-9), 0] = 0.0
+        off[(np.abs(P[:, 1]) < 1e-9) | (np.abs(P[:, 1] - Ly) < 1e-9), 1] = 0.0
+        if k == 0 or k == len(zl) - 1:
+            off[:, 2] = 0.0
+        pts.append(P + off)
+    pts = np.concatenate(pts)
+    T = Delaunay(pts).simplices.astype(np.int64)
+    X = pts[T]
+    vol = np.einsum("ij,ij->i", X[:, 1] - X[:, 0], np.cross(X[:, 2] - X[:, 0], X[:, 3] - X[:, 0]))
+    T = T[vol != 0.0]
+    neg = np.einsum("ij,ij->i", *(lambda X: (X[:, 1] - X[:, 0], np.cross(X[:, 2] - X[:, 0], X[:, 3] - X[:, 0])))(pts[T])) < 0
+    T[neg, 1], T[neg, 2] = T[neg, 2].copy(), T[neg, 1].copy()
+    nv = len(pts)
+    # edge nodes
+    E = np.stack([np.sort(T[:, [a, b]], 1) for a, b in TET_EDGES], 1)         # (n, 6, 2)
+    key = E[..., 0] * nv + E[..., 1]
+    ukey, inv = np.unique(key.ravel(), return_inverse=True)
+    ea, eb = ukey // nv, ukey % nv
+    xyz = np.concatenate([pts, 0.5 * (pts[ea] + pts[eb])])
+    tet10 = np.concatenate([T, nv + inv.reshape(-1, 6)], 1).astype(np.int32)
+    # boundary faces: faces of one tet only, all on the sides or the base
+    tri, own, role = [], [], []
+    tol = 1e-9 * max(Lx, Ly, Lz)
+    allf = np.concatenate([np.sort(tet10[:, list(v)], 1) for v, _ in _TET_FACES])
+    fkey = (allf[:, 0].astype(np.int64) * nv + allf[:, 1]) * nv + allf[:, 2]
+    uk, cnt = np.unique(fkey, return_counts=True)
+    single = set(uk[cnt == 1].tolist())
+    n = tet10.shape[0]
+    for fi, (verts, edges) in enumerate(_TET_FACES):
+        fv = tet10[:, list(verts)]
+        k3 = np.sort(fv, 1).astype(np.int64)
+        kk = (k3[:, 0] * nv + k3[:, 1]) * nv + k3[:, 2]
+        on_b = np.fromiter((int(v) in single for v in kk), bool, n)
+        P = xyz[fv]
+        for m, r in ((np.all(np.abs(P[..., 0]) < tol, 1), 1), (np.all(np.abs(P[..., 0] - Lx) < tol, 1), 1),
+                     (np.all(np.abs(P[..., 1]) < tol, 1), 1), (np.all(np.abs(P[..., 1] - Ly) < tol, 1), 1),
+                     (np.all(np.abs(P[..., 2] + Lz) < tol, 1), 2)):
+            sel = np.nonzero(m & on_b)[0]
+            if sel.size:
+                tri.append(np.concatenate([fv[sel], tet10[sel][:, list(edges)]], 1))
+                own.append(sel)
+                role.append(np.full(sel.size, r, np.uint8))
+    tri6 = np.concatenate(tri).astype(np.int32)
+    face_tet = np.concatenate(own).astype(np.int32)
+    face_role = np.concatenate(role)
+    o = np.lexsort((face_tet, face_role))
+    return Mesh(xyz=xyz, tet10=tet10, tri6=tri6[o], face_tet=face_tet[o], face_role=face_role[o],
+                box=(float(Lx), float(Ly), float(Lz)), cell=float(h_coarse), ncell=(0, 0, 0))
+
+
 # faces of a tet: (vertex triple, the tet-local edge slots of edges 01,12,20)
 _TET_FACES = (
     ((0, 1, 2), (4, 5, 6)),
@@ -254,11 +342,13 @@ def _rff_eval(k, ph, x, y, chunk=1 << 18):
 
 def interface_depth(mesh: Mesh, seed, h0, amp, corr):
     """Returns a callable depth(x, y) = h0 + g(x, y), where g is scaled so
-    that its largest magnitude over the centres of the surface cell grid is
-    ``amp``."""
+    that its largest magnitude over the centres of the surface cell grid (on
+    a mesh without one, a grid of the mesh's coarse spacing) is ``amp``."""
     k, ph = interface_field(seed, amp, corr)
     nx, ny, _ = mesh.ncell
     Lx, Ly, _ = mesh.box
+    if nx == 0:  # no cell grid: columns of the mesh's coarse spacing
+        nx, ny = max(1, int(round(Lx / mesh.cell))), max(1, int(round(Ly / mesh.cell)))
     xc = (np.arange(nx) + 0.5) * (Lx / nx)
     yc = (np.arange(ny) + 0.5) * (Ly / ny)
     X, Y = np.meshgrid(xc, yc, indexing="ij")
@@ -346,12 +436,17 @@ def rayleigh_coefficients(xi, f1, f2):
 # ----------------------------------------------------------- receivers
 
 def surface_receivers(mesh: Mesh, n):
-    """n x n grid of surface nodes at ((i+1/2) Lx/n, (j+1/2) Ly/n, 0)."""
+    """n x n grid of surface nodes at ((i+1/2) Lx/n, (j+1/2) Ly/n, 0); on a
+    mesh without a cell grid, the surface nodes nearest to those points."""
     Lx, Ly, _ = mesh.box
     xs = (np.arange(n) + 0.5) * (Lx / n)
     ys = (np.arange(n) + 0.5) * (Ly / n)
     X, Y = np.meshgrid(xs, ys, indexing="ij")
     target = np.stack([X.ravel(), Y.ravel(), np.zeros(X.size)], 1)
+    if mesh.ncell == (0, 0, 0):
+        top = np.nonzero(np.abs(mesh.xyz[:, 2]) < 1e-9)[0]
+        d = ((mesh.xyz[top][None, :, :2] - target[:, None, :2]) ** 2).sum(-1)
+        return top[np.argmin(d, 1)].astype(np.int32)
     nx, ny, nz = mesh.ncell
     NX, NY = 2 * nx + 1, 2 * ny + 1
     hh = mesh.cell / 2

@@ -172,6 +172,26 @@ def test_graded_mesh_march(sw, ctx):
     assert gc.stats()["max_true_rel_res"] <= 1e-8 and gc.stats()["flags"] == 0
 
 
+def test_unstructured_mesh_march(sw, ctx):
+    """An unstructured Delaunay mesh refined towards a 15 m deep layer
+    interface (element sizes 2.5-10 m), the benchmark's solver (mixed
+    precision, projected guess), as a single case and as a batch lane,
+    against the oracle's exact solves."""
+    mesh = cg.delaunay_mesh(40.0, 30.0, 30.0, 15.0, 2.5, 10.0, seed=8)
+    cfg = cg.CONFIGS["small"]
+    case = cg.make_case(mesh, cfg, n_steps=30, n_rec=3)
+    ref = march.run_case(mesh, case, solver="lu").rec_v
+    gm = sw.Mesh(ctx, mesh)
+    alone = sw.Case(ctx, gm, case, precision="mixed", guess="proj")
+    alone.step(case.n_steps)
+    lanes = [sw.Case(ctx, gm, case, precision="mixed", guess="proj") for _ in range(2)]
+    sw.Batch(ctx, lanes).step(case.n_steps)
+    for gc in [alone] + lanes:
+        err = np.linalg.norm(gc.waveforms() - ref) / np.linalg.norm(ref)
+        st = gc.stats()
+        assert err < TOL_WAVE and st["max_true_rel_res"] <= 1e-8 and not st["flags"] & 3, (err, st)
+
+
 def test_long_march_as_benchmarked(sw, ctx):
     """400 steps of the small model (4 s: the wave crosses the box, reflects
     at the free surface and leaves through the dashpots) in the benchmark's

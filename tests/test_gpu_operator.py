@@ -1,9 +1,10 @@
 """GPU parity of the matrix-free operator, the right-hand side, the
 block-Jacobi diagonal and the misfit against the CPU oracle (through the
 C-ABI).  Meshes: the small two-layer box (3000 tets: 11 full workgroups of
-256 tets plus a ragged tail), a jittered unstructured mesh (no lattice left
-in the geometry) and a jittered mesh graded towards the surface (element
-sizes varying fourfold)."""
+256 tets plus a ragged tail), a jittered mesh (no lattice left in the
+geometry), a jittered mesh graded towards the surface (element sizes varying
+fourfold) and an unstructured Delaunay mesh refined towards a layer
+interface (no lattice in the connectivity either)."""
 import numpy as np
 import pytest
 
@@ -29,7 +30,9 @@ def _meshes():
            "jitter": cg.box_mesh(80.0, 60.0, 40.0, 10.0, jitter=0.22, seed=3),
            # layers from 2.5 m at the surface to ~11 m at the base, jittered
            "graded": cg.box_mesh(80.0, 60.0, 40.0, 10.0, jitter=0.15, seed=4,
-                                 z_levels=cg.graded_levels(40.0, 2.5, 1.5))}
+                                 z_levels=cg.graded_levels(40.0, 2.5, 1.5)),
+           # unstructured Delaunay tetrahedra refined towards a 20 m deep interface
+           "delaunay": cg.delaunay_mesh(80.0, 60.0, 40.0, 20.0, 2.5, 10.0, seed=6)}
     return out
 
 

@@ -88,6 +88,7 @@ MESHES = {
     "graded": lambda: cg.box_mesh(60.0, 40.0, 40.0, 10.0, jitter=0.15, seed=5,
                                   z_levels=cg.graded_levels(40.0, 2.5, 1.5)),
     "shuffled": lambda: _shuffled(cg.box_mesh(60.0, 50.0, 40.0, 5.0)),
+    "delaunay": lambda: cg.delaunay_mesh(80.0, 60.0, 50.0, 25.0, 2.5, 10.0, seed=2),
     "batch200": lambda: cg.config_mesh(cg.CONFIGS["batch200"]),
 }
 

@@ -29,9 +29,22 @@ def _graded_mesh():
     return cg.box_mesh(40.0, 30.0, 30.0, 10.0, jitter=0.15, seed=9, z_levels=cg.graded_levels(30.0, 2.5, 1.6))
 
 
-@pytest.mark.parametrize("which", ["small", "jitter", "graded"])
+def _delaunay_mesh():
+    # unstructured: Delaunay tetrahedra refined towards a 15 m deep interface
+    return cg.delaunay_mesh(40.0, 30.0, 30.0, 15.0, 2.5, 10.0, seed=4)
+
+
+def _mesh(which, small_mesh, jitter_mesh):
+    if which == "small":
+        return small_mesh
+    if which == "jitter":
+        return jitter_mesh
+    return _graded_mesh() if which == "graded" else _delaunay_mesh()
+
+
+@pytest.mark.parametrize("which", ["small", "jitter", "graded", "delaunay"])
 def test_global_stiffness_rigid_modes(which, small_mesh, small_case, jitter_mesh):
-    mesh = {"small": small_mesh, "jitter": jitter_mesh}.get(which) or _graded_mesh()
+    mesh = _mesh(which, small_mesh, jitter_mesh)
     tet_mat = small_case.tet_mat if which == "small" else (np.arange(mesh.n_tets) % 2).astype(np.uint8)
     K, M = assemble.stiffness_and_mass(mesh, cg.material_table(), tet_mat)
     kn = abs(K).sum(1).max()
@@ -46,11 +59,11 @@ def test_global_stiffness_rigid_modes(which, small_mesh, small_case, jitter_mesh
     assert abs(t @ M @ t - np.sum(V * mat[tet_mat, 2])) < 1e-12 * np.sum(V * mat[tet_mat, 2])
 
 
-@pytest.mark.parametrize("which", ["jitter", "graded"])
+@pytest.mark.parametrize("which", ["jitter", "graded", "delaunay"])
 def test_patch_test_linear_field(which, jitter_mesh):
     # one material: a linear displacement then has uniform stress, so the
     # interior nodal forces vanish and the interior solution is exact
-    mesh = jitter_mesh if which == "jitter" else _graded_mesh()
+    mesh = _mesh(which, None, jitter_mesh)
     tet_mat = np.zeros(mesh.n_tets, np.uint8)
     K, _ = assemble.stiffness_and_mass(mesh, cg.material_table(), tet_mat)
     rng = np.random.default_rng(11)
@@ -201,3 +214,26 @@ def test_mesh_counts_match_config_sizes():
     m = cg.config_mesh(cg.CONFIGS["small"])
     assert (m.n_nodes, m.n_tets, m.n_faces) == (4851, 3000, 600)
     assert np.bincount(m.face_role).tolist() == [0, 400, 200]
+
+
+def test_delaunay_mesh_is_a_conforming_partition():
+    """The unstructured generator's output: positive volumes summing to the
+    box, edge nodes at midpoints, every interior face shared by exactly two
+    elements and every other face on the sides, base (with faces listed) or
+    top; element sizes vary several fold."""
+    m = _delaunay_mesh()
+    Lx, Ly, Lz = m.box
+    X = m.xyz[m.tet10[:, :4]]
+    V = np.einsum("ij,ij->i", X[:, 1] - X[:, 0], np.cross(X[:, 2] - X[:, 0], X[:, 3] - X[:, 0])) / 6
+    assert V.min() > 0 and abs(V.sum() - Lx * Ly * Lz) < 1e-9 * Lx * Ly * Lz
+    for k, (a, b) in enumerate(cg.TET_EDGES):
+        assert np.abs(m.xyz[m.tet10[:, 4 + k]] - 0.5 * (X[:, a] + X[:, b])).max() < 1e-12
+    faces = np.sort(np.concatenate([m.tet10[:, list(v)] for v in ((0, 1, 2), (0, 1, 3), (1, 2, 3), (0, 2, 3))]), 1)
+    u, cnt = np.unique(faces, axis=0, return_counts=True)
+    assert cnt.max() == 2
+    P = m.xyz[u[cnt == 1]]
+    top = np.all(np.abs(P[..., 2]) < 1e-9, 1)
+    assert (cnt == 1).sum() - top.sum() == m.n_faces
+    assert set(np.unique(m.face_role)) == {1, 2}
+    h = np.cbrt(6 * V)
+    assert h.max() / h.min() > 4
