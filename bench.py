@@ -64,10 +64,12 @@ def algorithmic_bytes(mesh, word):
     """Bytes one application of the element-by-element operator must move
     in the reference layout: 10 int32 node ids + 1 material byte per tet,
     the input vector read once and the output written once per node, and
-    the coordinates of every vertex node read once."""
+    the three coordinates of every vertex node read once, all values in the
+    pass's word size (FP32: about 76 bytes per tet, 726 MB on the large
+    case)."""
     nx, ny, nz = mesh.ncell
     n_vert = (nx + 1) * (ny + 1) * (nz + 1)
-    return mesh.n_tets * (40 + 1) + mesh.n_nodes * 2 * 3 * word + n_vert * 3 * 8
+    return mesh.n_tets * (40 + 1) + mesh.n_nodes * 2 * 3 * word + n_vert * 3 * word
 
 
 def read_traffic(kind):
@@ -84,33 +86,55 @@ def read_traffic(kind):
     return float(m_bytes.group(1))
 
 
-def cpu_baseline(cfg_name, dof_target, steps=4):
-    """The CPU oracle (FP64, assembled sparse matrices, conjugate gradients
-    with a Jacobi preconditioner to the same 1e-8 relative residual) timed on
-    a bounded sample of the workload: a 100 x 100 x 50 m box with the same
-    5 m cells, material law, time step and input, marched `steps` steps.
-    The rate is scaled to the workload by the DOF ratio."""
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(cfg_name, dof_target, steps=20, step0=80):
+    """The CPU oracle as it stands (oracle/bsr.py: FP64 symmetric 3x3
+    block-sparse matrices assembled in C++, block-Jacobi CG with OpenMP on
+    every host core, each step to the same 1e-8 true relative residual,
+    zero initial guess) timed on a bounded sample of the workload: a
+    100 x 100 m column of the large case's full depth with the same cells,
+    material law, time step and input, over a window of `steps` steps from
+    step `step0` (the input near its peak) with every element in motion
+    (seeded smooth initial velocity field).  The rate is scaled to the
+    workload by the DOF ratio (the per-iteration work of CG is proportional
+    to the DOF; iteration counts depend on the cells and time step, which
+    are the workload's)."""
     import numpy as np
     import casegen as cg
-    from oracle import march
+    from oracle import bsr
     base = cg.CONFIGS[cfg_name]
-    cfg = cg.BoxConfig("sample", (100.0, 100.0, 50.0), base.cell, min(base.h0, 25.0), base.amp, base.corr,
-                       base.freqs, base.t0, base.dt, steps, 4, base.seed)
+    Lz = base.box[2]
+    cfg = cg.BoxConfig("sample", (100.0, 100.0, Lz), base.cell, base.h0, base.amp, base.corr,
+                       base.freqs, base.t0, base.dt, step0 + steps, 4, base.seed)
     mesh = cg.config_mesh(cfg)
-    case = cg.make_case(mesh, cfg, n_steps=steps)
-    sys_ = march.build_system(mesh, case)
-    from threadpoolctl import threadpool_limits
-    with threadpool_limits(limits=1):
-        t0 = time.perf_counter()
-        r = march.run(sys_, case.dt, case.v_in, steps, case.rec_node, solver="cg", rtol=1e-8)
-        dt_wall = time.perf_counter() - t0
+    case = cg.make_case(mesh, cfg)
+    v0 = cg.smooth_field(mesh, 71, corr=40.0, amp=1e-3)
+    t0 = time.perf_counter()
+    S = bsr.System(mesh, case.mat, case.tet_mat)
+    t_asm = time.perf_counter() - t0
+    out = S.march(case.dt, case.ray_alpha, case.ray_beta, case.v_in[step0:], steps, case.rec_node, v0=v0,
+                  rtol=1e-8, guess="zero")
+    dt_wall = float(out["secs"].sum())
     dof = 3 * mesh.n_nodes
     rate = steps / dt_wall * dof / dof_target
-    return {"value": rate, "unit": "case-timesteps/s", "cores": 1, "kind": "oracle",
-            "sample": (f"oracle FP64 sparse CG (Jacobi, rtol 1e-8) on a 100x100x50 m box of the same 5 m cells "
-                       f"({mesh.n_tets} tets, {dof} DOF), {steps} steps in {dt_wall:.1f} s "
-                       f"(mean {np.mean(r.iters):.0f} CG iterations/step), scaled by DOF ratio {dof}/{dof_target}; "
-                       f"one thread (BLAS limited to 1), host has {os.cpu_count()} logical CPUs")}
+    return {"value": rate, "unit": "case-timesteps/s", "cores": S.threads, "kind": "oracle",
+            "scaled": "by DOF ratio (extrapolated from the sample)",
+            "host": {"logical_cpus": os.cpu_count(), "cpu_model": cpu_model(),
+                     "OMP_NUM_THREADS": os.environ.get("OMP_NUM_THREADS"), "omp_threads_used": S.threads},
+            "sample": (f"native oracle (C++/OpenMP, FP64 3x3 block-sparse, block-Jacobi CG, rtol 1e-8, zero guess) "
+                       f"on a 100x100x{Lz:.0f} m column of the same {base.cell:g} m cells ({mesh.n_tets} tets, "
+                       f"{dof} DOF), steps {step0}-{step0 + steps} from a seeded smooth velocity field: "
+                       f"{steps} steps in {dt_wall:.1f} s (mean {np.mean(out['iters']):.0f} CG iterations/step; "
+                       f"assembly {t_asm:.1f} s, not timed), scaled by DOF ratio {dof}/{dof_target}")}
 
 
 def train_network(sw, cg, ctx, cfg, n_cases, n_steps, train_steps, per_step=8192, box=(200.0, 200.0, 100.0)):
@@ -315,6 +339,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3, help="untimed steps on a separate copy of the case")
     ap.add_argument("--config", default="large")
     ap.add_argument("--guess", default="proj", choices=["zero", "poly", "mlp", "proj"])
+    ap.add_argument("--precision", default="mixed", choices=["mixed", "flex"],
+                    help="outer solver around the FP32 inner CG: iterative refinement or flexible CG")
     ap.add_argument("--proj-dim", type=int, default=6, help="past increments spanned by the projection guess")
     ap.add_argument("--inner-rtol", type=float, default=0.0,
                     help="floor of the inner FP32 CG tolerance (0 = the library default)")
@@ -372,8 +398,8 @@ def main():
 
     # warm-up on a separate copy of the case
     if args.warmup > 0:
-        w = sw.Case(ctx, gmesh, case, rtol=1e-8, precision="mixed", guess=args.guess, proj_dim=args.proj_dim,
-                    inner_rtol=args.inner_rtol)
+        w = sw.Case(ctx, gmesh, case, rtol=1e-8, precision=args.precision, guess=args.guess,
+                    proj_dim=args.proj_dim, inner_rtol=args.inner_rtol)
         if args.guess == "mlp":
             w.attach_mlp(net)
         w.step(args.warmup)
@@ -381,7 +407,7 @@ def main():
         del w
         torch.cuda.empty_cache()
 
-    gc = sw.Case(ctx, gmesh, case, rtol=1e-8, precision="mixed", guess=args.guess, proj_dim=args.proj_dim,
+    gc = sw.Case(ctx, gmesh, case, rtol=1e-8, precision=args.precision, guess=args.guess, proj_dim=args.proj_dim,
                  inner_rtol=args.inner_rtol)
     if args.guess == "mlp":
         gc.attach_mlp(net)
@@ -427,16 +453,18 @@ def main():
     traffic = read_traffic(dom)
     tflops = aflops / avg_s / 1e12
     gbs = abytes / avg_s / 1e9
-    roofline = {"bound": "alu", "achieved": round(tflops, 2), "peak": ALU_PEAK_TFLOPS, "unit": "TFLOP/s",
-                "frac": round(tflops / ALU_PEAK_TFLOPS, 4), "traffic": traffic,
+    roofline = {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": traffic,
                 "kernel": dom, "avg_launch_us": round(avg_s * 1e6, 1), "launches": n_full,
                 "launches_incl_early_exit": n_launch, "timed_one_launch_in": PROFILE_EVERY,
-                "algorithmic_flops_per_launch": aflops, "flops_per_tet": FLOPS_PER_TET,
-                "intensity_flop_per_byte": round(aflops / abytes, 2),
-                "ridge_flop_per_byte": round(ALU_PEAK_TFLOPS * 1e3 / HBM_PEAK_GBS, 2),
-                "hbm": {"achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                        "frac": round(gbs / HBM_PEAK_GBS, 4), "algorithmic_bytes_per_launch": abytes,
-                        "counter_traffic_GBs": None if traffic is None else round(traffic / avg_s / 1e9, 1)}}
+                "algorithmic_bytes_per_launch": abytes,
+                "bytes_per_tet": round(abytes / mesh.n_tets, 2),
+                "counter_traffic_GBs": None if traffic is None else round(traffic / avg_s / 1e9, 1),
+                "alu": {"achieved": round(tflops, 2), "peak": ALU_PEAK_TFLOPS, "unit": "TFLOP/s",
+                        "frac": round(tflops / ALU_PEAK_TFLOPS, 4), "algorithmic_flops_per_launch": aflops,
+                        "flops_per_tet": FLOPS_PER_TET, "intensity_flop_per_byte": round(aflops / abytes, 2),
+                        "ridge_flop_per_byte": round(ALU_PEAK_TFLOPS * 1e3 / HBM_PEAK_GBS, 2),
+                        "peak_note": "FP32 vector FMA without packed instructions (the build disables them)"}}
 
     # comparisons on the common window of steps from rest
     compare = None
@@ -444,8 +472,11 @@ def main():
         compare = {"window_steps": cmp_n,
                    args.guess: {"ms_per_step": round(ms_window, 2), "value": round(1000.0 / ms_window, 3),
                                 "cg_iters_per_step": float(np.mean(it[:cmp_n]))}}
-        legs = [(g, dict(precision="mixed", guess=g, proj_dim=args.proj_dim, net=net if g == "mlp" else None))
+        legs = [(g, dict(precision=args.precision, guess=g, proj_dim=args.proj_dim, net=net if g == "mlp" else None))
                 for g in ("poly", "mlp", "proj") if g != args.guess and (g != "mlp" or net is not None)]
+        other = "flex" if args.precision == "mixed" else "mixed"
+        legs.append((f"{other}_{args.guess}", dict(precision=other, guess=args.guess, proj_dim=args.proj_dim,
+                                                    net=net if args.guess == "mlp" else None)))
         legs.append(("plain_fp64", dict(precision="fp64", guess="zero")))
         for name, kw in legs:
             ms, pit, prel, pst = timed_window(sw, ctx, gmesh, case, cmp_n, **kw)
@@ -482,7 +513,9 @@ def main():
         "config": {"workload": (f"{args.config}: {cfg.box[0]:.0f}x{cfg.box[1]:.0f}x{cfg.box[2]:.0f} m, "
                                 f"{cfg.cell:g} m cells, {mesh.n_tets} P2 tets, {dof} DOF, dt {cfg.dt} s, "
                                 f"Ricker {cfg.freqs} Hz, one case, steps 0-{args.steps} from rest"),
-                   "precision": "FP32 inner CG in FP64 refinement", "guess": args.guess, "rtol": 1e-8,
+                   "precision": ("FP32 inner CG in FP64 refinement" if args.precision == "mixed"
+                                 else "FP32 inner CG preconditioning FP64 flexible CG"),
+                   "guess": args.guess, "rtol": 1e-8,
                    "parallelism": "single GPU"},
         "cg_iters_per_step": float(np.mean(it)), "refinement_rounds_per_step": round(stats["ir_outer"] / stats["steps"], 3),
         "max_true_rel_res": float(np.max(rel)),

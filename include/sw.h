@@ -81,8 +81,13 @@ enum { SW_FLAG_NOCONV = 1, SW_FLAG_NONFINITE = 2, SW_FLAG_GUESS_FALLBACK = 4 };
 /* precision of the per-step solve */
 enum {
   SW_FP64 = 0,        /* FP64 preconditioned CG on the FP64 operator */
-  SW_MIXED_FP32 = 1   /* FP32 inner CG (FP32 operator, FP32 vectors) inside FP64
+  SW_MIXED_FP32 = 1,  /* FP32 inner CG (FP32 operator, FP32 vectors) inside FP64
                          iterative refinement; FP64 true residual and update */
+  SW_MIXED_FP32_FLEX = 2  /* the same FP32 inner CG as the variable preconditioner of
+                             an FP64 flexible CG (one previous direction kept; the
+                             CG with variable preconditioning of Section 3); FP64
+                             true residual confirms convergence.  Single cases only
+                             (batches march SW_MIXED_FP32 lanes) */
 };
 
 /* initial guess of each step's solve */
@@ -180,10 +185,10 @@ typedef struct {
   double ray_beta;       /* Rayleigh stiffness coefficient (s), >= 0 */
   double rtol;           /* relative residual target, in (0, 1) */
   int32_t max_iter;      /* CG iteration cap per step (inner + outer) */
-  int32_t precision;     /* SW_FP64 or SW_MIXED_FP32 */
+  int32_t precision;     /* SW_FP64, SW_MIXED_FP32 or SW_MIXED_FP32_FLEX */
   int32_t guess;         /* SW_GUESS_* */
   int32_t poly_order;    /* 0..3, used by SW_GUESS_POLY / SW_GUESS_MLP */
-  double inner_rtol;     /* SW_MIXED_FP32: inner CG relative tolerance (0 = default 1e-3) */
+  double inner_rtol;     /* mixed precisions: floor of the inner CG relative tolerance (0 = default 1e-3) */
   int32_t n_mat;         /* rows of mat, 1..255 */
   const double* mat;     /* host, n_mat x 3 rows (Vp, Vs, rho), Vp^2 > 2 Vs^2 */
   const uint8_t* tet_mat;/* host, n_tets material ids */

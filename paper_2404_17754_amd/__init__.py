@@ -23,7 +23,8 @@ import numpy as np
 from . import _lib as L
 from ._lib import SwError  # noqa: F401
 
-PRECISIONS = {"fp64": L.SW_FP64, "mixed": L.SW_MIXED_FP32, "mixed_fp32": L.SW_MIXED_FP32}
+PRECISIONS = {"fp64": L.SW_FP64, "mixed": L.SW_MIXED_FP32, "mixed_fp32": L.SW_MIXED_FP32,
+              "flex": L.SW_MIXED_FP32_FLEX}
 GUESSES = {"zero": L.SW_GUESS_ZERO, "poly": L.SW_GUESS_POLY, "mlp": L.SW_GUESS_MLP, "proj": L.SW_GUESS_PROJ}
 OPS = {"M": L.SW_OP_M, "K": L.SW_OP_K, "Cabs": L.SW_OP_CABS, "A": L.SW_OP_A}
 

@@ -167,6 +167,9 @@ struct sw_case {
   double *diag6, *pinv64, *pmax;
   __half* pinv16;  // block-Jacobi inverse / its largest diagonal entry, FP16 (FP32 CG)
   float *r32, *d32, *z32, *p32, *q32;
+  // flexible outer CG (SW_MIXED_FP32_FLEX): directions and their images of
+  // the current and the previous iteration (by parity), dot products
+  double *fp[2] = {nullptr, nullptr}, *fq[2] = {nullptr, nullptr}, *fdots = nullptr;
   double* wave;
   int32_t* log_it;
   double* log_rel;
@@ -569,7 +572,8 @@ extern "C" int sw_mesh_destroy(sw_mesh* m) {
 
 static size_t case_layout(const sw_mesh* m, const sw_case_desc* d, Carver& cv, sw_case* c) {
   const int64_t nn = m->n_nodes, nd = 3 * nn;
-  const bool mixed = d->precision == SW_MIXED_FP32;
+  const bool mixed = d->precision != SW_FP64;
+  const bool flex = d->precision == SW_MIXED_FP32_FLEX;
   auto mats = cv.take<MatDev>(d->n_mat);
   auto em = cv.take<uint8_t>(m->n_tets);
   auto rec = cv.take<int32_t>(std::max(d->n_rec, 1));
@@ -584,6 +588,12 @@ static size_t case_layout(const sw_mesh* m, const sw_case_desc* d, Carver& cv, s
   float* f32[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
   if (mixed)
     for (int i = 0; i < 5; ++i) f32[i] = cv.take<float>(nd);
+  double* fvec[4] = {nullptr, nullptr, nullptr, nullptr};
+  double* fdots = nullptr;
+  if (flex) {
+    for (int i = 0; i < 4; ++i) fvec[i] = cv.take<double>(nd);
+    fdots = cv.take<double>(8);
+  }
   auto wave = cv.take<double>(std::max<int64_t>(d->n_steps * 3 * d->n_rec, 1));
   auto log_it = cv.take<int32_t>(d->n_steps);
   auto log_rel = cv.take<double>(d->n_steps);
@@ -629,6 +639,11 @@ static size_t case_layout(const sw_mesh* m, const sw_case_desc* d, Carver& cv, s
     c->z32 = f32[2];
     c->p32 = f32[3];
     c->q32 = f32[4];
+    c->fp[0] = fvec[0];
+    c->fp[1] = fvec[1];
+    c->fq[0] = fvec[2];
+    c->fq[1] = fvec[3];
+    c->fdots = fdots;
     c->wave = wave;
     c->log_it = log_it;
     c->log_rel = log_rel;
@@ -654,7 +669,7 @@ static int validate_case(const sw_mesh* m, const sw_case_desc* d) {
   if (!(d->ray_alpha >= 0.0) || !(d->ray_beta >= 0.0)) return fail(SW_EINVAL, "Rayleigh coefficients must be >= 0");
   if (!(d->rtol > 0.0 && d->rtol < 1.0)) return fail(SW_EINVAL, "rtol must be in (0, 1)");
   if (d->max_iter <= 0) return fail(SW_EINVAL, "max_iter must be > 0");
-  if (d->precision != SW_FP64 && d->precision != SW_MIXED_FP32)
+  if (d->precision != SW_FP64 && d->precision != SW_MIXED_FP32 && d->precision != SW_MIXED_FP32_FLEX)
     return fail(SW_EINVAL, "unknown precision %d", d->precision);
   if (d->guess != SW_GUESS_ZERO && d->guess != SW_GUESS_POLY && d->guess != SW_GUESS_MLP &&
       d->guess != SW_GUESS_PROJ)
@@ -834,9 +849,14 @@ extern "C" int sw_case_create(sw_ctx* ctx, sw_mesh* m, const sw_case_desc* d, vo
   double* zero_vecs[] = {c->u, c->v, c->a, c->b, c->x, c->r, c->z, c->p, c->q};
   for (double* zv : zero_vecs) launch_fill_f64(nd, zv, 0.0, s);
   launch_fill_f64(4 * nd, c->hist, 0.0, s);
-  if (c->precision == SW_MIXED_FP32) {
+  if (c->precision != SW_FP64) {
     float* zf[] = {c->r32, c->d32, c->z32, c->p32, c->q32};
     for (float* zv : zf) launch_fill_f32(nd, zv, 0.0f, s);
+  }
+  if (c->precision == SW_MIXED_FP32_FLEX) {
+    double* zf[] = {c->fp[0], c->fp[1], c->fq[0], c->fq[1]};
+    for (double* zv : zf) launch_fill_f64(nd, zv, 0.0, s);
+    launch_fill_f64(8, c->fdots, 0.0, s);
   }
   launch_fill_f64(std::max<int64_t>(c->n_steps * 3 * c->n_rec, 1), c->wave, 0.0, s);
   launch_fill_f64((int64_t)(2 * sizeof(CgCtl) / 8), (double*)c->ctl64, 0.0, s);
@@ -1159,7 +1179,7 @@ int solve_step(sw_case* c, int* iters, int* outer, double* relres, int* flags) {
   // guess: the projection needs two past increments, the network four and
   // their neighbour means, extrapolation one; otherwise zero
   int g = guess_kind(c);
-  rc = set_guess(c, g, c->precision == SW_MIXED_FP32);
+  rc = set_guess(c, g, c->precision != SW_FP64);
   if (rc) return rc;
   CgCtl h;
   if (c->precision == SW_FP64) {
@@ -1215,14 +1235,33 @@ int solve_step(sw_case* c, int* iters, int* outer, double* relres, int* flags) {
       LAUNCHED();
     }
   } else {
+    // FP32 inner CG, either inside FP64 iterative refinement (each round
+    // adds the inner solution and takes the true residual), or as the
+    // variable preconditioner of an FP64 flexible CG (Section 3 names CG with
+    // variable preconditioning): each outer iteration applies A to the inner
+    // solution z, makes the direction A-orthogonal to the previous one
+    // (truncation to one) and updates x and r by the recurrence; the true
+    // residual confirms convergence and restarts the recurrence if it
+    // disagrees.
+    const bool flex = c->precision == SW_MIXED_FP32_FLEX;
+    const int64_t ni3 = 3 * c->mesh->dev.n_interior;
     int inner_est = std::max(1, c->last_iters / 2);
     bool first = true;
     // a projected guess comes with its residual from the stored images
     bool image_res = g == GUESS_PROJ;
+    bool recursive = false;  // residual from the flexible recurrence
+    int k = 0;               // flexible iterations since the last true residual
     for (;;) {
       const bool from_images = image_res;
+      const bool from_rec = recursive;
       image_res = false;
-      rc = from_images ? read_ctl(c, c->ctl64, &h) : true_residual(c, &h, true);
+      recursive = false;
+      if (from_images || from_rec) {
+        rc = read_ctl(c, c->ctl64, &h);
+      } else {
+        rc = true_residual(c, &h, true);
+        k = 0;
+      }
       if (rc) return rc;
       ++*outer;
       if (first && (g == GUESS_NET || g == GUESS_PROJ) && !(h.rr_true <= h.bb)) {
@@ -1240,7 +1279,7 @@ int solve_step(sw_case* c, int* iters, int* outer, double* relres, int* flags) {
         break;
       }
       if (h.rr_true <= c->rtol * c->rtol * h.bb) {
-        if (from_images) continue;  // confirm with an operator pass
+        if (from_images || from_rec) continue;  // confirm with an operator pass
         break;
       }
       if (*iters >= c->max_iter) {
@@ -1261,8 +1300,27 @@ int solve_step(sw_case* c, int* iters, int* outer, double* relres, int* flags) {
       if (rc) return rc;
       *iters += it;
       inner_est = std::max(1, it);
-      launch_ir_update(nd, c->x, c->d32, c->ctl64, s);
+      if (!flex) {
+        launch_ir_update(nd, c->x, c->d32, c->ctl64, s);
+        LAUNCHED();
+        continue;
+      }
+      const int par = k & 1;
+      const bool prev = k > 0;
+      launch_fill_f64(2, c->fdots, 0.0, s);
+      launch_fill_f64(1, c->fdots + 2 + par, 0.0, s);
+      launch_fcg_begin(nd, c->d32, c->ctl64, prev ? c->fq[par ^ 1] : nullptr, c->z, c->fdots, s);
+      // w = A z into q (its shared nodes are clear between passes)
+      rc = apply_f64(c, SW_OP_A, c->z, c->q, nullptr, -1);
+      if (rc) return rc;
+      launch_fcg_dir(nd, c->z, c->q, c->r, prev ? c->fp[par ^ 1] : nullptr, prev ? c->fq[par ^ 1] : nullptr,
+                     c->fp[par], c->fq[par], c->fdots, par, s);
+      launch_fill_f64(1, &c->ctl64->rr_true, 0.0, s);
+      launch_fcg_update(nd, c->x, c->r, c->fp[par], c->fq[par], c->fdots, par, c->ctl64, s);
+      launch_fill_f64(nd - ni3, c->q + ni3, 0.0, s);
       LAUNCHED();
+      ++k;
+      recursive = true;
     }
   }
   *relres = h.bb > 0.0 ? std::sqrt(h.rr_true / h.bb) : 0.0;

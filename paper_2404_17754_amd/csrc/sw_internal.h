@@ -211,6 +211,13 @@ void launch_ir_begin(int64_t n_nodes, const double* r64, const __half* P, float*
                      float* d32, CgCtl* ctl64, CgCtl* ctl32, hipStream_t s);
 // x64 += ctl->scale * d32
 void launch_ir_update(int64_t n, double* x64, const float* d32, const CgCtl* ctl, hipStream_t s);
+// flexible outer CG (see sw_kernels.hip)
+void launch_fcg_begin(int64_t n, const float* d32, const CgCtl* ctl64, const double* q_prev, double* z,
+                      double* dots, hipStream_t s);
+void launch_fcg_dir(int64_t n, const double* z, const double* w, const double* r, const double* p_prev,
+                    const double* q_prev, double* p, double* q, double* dots, int par, hipStream_t s);
+void launch_fcg_update(int64_t n, double* x, double* r, const double* p, const double* q, const double* dots,
+                       int par, CgCtl* ctl64, hipStream_t s);
 
 // x = sum_j coef[j] hist[(head - j) mod 4]; zero if ctl->bb == 0
 void launch_guess_poly(int64_t n, const double* hist, int head, int order, double* x, const CgCtl* ctl,

@@ -353,6 +353,95 @@ void launch_ir_update(int64_t n, double* x64, const float* d32, const CgCtl* ctl
   hipLaunchKernelGGL(k_ir_update, dim3(g), dim3(TPB), 0, s, n, x64, d32, ctl);
 }
 
+// ------------------------------------------------ flexible outer CG (FP64)
+//
+// One outer iteration of the flexible (variable-preconditioned) CG whose
+// preconditioner is the FP32 inner CG: z = scale d32 (the inner solution of
+// the scaled residual system), w = A z (FP64 operator pass), then
+//   p = z - beta p_prev,  q = w - beta q_prev,  beta = (z.q_prev)/(p_prev.q_prev)
+//   x += alpha p,  r -= alpha q,                alpha = (p.r)/(p.q)
+// (truncation to one previous direction).  Dot products go through dots[]
+// (cleared by the host before each kernel that adds into them): dots[0]
+// z.q_prev, dots[1] p.r, dots[2 + parity] p.q of the iteration of that
+// parity, and r.r into ctl->rr_true.
+
+__global__ __launch_bounds__(TPB) void k_fcg_begin(int64_t n, const float* __restrict__ d32, const CgCtl* ctl,
+                                                   const double* __restrict__ q_prev, double* __restrict__ z,
+                                                   double* dots) {
+  __shared__ double sh[2 * TPB / 64];
+  const double sc = ctl->scale;
+  double acc = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * TPB + threadIdx.x; i < n; i += (int64_t)gridDim.x * TPB) {
+    const double v = sc * (double)d32[i];
+    z[i] = v;
+    if (q_prev) acc += v * q_prev[i];
+  }
+  if (q_prev) {
+    acc = block_sum(acc, sh);
+    if (threadIdx.x == 0) atomic_add(&dots[0], acc);
+  }
+}
+void launch_fcg_begin(int64_t n, const float* d32, const CgCtl* ctl64, const double* q_prev, double* z,
+                      double* dots, hipStream_t s) {
+  unsigned g = nblocks(n);
+  if (g > 8192) g = 8192;
+  hipLaunchKernelGGL(k_fcg_begin, dim3(g), dim3(TPB), 0, s, n, d32, ctl64, q_prev, z, dots);
+}
+
+__global__ __launch_bounds__(TPB) void k_fcg_dir(int64_t n, const double* __restrict__ z,
+                                                 const double* __restrict__ w, const double* __restrict__ r,
+                                                 const double* __restrict__ p_prev, const double* __restrict__ q_prev,
+                                                 double* __restrict__ p, double* __restrict__ q, double* dots,
+                                                 int par) {
+  __shared__ double sh[2 * TPB / 64];
+  const double beta = p_prev ? dots[0] / dots[2 + (par ^ 1)] : 0.0;
+  double pr = 0.0, pq = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * TPB + threadIdx.x; i < n; i += (int64_t)gridDim.x * TPB) {
+    double pv = z[i], qv = w[i];
+    if (p_prev) {
+      pv -= beta * p_prev[i];
+      qv -= beta * q_prev[i];
+    }
+    p[i] = pv;
+    q[i] = qv;
+    pr += pv * r[i];
+    pq += pv * qv;
+  }
+  block_sum2(pr, pq, sh);
+  if (threadIdx.x == 0) {
+    atomic_add(&dots[1], pr);
+    atomic_add(&dots[2 + par], pq);
+  }
+}
+void launch_fcg_dir(int64_t n, const double* z, const double* w, const double* r, const double* p_prev,
+                    const double* q_prev, double* p, double* q, double* dots, int par, hipStream_t s) {
+  unsigned g = nblocks(n);
+  if (g > 8192) g = 8192;
+  hipLaunchKernelGGL(k_fcg_dir, dim3(g), dim3(TPB), 0, s, n, z, w, r, p_prev, q_prev, p, q, dots, par);
+}
+
+__global__ __launch_bounds__(TPB) void k_fcg_update(int64_t n, double* __restrict__ x, double* __restrict__ r,
+                                                    const double* __restrict__ p, const double* __restrict__ q,
+                                                    const double* dots, int par, CgCtl* ctl) {
+  __shared__ double sh[2 * TPB / 64];
+  const double alpha = dots[1] / dots[2 + par];
+  double rr = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * TPB + threadIdx.x; i < n; i += (int64_t)gridDim.x * TPB) {
+    x[i] += alpha * p[i];
+    const double rv = r[i] - alpha * q[i];
+    r[i] = rv;
+    rr += rv * rv;
+  }
+  rr = block_sum(rr, sh);
+  if (threadIdx.x == 0) atomic_add(&ctl->rr_true, rr);
+}
+void launch_fcg_update(int64_t n, double* x, double* r, const double* p, const double* q, const double* dots,
+                       int par, CgCtl* ctl64, hipStream_t s) {
+  unsigned g = nblocks(n);
+  if (g > 8192) g = 8192;
+  hipLaunchKernelGGL(k_fcg_update, dim3(g), dim3(TPB), 0, s, n, x, r, p, q, dots, par, ctl64);
+}
+
 // ------------------------------------------------------------- guesses
 
 // Lagrange extrapolation of order p from the last p+1 increments:
