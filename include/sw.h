@@ -118,6 +118,14 @@ SW_API const char* sw_version(void);
 SW_API int sw_ctx_create(int device, void* hip_stream, sw_ctx** out);
 SW_API int sw_ctx_destroy(sw_ctx* ctx);
 
+/* enable != 0 (the default): CG iterations after the first chunk of each
+ * solve are replayed from HIP graphs of two iterations (one per case and
+ * precision, one per batch), captured on first use on a stream of the
+ * library's own and launched on the context stream; 0: every kernel is
+ * launched directly.  The kernels and their results are the same either
+ * way; while the profiler is on, kernels are launched directly. */
+SW_API int sw_ctx_set_graphs(sw_ctx* ctx, int32_t enable);
+
 /* Workgroup count of the persistent FP32 operator passes (single case and
  * batch lanes) of objects on this context: 0 (default) = three per compute
  * unit, else at most max_workgroups (a positive multiple of 8, one run per

@@ -60,6 +60,11 @@ class Context:
         L.check(self.lib.sw_ctx_create(device, C.c_void_p(stream.cuda_stream), C.byref(h)))
         self.h = h
 
+    def set_graphs(self, enable):
+        """Replay CG iterations from captured HIP graphs (default) or launch
+        every kernel directly."""
+        L.check(self.lib.sw_ctx_set_graphs(self.h, 1 if enable else 0))
+
     def set_grid_cap(self, max_workgroups):
         """Cap the workgroups of the persistent FP32 passes (0: default)."""
         L.check(self.lib.sw_ctx_set_grid_cap(self.h, int(max_workgroups)))

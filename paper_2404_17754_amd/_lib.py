@@ -58,6 +58,7 @@ SIGNATURES = {
     "sw_ctx_create": (C.c_int, VP, PP),
     "sw_ctx_destroy": (VP,),
     "sw_ctx_set_grid_cap": (VP, I32),
+    "sw_ctx_set_graphs": (VP, I32),
     "sw_ctx_profile": (VP, I32),
     "sw_ctx_profile_kinds": (VP, C.c_uint32, I32),
     "sw_ctx_profile_read": (VP, I32, C.POINTER(F64), C.POINTER(I64), C.POINTER(F64), C.POINTER(I64)),

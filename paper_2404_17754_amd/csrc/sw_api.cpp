@@ -103,6 +103,10 @@ struct sw_ctx {
   hipStream_t stream;
   KernelProfiler prof;
   int grid_cap = 0;  // workgroup cap of the persistent FP32 passes (0: none)
+  // CG iterations after a solve's first chunk replay captured HIP graphs of
+  // two iterations; they are captured on a stream of the library's own
+  bool graphs = true;
+  hipStream_t cap_stream = nullptr;
 };
 
 namespace {
@@ -170,6 +174,10 @@ struct sw_case {
   // flexible outer CG (SW_MIXED_FP32_FLEX): directions and their images of
   // the current and the previous iteration (by parity), dot products
   double *fp[2] = {nullptr, nullptr}, *fq[2] = {nullptr, nullptr}, *fdots = nullptr;
+  // captured pair of CG iterations (FP64, FP32) and the grid cap it was
+  // captured with
+  hipGraphExec_t cg_graph[2] = {nullptr, nullptr};
+  int cg_graph_cap[2] = {-1, -1};
   double* wave;
   int32_t* log_it;
   double* log_rel;
@@ -218,6 +226,8 @@ struct sw_mlp {
 struct sw_batch {
   sw_ctx* ctx;
   std::vector<sw_case*> cases;
+  hipGraphExec_t cg_graph = nullptr;  // captured pair of FP32 CG iterations
+  int cg_graph_cap = -1;
   int n = 0;
   int64_t max_nodes = 0;
   int max_tile_nodes = 0;
@@ -255,9 +265,17 @@ extern "C" int sw_ctx_create(int device, void* hip_stream, sw_ctx** out) {
 }
 
 extern "C" int sw_ctx_destroy(sw_ctx* ctx) {
-  if (ctx)
+  if (ctx) {
     for (hipEvent_t e : ctx->prof.ev) (void)hipEventDestroy(e);
+    if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
+  }
   delete ctx;
+  return SW_OK;
+}
+
+extern "C" int sw_ctx_set_graphs(sw_ctx* ctx, int32_t enable) {
+  if (!ctx) return fail(SW_EINVAL, "NULL context");
+  ctx->graphs = enable != 0;
   return SW_OK;
 }
 
@@ -721,19 +739,22 @@ void op_scales(const sw_case* c, int op, double* sM, double* sK, double* sC) {
 
 // y = op x (internal order).  y's shared-node entries must be zero on entry
 // (interior entries are overwritten).
-int apply_f64(sw_case* c, int op, const double* x, double* y, CgCtl* ctl, int iter) {
+int apply_f64(sw_case* c, int op, const double* x, double* y, CgCtl* ctl, int iter, hipStream_t s) {
   TileArgs<double> A{};
   op_scales(c, op, &A.sM, &A.sK, &A.sC);
   A.x1 = x;
   A.a1 = 1.0;
   A.xf = x;
   A.y = y;
-  launch_tile_f64(c->mesh->dev, c->emat, c->mats, A, ctl, iter, c->ctx->stream);
+  launch_tile_f64(c->mesh->dev, c->emat, c->mats, A, ctl, iter, s);
   LAUNCHED();
   return SW_OK;
 }
+int apply_f64(sw_case* c, int op, const double* x, double* y, CgCtl* ctl, int iter) {
+  return apply_f64(c, op, x, y, ctl, iter, c->ctx->stream);
+}
 
-int apply_f32(sw_case* c, int op, const float* x, float* y, CgCtl* ctl, int iter) {
+int apply_f32(sw_case* c, int op, const float* x, float* y, CgCtl* ctl, int iter, hipStream_t s) {
   TileArgs<float> A{};
   double sM, sK, sC;
   op_scales(c, op, &sM, &sK, &sC);
@@ -745,9 +766,12 @@ int apply_f32(sw_case* c, int op, const float* x, float* y, CgCtl* ctl, int iter
   A.xf = x;
   A.y = y;
   A.n_mat = c->n_mat;
-  launch_tile_f32(c->mesh->dev, c->emat, c->mats, A, ctl, iter, c->ctx->grid_cap, c->ctx->stream);
+  launch_tile_f32(c->mesh->dev, c->emat, c->mats, A, ctl, iter, c->ctx->grid_cap, s);
   LAUNCHED();
   return SW_OK;
+}
+int apply_f32(sw_case* c, int op, const float* x, float* y, CgCtl* ctl, int iter) {
+  return apply_f32(c, op, x, y, ctl, iter, c->ctx->stream);
 }
 
 // Right-hand side of step c->step -> c->step + 1 (internal order) into y:
@@ -895,6 +919,9 @@ extern "C" int sw_case_create(sw_ctx* ctx, sw_mesh* m, const sw_case_desc* d, vo
 }
 
 extern "C" int sw_case_destroy(sw_case* c) {
+  if (c)
+    for (hipGraphExec_t g : c->cg_graph)
+      if (g) (void)hipGraphExecDestroy(g);
   delete c;
   return SW_OK;
 }
@@ -966,40 +993,108 @@ int read_ctl(sw_case* c, CgCtl* dev, CgCtl* host) {
 // Runs CG iterations of the solve in `ctl` until its done flag is set.  The
 // first chunk is sized from the previous solve's count; later ones are short
 // so that few launches are spent after convergence.
+// One CG iteration of the single-case solve on stream s: the operator pass
+// (iteration `iter` of the solve: parity and the first-iteration test), the
+// update and the direction kernels (iter_abs: the iteration's index in the
+// step, or -1 to take it from the control block).
+template <bool F32>
+int cg_iteration(sw_case* c, CgCtl* ctl, int iter, int iter_abs, hipStream_t s, bool prof) {
+  const int64_t nn = c->mesh->n_nodes;
+  sw_ctx* cx = c->ctx;
+  int rc;
+  if (F32) {
+    int ev = prof ? prof_begin(cx, SW_PROF_TILE_F32) : -1;
+    rc = apply_f32(c, SW_OP_A, c->p32, c->q32, ctl, iter, s);
+    if (prof) prof_end(cx, ev);
+    if (rc) return rc;
+    ev = prof ? prof_begin(cx, SW_PROF_UPDATE_F32) : -1;
+    launch_cg_update_f32(nn, c->mesh->dev.n_interior, iter & 1, c->pinv16, c->r32, c->z32, c->q32, ctl, s);
+    if (prof) prof_end(cx, ev);
+    ev = prof ? prof_begin(cx, SW_PROF_DIR_F32) : -1;
+    launch_cg_dir_f32(nn, iter & 1, iter_abs, c->max_iter, c->z32, c->p32, c->d32, ctl, s);
+    if (prof) prof_end(cx, ev);
+  } else {
+    int ev = prof ? prof_begin(cx, SW_PROF_TILE_F64) : -1;
+    rc = apply_f64(c, SW_OP_A, c->p, c->q, ctl, iter, s);
+    if (prof) prof_end(cx, ev);
+    if (rc) return rc;
+    ev = prof ? prof_begin(cx, SW_PROF_UPDATE_F64) : -1;
+    launch_cg_update_f64(nn, iter & 1, c->pinv64, c->r, c->z, c->q, ctl, s);
+    if (prof) prof_end(cx, ev);
+    ev = prof ? prof_begin(cx, SW_PROF_DIR_F64) : -1;
+    launch_cg_dir_f64(nn, iter & 1, iter_abs, c->max_iter, c->z, c->p, c->x, ctl, s);
+    if (prof) prof_end(cx, ev);
+  }
+  LAUNCHED();
+  return SW_OK;
+}
+
+// The capture stream of a context (created on first use; default priority).
+int capture_stream(sw_ctx* cx, hipStream_t* out) {
+  if (!cx->cap_stream) HIPC(hipStreamCreateWithFlags(&cx->cap_stream, hipStreamNonBlocking));
+  *out = cx->cap_stream;
+  return SW_OK;
+}
+
+// Instantiated graph of two CG iterations of this case's solve (an even
+// iteration then an odd one, past the first: the direction kernels take
+// the iteration index from the control block), captured once per case and
+// precision (again when the grid cap changes).  The captured kernels read
+// and write only the case's vectors and control block, so every replay
+// continues the solve in the control block.  *out stays null if capture is
+// not available (the caller then launches the kernels directly).
+template <bool F32>
+int cg_pair_graph(sw_case* c, CgCtl* ctl, hipGraphExec_t* out) {
+  const int slot = F32 ? 1 : 0;
+  if (c->cg_graph[slot] && c->cg_graph_cap[slot] == c->ctx->grid_cap) {
+    *out = c->cg_graph[slot];
+    return SW_OK;
+  }
+  if (c->cg_graph[slot]) {
+    HIPC(hipGraphExecDestroy(c->cg_graph[slot]));
+    c->cg_graph[slot] = nullptr;
+  }
+  hipStream_t cs;
+  int rc = capture_stream(c->ctx, &cs);
+  if (rc) return rc;
+  HIPC(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+  for (int k = 0; k < 2 && !rc; ++k) rc = cg_iteration<F32>(c, ctl, 2 + k, -1, cs, false);
+  hipGraph_t g = nullptr;
+  const hipError_t e = hipStreamEndCapture(cs, &g);
+  if (rc) return rc;
+  if (e != hipSuccess) return fail(SW_EHIP, "CG graph capture failed: %s", hipGetErrorString(e));
+  hipGraphExec_t ex = nullptr;
+  const hipError_t e2 = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  if (e2 != hipSuccess) return fail(SW_EHIP, "CG graph instantiation failed: %s", hipGetErrorString(e2));
+  c->cg_graph[slot] = ex;
+  c->cg_graph_cap[slot] = c->ctx->grid_cap;
+  *out = ex;
+  return SW_OK;
+}
+
 template <bool F32>
 int cg_loop(sw_case* c, CgCtl* ctl, int iter_base, int first_chunk, int* iters_out) {
   const int64_t nn = c->mesh->n_nodes;
   hipStream_t s = c->ctx->stream;
+  sw_ctx* cx = c->ctx;
   int it = 0;
-  int chunk = std::max(1, first_chunk);
+  // the first chunk has an even count, so that the chunks of two that follow
+  // start at even iterations (the parity a captured pair assumes)
+  int chunk = std::max(2, first_chunk + (first_chunk & 1));
   CgCtl h;
   for (;;) {
-    for (int k = 0; k < chunk; ++k) {
-      const int i = it + k;
-      int rc;
-      sw_ctx* cx = c->ctx;
-      if (F32) {
-        int ev = prof_begin(cx, SW_PROF_TILE_F32);
-        rc = apply_f32(c, SW_OP_A, c->p32, c->q32, ctl, i);
-        prof_end(cx, ev);
+    hipGraphExec_t g = nullptr;
+    if (it > 0 && chunk == 2 && cx->graphs && !cx->prof.on) {
+      int rc = cg_pair_graph<F32>(c, ctl, &g);
+      if (rc) return rc;
+    }
+    if (g) {
+      HIPC(hipGraphLaunch(g, s));
+    } else {
+      for (int k = 0; k < chunk; ++k) {
+        int rc = cg_iteration<F32>(c, ctl, it + k, iter_base + it + k, s, true);
         if (rc) return rc;
-        ev = prof_begin(cx, SW_PROF_UPDATE_F32);
-        launch_cg_update_f32(nn, c->mesh->dev.n_interior, i & 1, c->pinv16, c->r32, c->z32, c->q32, ctl, s);
-        prof_end(cx, ev);
-        ev = prof_begin(cx, SW_PROF_DIR_F32);
-        launch_cg_dir_f32(nn, i & 1, iter_base + i, c->max_iter, c->z32, c->p32, c->d32, ctl, s);
-        prof_end(cx, ev);
-      } else {
-        int ev = prof_begin(cx, SW_PROF_TILE_F64);
-        rc = apply_f64(c, SW_OP_A, c->p, c->q, ctl, i);
-        prof_end(cx, ev);
-        if (rc) return rc;
-        ev = prof_begin(cx, SW_PROF_UPDATE_F64);
-        launch_cg_update_f64(nn, i & 1, c->pinv64, c->r, c->z, c->q, ctl, s);
-        prof_end(cx, ev);
-        ev = prof_begin(cx, SW_PROF_DIR_F64);
-        launch_cg_dir_f64(nn, i & 1, iter_base + i, c->max_iter, c->z, c->p, c->x, ctl, s);
-        prof_end(cx, ev);
       }
     }
     LAUNCHED();
@@ -2008,6 +2103,51 @@ int batch_gather(sw_batch* b) {
   return b->ctx->prof.on ? prof_flush(b->ctx) : SW_OK;
 }
 
+// One FP32 CG iteration of every refining lane on stream s (dev_index: the
+// direction kernels take the iteration index from the lanes' control
+// blocks, as in a captured pair).
+void batch_cg_iteration(sw_batch* b, int i, bool dev_index, hipStream_t s, bool prof) {
+  sw_ctx* cx = b->ctx;
+  const int n = b->n;
+  int ev = prof ? prof_begin(cx, SW_PROF_TILE_F32) : -1;
+  launch_tile_lanes_pipe_f32(b->d_cg32, b->d_items, b->n_items, b->max_tile_nodes, b->d_st, i, cx->grid_cap, s);
+  if (prof) prof_end(cx, ev);
+  ev = prof ? prof_begin(cx, SW_PROF_UPDATE_F32) : -1;
+  launch_lanes_cg(true, false, n, b->max_nodes, b->d_lanes, b->d_st, i, s, dev_index);
+  if (prof) prof_end(cx, ev);
+  ev = prof ? prof_begin(cx, SW_PROF_DIR_F32) : -1;
+  launch_lanes_cg(true, true, n, b->max_nodes, b->d_lanes, b->d_st, i, s, dev_index);
+  if (prof) prof_end(cx, ev);
+}
+
+// The batch's captured pair of FP32 CG iterations (see cg_pair_graph).
+int batch_pair_graph(sw_batch* b, hipGraphExec_t* out) {
+  if (b->cg_graph && b->cg_graph_cap == b->ctx->grid_cap) {
+    *out = b->cg_graph;
+    return SW_OK;
+  }
+  if (b->cg_graph) {
+    HIPC(hipGraphExecDestroy(b->cg_graph));
+    b->cg_graph = nullptr;
+  }
+  hipStream_t cs;
+  int rc = capture_stream(b->ctx, &cs);
+  if (rc) return rc;
+  HIPC(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+  for (int k = 0; k < 2; ++k) batch_cg_iteration(b, 2 + k, true, cs, false);
+  hipGraph_t g = nullptr;
+  const hipError_t e = hipStreamEndCapture(cs, &g);
+  if (e != hipSuccess) return fail(SW_EHIP, "batch CG graph capture failed: %s", hipGetErrorString(e));
+  hipGraphExec_t ex = nullptr;
+  const hipError_t e2 = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  if (e2 != hipSuccess) return fail(SW_EHIP, "batch CG graph instantiation failed: %s", hipGetErrorString(e2));
+  b->cg_graph = ex;
+  b->cg_graph_cap = b->ctx->grid_cap;
+  *out = ex;
+  return SW_OK;
+}
+
 // One time step of every lane (mixed precision: FP32 inner CG inside FP64
 // refinement), the same arithmetic as solve_step + sw_case_step per case.
 int batch_step_once(sw_batch* b) {
@@ -2125,23 +2265,18 @@ int batch_step_once(sw_batch* b) {
     launch_lanes(LANE_CG_INIT32, n, b->max_nodes, b->d_lanes, b->d_st, nullptr, s);
     LAUNCHED();
     // inner CG of every refining lane in lockstep; converged lanes' work
-    // items return at once
-    int chunk = 1;
+    // items return at once.  The first chunk has an even count; the chunks
+    // of two after it replay the batch's captured pair of iterations.
+    int chunk = 2;
     for (int l = 0; l < n; ++l)
-      if (b->st[l].active) chunk = std::max(chunk, est[l]);
+      if (b->st[l].active) chunk = std::max(chunk, est[l] + (est[l] & 1));
     for (int it = 0;;) {
-      for (int k = 0; k < chunk; ++k) {
-        const int i = it + k;
-        int ev = prof_begin(cx, SW_PROF_TILE_F32);
-        launch_tile_lanes_pipe_f32(b->d_cg32, b->d_items, b->n_items, b->max_tile_nodes, b->d_st, i,
-                                   b->ctx->grid_cap, s);
-        prof_end(cx, ev);
-        ev = prof_begin(cx, SW_PROF_UPDATE_F32);
-        launch_lanes_cg(true, false, n, b->max_nodes, b->d_lanes, b->d_st, i, s);
-        prof_end(cx, ev);
-        ev = prof_begin(cx, SW_PROF_DIR_F32);
-        launch_lanes_cg(true, true, n, b->max_nodes, b->d_lanes, b->d_st, i, s);
-        prof_end(cx, ev);
+      hipGraphExec_t g = nullptr;
+      if (it > 0 && chunk == 2 && cx->graphs && !cx->prof.on && (rc = batch_pair_graph(b, &g))) return rc;
+      if (g) {
+        HIPC(hipGraphLaunch(g, s));
+      } else {
+        for (int k = 0; k < chunk; ++k) batch_cg_iteration(b, it + k, false, s, true);
       }
       LAUNCHED();
       it += chunk;
@@ -2399,6 +2534,7 @@ extern "C" int sw_batch_step(sw_batch* b, int32_t n_steps) {
 }
 
 extern "C" int sw_batch_destroy(sw_batch* b) {
+  if (b && b->cg_graph) (void)hipGraphExecDestroy(b->cg_graph);
   delete b;
   return SW_OK;
 }

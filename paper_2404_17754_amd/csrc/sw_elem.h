@@ -118,7 +118,7 @@ SW_HD void element_apply(const Geo<T>& G, T lam, T mu, T sK, T sMV, const T w[10
 #pragma unroll
       for (int m = 0; m < 6; ++m) sum[m] += S[k][m];
     }
-    const T c20 = sK * G.vol / (T)20;
+    const T c20 = sK * G.vol * (T)0.05;
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
 #pragma unroll
@@ -129,7 +129,7 @@ SW_HD void element_apply(const Geo<T>& G, T lam, T mu, T sK, T sMV, const T w[10
     }
   }
   // mass: per component the vertex sum, edge sum and each vertex's incident-edge sum
-  const T s = sMV / (T)420;
+  const T s = sMV * (T)(1.0 / 420.0);
   T Uv[3], Ue[3], inc[4][3];
 #pragma unroll
   for (int c = 0; c < 3; ++c) {

@@ -33,7 +33,9 @@ struct CgCtl {
   int32_t iters;   // iterations of the current solve
   int32_t live;    // 1 when the last update kernel ran its iteration (the
                    // direction kernel after it applies x += alpha p)
-  int32_t pad;
+  int32_t iter_cur;  // the running iteration's index in the step (written by the
+                     // update kernel, read by the direction kernel launched with
+                     // iter_abs < 0, as in a captured graph of iterations)
 };
 
 // Tiled mesh in device memory (internal element and node numbering; see
@@ -43,7 +45,7 @@ struct MeshDev {
   int64_t n_interior;            // nodes [0, n_interior) belong to one tile each
   int32_t n_tiles, max_tile_nodes;
   int64_t tet_stride, face_stride;
-  const uint16_t* conn_loc;      // [10][tet_stride]
+  const uint16_t* conn_loc;      // [10][tet_stride], 3 x tile-local node index
   const int32_t* tile_elem_off;  // [n_tiles + 1]
   const int32_t* tile_node_off;  // [n_tiles + 1]
   const int32_t* tile_nodes;
@@ -160,7 +162,7 @@ enum LaneOp {
 void launch_lanes(LaneOp op, int n_lanes, int64_t max_nodes, const LaneDev* lanes, const LaneState* st,
                   LaneInfo* info, hipStream_t s);
 void launch_lanes_cg(bool f32, bool dir, int n_lanes, int64_t max_nodes, const LaneDev* lanes, const LaneState* st,
-                     int iter, hipStream_t s);
+                     int iter, hipStream_t s, bool dev_index = false);
 
 // Launches (sw_kernels.hip).  iter >= 0: CG iteration `iter` of the solve in
 // ctl (early exit when done, p.Ap accumulated into ctl); iter < 0: plain.

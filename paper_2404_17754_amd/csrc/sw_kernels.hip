@@ -107,6 +107,7 @@ __device__ __forceinline__ void cg_update_body(int64_t n, int64_t n_int, int par
   if (lead) {
     ctl->alpha = (double)alpha;
     ctl->live = 1;
+    ctl->iter_cur = ctl->iters;
   }
   double rz = 0.0, rr = 0.0;
   for (int64_t i = (int64_t)blockIdx.x * TPB + threadIdx.x; i < n; i += (int64_t)gridDim.x * TPB) {
@@ -147,11 +148,17 @@ __device__ __forceinline__ void cg_update_body(int64_t n, int64_t n_int, int par
 
 // After a live update: x += alpha p with the update's alpha, the convergence
 // test, then (unless the solve stops here) p = z + beta p with
-// beta = rz[par^1] / rz[par].
+// beta = rz[par^1] / rz[par].  ctl->iters (the step's iterations so far) is
+// written by the first workgroup only; the update kernel before it keeps a
+// copy in ctl->iter_cur, so that no workgroup reads a value another one is
+// writing.
 template <typename T>
 __device__ __forceinline__ void cg_dir_body(int64_t n, int par, int iter_abs, int max_iter, const T* __restrict__ z,
                                             T* __restrict__ p, T* __restrict__ x, CgCtl* ctl) {
   if (!ctl->live) return;
+  // iter_abs < 0: the iteration index from the control block (graph replays
+  // launch the same arguments for every pair of iterations)
+  if (iter_abs < 0) iter_abs = ctl->iter_cur;
   const double rr = slot_sum<NSLOT>(ctl->rr[par ^ 1]);
   const bool stop = !(rr > ctl->tol2) || (iter_abs + 1 >= max_iter);  // NaN stops too
   const T alpha = (T)ctl->alpha;
@@ -722,21 +729,24 @@ __global__ __launch_bounds__(TPB) void k_lane_op(const LaneDev* __restrict__ lan
 
 // CG update (DIR false) or direction (DIR true) kernel of iteration `iter`
 // of every active lane's current solve (FP32 inner or FP64).
+// dev_index: the iteration's index in the step comes from each lane's
+// control block (graph replays), not from iter_base + iter.
 template <typename T, bool DIR>
 __global__ __launch_bounds__(TPB) void k_lane_cg(const LaneDev* __restrict__ lanes, const LaneState* __restrict__ st,
-                                                 int iter) {
+                                                 int iter, int dev_index) {
   const int l = blockIdx.y;
   if (!st[l].active) return;
   const LaneDev& L = lanes[l];
   const int par = iter & 1;
+  const int iabs = dev_index ? -1 : st[l].iter_base + iter;
   if constexpr (sizeof(T) == 4) {
     if constexpr (DIR)
-      cg_dir_body<float>(L.n_nodes, par, st[l].iter_base + iter, L.max_iter, L.z32, L.p32, L.d32, L.ctl32);
+      cg_dir_body<float>(L.n_nodes, par, iabs, L.max_iter, L.z32, L.p32, L.d32, L.ctl32);
     else
       cg_update_body<float, __half>(L.n_nodes, L.n_interior, par, L.pinv16, L.r32, L.z32, L.q32, L.ctl32);
   } else {
     if constexpr (DIR)
-      cg_dir_body<double>(L.n_nodes, par, st[l].iter_base + iter, L.max_iter, L.z, L.p, L.x, L.ctl64);
+      cg_dir_body<double>(L.n_nodes, par, iabs, L.max_iter, L.z, L.p, L.x, L.ctl64);
     else
       cg_update_body<double, double>(L.n_nodes, 0, par, L.pinv64, L.r, L.z, L.q, L.ctl64);
   }
@@ -781,19 +791,20 @@ void launch_lanes(LaneOp op, int n_lanes, int64_t max_nodes, const LaneDev* lane
 }
 
 void launch_lanes_cg(bool f32, bool dir, int n_lanes, int64_t max_nodes, const LaneDev* lanes, const LaneState* st,
-                     int iter, hipStream_t s) {
+                     int iter, hipStream_t s, bool dev_index) {
   const unsigned bn = lane_blocks(n_lanes, max_nodes, 2048);
   const dim3 g(bn, n_lanes);
+  const int dv = dev_index ? 1 : 0;
   if (f32) {
     if (dir)
-      hipLaunchKernelGGL((k_lane_cg<float, true>), g, dim3(TPB), 0, s, lanes, st, iter);
+      hipLaunchKernelGGL((k_lane_cg<float, true>), g, dim3(TPB), 0, s, lanes, st, iter, dv);
     else
-      hipLaunchKernelGGL((k_lane_cg<float, false>), g, dim3(TPB), 0, s, lanes, st, iter);
+      hipLaunchKernelGGL((k_lane_cg<float, false>), g, dim3(TPB), 0, s, lanes, st, iter, dv);
   } else {
     if (dir)
-      hipLaunchKernelGGL((k_lane_cg<double, true>), g, dim3(TPB), 0, s, lanes, st, iter);
+      hipLaunchKernelGGL((k_lane_cg<double, true>), g, dim3(TPB), 0, s, lanes, st, iter, dv);
     else
-      hipLaunchKernelGGL((k_lane_cg<double, false>), g, dim3(TPB), 0, s, lanes, st, iter);
+      hipLaunchKernelGGL((k_lane_cg<double, false>), g, dim3(TPB), 0, s, lanes, st, iter, dv);
   }
 }
 

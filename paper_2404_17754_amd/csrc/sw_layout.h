@@ -32,7 +32,8 @@ struct HostLayout {
   std::vector<int32_t> tile_int_base;  // first interior node id of each tile
   std::vector<int32_t> tile_nint;      // interior node count of each tile
   std::vector<int32_t> tile_face_off;  // [n_tiles + 1]
-  std::vector<uint16_t> conn_loc;      // [10][tet_stride] tile-local node index
+  std::vector<uint16_t> conn_loc;      // [10][tet_stride] 3 x tile-local node index (offset of the node's
+                                       // first value in 3-value-per-node tile arrays)
   std::vector<double> xyz;             // [n_nodes][3] internal order
   std::vector<int32_t> fconn;          // [6][face_stride] internal node ids
   std::vector<uint16_t> fconn_loc;     // [6][face_stride] tile-local node index

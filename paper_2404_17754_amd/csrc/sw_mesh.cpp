@@ -188,7 +188,8 @@ void build_layout(int64_t n_nodes, int64_t n_tets, int64_t n_faces, const double
     for (int32_t i = L.tile_elem_off[t]; i < L.tile_elem_off[t + 1]; ++i) {
       const int32_t e = L.elem_order[i];
       L.elem_u2i[e] = i;
-      for (int k = 0; k < 10; ++k) L.conn_loc[k * (size_t)L.tet_stride + i] = (uint16_t)loc[tet10[10 * (int64_t)e + k]];
+      for (int k = 0; k < 10; ++k)
+        L.conn_loc[k * (size_t)L.tet_stride + i] = (uint16_t)(3 * loc[tet10[10 * (int64_t)e + k]]);
     }
     // reset loc for this tile's nodes
     for (int32_t j = L.tile_node_off[t]; j < L.tile_node_off[t + 1]; ++j) loc[L.node_i2u[L.tile_nodes[j]]] = -1;

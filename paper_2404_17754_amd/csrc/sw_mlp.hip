@@ -391,7 +391,7 @@ __global__ __launch_bounds__(TPB) void k_elem_to_node(MeshDev m, const double* _
   __syncthreads();
   for (int e = m.tile_elem_off[t] + threadIdx.x; e < m.tile_elem_off[t + 1]; e += TPB) {
     int ln[10];
-    for (int a = 0; a < 10; ++a) ln[a] = m.conn_loc[a * m.tet_stride + e];
+    for (int a = 0; a < 10; ++a) ln[a] = m.conn_loc[a * m.tet_stride + e] / 3;
     float val[K];
     if constexpr (K == 3) {
       for (int c = 0; c < 3; ++c) {

@@ -31,9 +31,11 @@ __device__ __forceinline__ U ldc(const U* p, int64_t i) {
   return ((const __attribute__((address_space(4))) U*)p)[i];
 }
 
-// Per-element inputs fetched from global memory: tile-local connectivity,
-// material id, and the precomputed barycentric gradients and volume in the
-// pass's precision (coalesced streams, no dependent gather).
+// Per-element inputs fetched from global memory: tile-local connectivity
+// (stored as 3 x the local index: the offset of the node's first value in
+// the tile's 3-value-per-node LDS arrays, which saves the address
+// arithmetic), material id, and the precomputed barycentric gradients and
+// volume in the pass's precision (coalesced streams, no dependent gather).
 template <typename T>
 struct ElemIn {
   int ln[10];
@@ -126,14 +128,14 @@ __device__ __forceinline__ double tile_element_loop(const MeshDev& m, const uint
 #pragma unroll
     for (int k = 0; k < 10; ++k) {
 #pragma unroll
-      for (int c = 0; c < 3; ++c) w[k][c] = xs[3 * ln[k] + c];
+      for (int c = 0; c < 3; ++c) w[k][c] = xs[ln[k] + c];
     }
     // each node's force goes to the LDS accumulator as soon as it is
     // complete (no 30-value force array held in registers)
     T eloc = (T)0;
     element_apply<T, STIFF, MASS, DYN>(G, lam, mu, A.sK, A.sM * rho * G.vol, w,
                                   [&](int k, T f0, T f1, T f2) {
-                                    double* yk = &ys[3 * ln[k]];
+                                    double* yk = &ys[ln[k]];
                                     atomicAdd(yk, (double)f0);
                                     atomicAdd(yk + 1, (double)f1);
                                     atomicAdd(yk + 2, (double)f2);
@@ -674,7 +676,7 @@ __global__ __launch_bounds__(TPB) void k_geom(MeshDev m, float* __restrict__ geo
   for (int e = m.tile_elem_off[t] + threadIdx.x; e < m.tile_elem_off[t + 1]; e += TPB) {
     double X[4][3];
     for (int k = 0; k < 4; ++k) {
-      const int64_t g = gid[m.conn_loc[k * m.tet_stride + e]];
+      const int64_t g = gid[m.conn_loc[k * m.tet_stride + e] / 3];
       for (int d = 0; d < 3; ++d) X[k][d] = m.xyz[3 * g + d];
     }
     Geo<double> G;
@@ -712,7 +714,7 @@ __global__ __launch_bounds__(TPB) void k_tile_diag(MeshDev m, const uint8_t* __r
   const int e1 = m.tile_elem_off[t + 1];
   for (int e = m.tile_elem_off[t] + threadIdx.x; e < e1; e += TPB) {
     int ln[10];
-    for (int k = 0; k < 10; ++k) ln[k] = m.conn_loc[k * m.tet_stride + e];
+    for (int k = 0; k < 10; ++k) ln[k] = m.conn_loc[k * m.tet_stride + e] / 3;
     double X[4][3];
     for (int k = 0; k < 4; ++k)
       for (int d = 0; d < 3; ++d) X[k][d] = m.xyz[3 * (int64_t)gid[ln[k]] + d];

@@ -64,7 +64,11 @@ extern "C" int check_layout(int64_t nn, int64_t nt, int64_t nf, const double* xy
       const int ue = L.elem_order[e];
       if (L.elem_u2i[ue] != e) return 9;
       for (int k = 0; k < 10; ++k) {
-        const int l = L.conn_loc[k * L.tet_stride + e];
+        // stored as three times the tile-local index (the offset of the
+        // node's first value in the tile's 3-value-per-node arrays)
+        const int l3 = L.conn_loc[k * L.tet_stride + e];
+        if (l3 % 3) return 10;
+        const int l = l3 / 3;
         if (l >= ntn || L.tile_nodes[n0 + l] != L.node_u2i[tet10[10 * (int64_t)ue + k]]) return 10;
         used[l] = 1;
         const int g = L.tile_nodes[n0 + l];
