@@ -173,16 +173,20 @@ def train_network(sw, cg, ctx, cfg, n_cases, n_steps, train_steps, per_step=8192
     return net, info
 
 
-def batched_study(sw, cg, ctx, per_mesh, steps, proj_dim, legs=("seq", "batched", "plain")):
+def batched_study(sw, cg, ctx, per_mesh, steps, proj_dim, legs=("seq", "batched", "plain"), sample=None):
     """Candidate models on the three uneven meshes of the batched workload
     (200/300/400 x 100 m boxes, 5 m cells; seeded interface fields), marched
-    `steps` steps from rest with the projection guess: case by case ("seq"),
-    as one batch ("batched") and case by case with plain FP64 PCG and a zero
-    guess ("plain"), the legs asked for.  Returns the rates in
-    case-timesteps/s."""
+    `steps` steps from rest with the projection guess: as one batch of all
+    `per_mesh` models per mesh ("batched"), and case by case ("seq") and case
+    by case with plain FP64 PCG and a zero guess ("plain") on the first
+    `sample` models of each mesh (all of them if sample is None), the legs
+    asked for.  Every case of one mesh costs the same per step, and the
+    sample keeps the mix of meshes, so the rates in case-timesteps/s
+    compare."""
     import numpy as np
     import torch
-    meshes, cases = [], []
+    meshes, cases, in_sample = [], [], []
+    sample = per_mesh if sample is None else min(sample, per_mesh)
     for name in ("batch200", "batch300", "batch400"):
         cfg = cg.CONFIGS[name]
         m = cg.config_mesh(cfg)
@@ -190,9 +194,11 @@ def batched_study(sw, cg, ctx, per_mesh, steps, proj_dim, legs=("seq", "batched"
         meshes.append((name, m.n_tets))
         for k in range(per_mesh):
             cases.append((gm, cg.make_case(m, cfg, seed=cfg.seed + 3 * k + len(cases), n_steps=steps)))
+            in_sample.append(k < sample)
 
     def run(batched, precision="mixed", guess="proj"):
-        lanes = [sw.Case(ctx, gm, c, precision=precision, guess=guess, proj_dim=proj_dim) for gm, c in cases]
+        sel = cases if batched else [c for c, s in zip(cases, in_sample) if s]
+        lanes = [sw.Case(ctx, gm, c, precision=precision, guess=guess, proj_dim=proj_dim) for gm, c in sel]
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         if batched:
@@ -202,13 +208,14 @@ def batched_study(sw, cg, ctx, per_mesh, steps, proj_dim, legs=("seq", "batched"
                 lane.step(steps)
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
-        its = float(np.mean([lane.step_log()[0].mean() for lane in lanes]))
+        its = np.concatenate([lane.step_log()[0] for lane in lanes]).astype(np.float64)
         worst = float(max(lane.stats()["max_true_rel_res"] for lane in lanes))
         del lanes
         torch.cuda.empty_cache()
-        return len(cases) * steps / dt, its, worst
+        return len(sel) * steps / dt, float(its.mean()), worst
 
     out = {"meshes": [f"{n}: {t} tets" for n, t in meshes], "cases": len(cases), "steps": steps,
+           "sequential_and_plain_sample": f"{sample} models per mesh ({3 * sample})",
            "guess": f"proj (L={proj_dim})", "cg_iters_per_step": {}}
     worst = 0.0
     if "seq" in legs:
@@ -312,6 +319,39 @@ def fit_study(sw, cg, ctx, n_steps, stride, proj_dim):
             "fit_ms": round(1e3 * (t3 - t2), 2), "err_vs_other_model": round(e, 4), "pairs": used, "rank": rank}
 
 
+def solver_study(sw, ctx, gmesh, case, steps, guess, proj_dim, windows=(20, 100, 400)):
+    """The two outer solvers around the FP32 inner CG on the workload from
+    rest: iterative refinement ("mixed") and the flexible CG ("flex"), each
+    marched `steps` steps with per-step HIP-event timing; ms per step, CG
+    iterations and FP64 operator passes per step over the windows of steps
+    0-w."""
+    import numpy as np
+    import torch
+    out = {"steps": steps, "guess": guess}
+    for prec in ("mixed", "flex"):
+        c = sw.Case(ctx, gmesh, case, rtol=1e-8, precision=prec, guess=guess, proj_dim=proj_dim)
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
+        torch.cuda.synchronize()
+        ev[0].record()
+        outer = []
+        for k in range(steps):
+            c.step(1)
+            ev[k + 1].record()
+            outer.append(c.stats()["ir_outer"])
+        torch.cuda.synchronize()
+        ms = np.array([ev[k].elapsed_time(ev[k + 1]) for k in range(steps)])
+        it, rel = c.step_log(0, steps)
+        outer = np.diff(np.concatenate([[0], outer]))
+        out[prec] = {f"0-{w}": {"ms_per_step": round(float(ms[:w].mean()), 3),
+                                "cg_iters_per_step": round(float(it[:w].mean()), 2),
+                                "fp64_passes_per_step": round(float(outer[:w].mean()), 3)}
+                     for w in windows if w <= steps}
+        out[prec]["max_true_rel_res"] = float(rel.max())
+        del c
+        torch.cuda.empty_cache()
+    return out
+
+
 def timed_window(sw, ctx, gmesh, case, n, **kw):
     """A fresh case marched `n` steps from rest; ms per step and the step
     log."""
@@ -347,14 +387,18 @@ def main():
     ap.add_argument("--compare-steps", type=int, default=100,
                     help="window (from rest) on which the other guesses and plain FP64 PCG are timed (0 = skip)")
     ap.add_argument("--no-mlp-compare", action="store_true", help="leave the trained-network leg out")
-    ap.add_argument("--batched", type=int, default=8,
+    ap.add_argument("--batched", type=int, default=86,
                     help="cases per mesh of the batched study on the 200/300/400 m meshes (0: none)")
-    ap.add_argument("--batched-steps", type=int, default=30)
+    ap.add_argument("--batched-steps", type=int, default=100)
+    ap.add_argument("--batched-sample", type=int, default=8,
+                    help="cases per mesh marched case by case (sequential and plain FP64 legs)")
     ap.add_argument("--batched-legs", default="seq,batched,plain",
                     help="legs of the batched study: seq, batched, plain (comma separated)")
-    ap.add_argument("--guess-study", type=int, default=0,
+    ap.add_argument("--guess-study", type=int, default=64,
                     help="held-out models of the 300 m mesh for the learned-guess study (0: none)")
     ap.add_argument("--guess-study-steps", type=int, default=100)
+    ap.add_argument("--solver-study", type=int, default=0,
+                    help="steps (from rest) of the outer-solver study: refinement vs flexible CG (0 = skip)")
     ap.add_argument("--fit-study", type=int, default=0,
                     help="steps of an extra input-estimation study (Green's runs + fit) on the 300 m mesh (0 = skip)")
     ap.add_argument("--train-cases", type=int, default=4)
@@ -486,12 +530,17 @@ def main():
         compare["speedup_vs_plain_fp64"] = round(compare["plain_fp64"]["ms_per_step"] / ms_window, 3)
         compare["plain_fp64"]["method"] = "FP64 block-Jacobi PCG, zero initial guess"
 
+    solvers = None
+    if args.solver_study > 0:
+        case_s = cg.make_case(mesh, cfg, n_steps=args.solver_study + 1)
+        solvers = solver_study(sw, ctx, gmesh, case_s, args.solver_study, args.guess, args.proj_dim)
+
     batched = None
     if args.batched > 0:
         del gmesh
         torch.cuda.empty_cache()
         batched = batched_study(sw, cg, ctx, args.batched, args.batched_steps, args.proj_dim,
-                                tuple(args.batched_legs.split(",")))
+                                tuple(args.batched_legs.split(",")), sample=args.batched_sample)
 
     gstudy = None
     if args.guess_study > 0:
@@ -525,7 +574,8 @@ def main():
         "kernels_ms": {k: {"total_ms": round(v[0], 3), "launches": v[1], "full_launch_us": round(1e3 * v[2], 1),
                            "timed_one_launch_in": PROFILE_EVERY}
                        for k, v in kernels.items() if v[1]},
-        "roofline": roofline, "compare": compare, "batched": batched, "learned_guess_study": gstudy,
+        "roofline": roofline, "compare": compare, "outer_solvers": solvers, "batched": batched,
+        "learned_guess_study": gstudy,
         "input_estimation": fit, "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
