@@ -292,7 +292,9 @@ SW_API int sw_case_misfit(sw_case* c, const double* obs_dev, double* err, int32_
  *   nb_k  = element-neighbour mean of du^{m-1-k}  (mean over the elements
  *           containing n of the element's mean of component c)
  *   s     = max_k(|d_k|, |nb_k|)
- *   x     = (d_0..d_3, nb_0..nb_3) / s, Vs/500, rho/2000  (node means)
+ *   D(a)  = (a_0, a_0 - a_1, a_0 - 2 a_1 + a_2, a_0 - 3 a_1 + 3 a_2 - a_3)
+ *   x     = D(d) / s, D(nb) / s, Vs/500, rho/2000  (node means; the
+ *           differences formed in FP64)
  *   y     = w3 . ReLU(W2 ReLU(W1 x + b1) + b2) + b3
  *   guess = 3 d_0 - 3 d_1 + d_2 + s y                 (0 when s = 0)
  * Parameters (SW_MLP_NPARAM floats, FP32, host order): W1[64][10], b1[64],
@@ -416,6 +418,21 @@ SW_API int sw_batch_workspace_bytes(sw_case* const* cases, int32_t n, size_t* by
 SW_API int sw_batch_create(sw_ctx* ctx, sw_case* const* cases, int32_t n, void* dev_ws, size_t ws_bytes,
                     sw_batch** out);
 SW_API int sw_batch_step(sw_batch* b, int32_t n_steps);
+/* Set-up-time tuning of the schedule of the batch's FP32 lane pass (the
+ * launch every inner CG iteration of sw_batch_step makes): times `reps`
+ * (1..1000) passes of each candidate on the lanes' inner-solve vectors
+ * (free between steps; left zero) and keeps the fastest for later steps.
+ * Candidates k = 2 * order + grid: order 0 = one mesh after the other,
+ * 1 = the meshes interleaved tile by tile (each with the lanes of a tile
+ * adjacent); grid 0 = three workgroups per compute unit, 1 = two.  Writes
+ * the chosen k and (optional) the mean pass time of each candidate (ms, 4
+ * values).  Results do not depend on the schedule beyond rounding.
+ * Synchronous. */
+SW_API int sw_batch_autotune(sw_batch* b, int32_t reps, int32_t* choice, double* ms);
+/* The same for a single case's persistent FP32 pass (mixed precisions):
+ * candidates k = 0, 1, 2 are three, two and one workgroups per compute
+ * unit; ms: 3 values (optional).  Synchronous. */
+SW_API int sw_case_autotune(sw_case* c, int32_t reps, int32_t* choice, double* ms);
 /* Statistics of every lane (out: n entries, lane order; as
  * sw_case_stats_get of each case). */
 SW_API int sw_batch_stats(const sw_batch* b, sw_case_stats* out);

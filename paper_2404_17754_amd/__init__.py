@@ -236,6 +236,14 @@ class Case:
         L.check(self.ctx.lib.sw_case_apply_f32(self.h, mask, C.c_void_p(x.data_ptr()), C.c_void_p(y.data_ptr())))
         return y
 
+    def autotune(self, reps=5):
+        """Pick the fastest workgroup count of the FP32 pass
+        (sw_case_autotune); returns (choice, mean ms of the 3 candidates)."""
+        ch = C.c_int32()
+        ms = np.zeros(3)
+        L.check(self.ctx.lib.sw_case_autotune(self.h, int(reps), C.byref(ch), _ptr(ms)))
+        return ch.value, ms
+
     def rhs(self):
         torch = _torch()
         y = torch.empty(self.n_dof, dtype=torch.float64, device=self.ctx.device)
@@ -448,6 +456,14 @@ class Batch:
 
     def step(self, n=1):
         L.check(self.ctx.lib.sw_batch_step(self.h, int(n)))
+
+    def autotune(self, reps=5):
+        """Pick the fastest lane-pass schedule (sw_batch_autotune); returns
+        (choice, mean ms of each of the 4 candidates)."""
+        ch = C.c_int32()
+        ms = np.zeros(4)
+        L.check(self.ctx.lib.sw_batch_autotune(self.h, int(reps), C.byref(ch), _ptr(ms)))
+        return ch.value, ms
 
     def stats(self):
         """Statistics of every lane (sw_batch_stats), in lane order."""

@@ -105,6 +105,8 @@ SIGNATURES = {
     "sw_batch_create": (VP, C.POINTER(VP), I32, VP, SZ, PP),
     "sw_batch_step": (VP, I32),
     "sw_batch_stats": (VP, C.POINTER(CaseStats)),
+    "sw_batch_autotune": (VP, I32, C.POINTER(I32), VP),
+    "sw_case_autotune": (VP, I32, C.POINTER(I32), VP),
     "sw_batch_apply_f32": (VP, C.POINTER(VP), C.POINTER(VP)),
     "sw_batch_destroy": (VP,),
 }

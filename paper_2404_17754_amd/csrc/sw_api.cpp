@@ -178,6 +178,9 @@ struct sw_case {
   // captured with
   hipGraphExec_t cg_graph[2] = {nullptr, nullptr};
   int cg_graph_cap[2] = {-1, -1};
+  // workgroup cap of this case's persistent FP32 pass chosen by
+  // sw_case_autotune (-1: the context's)
+  int grid_cap = -1;
   double* wave;
   int32_t* log_it;
   double* log_rel;
@@ -212,6 +215,8 @@ struct sw_case {
   sw_case_stats stats{};
 };
 
+inline int case_grid_cap(const sw_case* c) { return c->grid_cap >= 0 ? c->grid_cap : c->ctx->grid_cap; }
+
 struct sw_mlp {
   sw_ctx* ctx;
   float *theta, *m, *v;  // FP32 master weights, Adam moments
@@ -228,6 +233,8 @@ struct sw_batch {
   std::vector<sw_case*> cases;
   hipGraphExec_t cg_graph = nullptr;  // captured pair of FP32 CG iterations
   int cg_graph_cap = -1;
+  int grid_cap = -1;                  // chosen by sw_batch_autotune (-1: the context's)
+  int schedule = 0;                   // work-item order (see batch_items)
   int n = 0;
   int64_t max_nodes = 0;
   int max_tile_nodes = 0;
@@ -249,6 +256,8 @@ struct sw_batch {
   std::vector<LaneInfo> info;
   std::vector<TileLane<double>> rhs1;
 };
+
+inline int batch_grid_cap(const sw_batch* b) { return b->grid_cap >= 0 ? b->grid_cap : b->ctx->grid_cap; }
 
 static int static_scratch_init(int device);
 
@@ -766,7 +775,7 @@ int apply_f32(sw_case* c, int op, const float* x, float* y, CgCtl* ctl, int iter
   A.xf = x;
   A.y = y;
   A.n_mat = c->n_mat;
-  launch_tile_f32(c->mesh->dev, c->emat, c->mats, A, ctl, iter, c->ctx->grid_cap, s);
+  launch_tile_f32(c->mesh->dev, c->emat, c->mats, A, ctl, iter, case_grid_cap(c), s);
   LAUNCHED();
   return SW_OK;
 }
@@ -1046,7 +1055,7 @@ int capture_stream(sw_ctx* cx, hipStream_t* out) {
 template <bool F32>
 int cg_pair_graph(sw_case* c, CgCtl* ctl, hipGraphExec_t* out) {
   const int slot = F32 ? 1 : 0;
-  if (c->cg_graph[slot] && c->cg_graph_cap[slot] == c->ctx->grid_cap) {
+  if (c->cg_graph[slot] && c->cg_graph_cap[slot] == case_grid_cap(c)) {
     *out = c->cg_graph[slot];
     return SW_OK;
   }
@@ -1068,7 +1077,7 @@ int cg_pair_graph(sw_case* c, CgCtl* ctl, hipGraphExec_t* out) {
   (void)hipGraphDestroy(g);
   if (e2 != hipSuccess) return fail(SW_EHIP, "CG graph instantiation failed: %s", hipGetErrorString(e2));
   c->cg_graph[slot] = ex;
-  c->cg_graph_cap[slot] = c->ctx->grid_cap;
+  c->cg_graph_cap[slot] = case_grid_cap(c);
   *out = ex;
   return SW_OK;
 }
@@ -2039,17 +2048,29 @@ std::vector<int2> batch_work(sw_case* const* cases, int n) {
   return work;
 }
 
-// Items of the persistent FP32 pass: for each mesh, tile by tile, the lanes
-// of that mesh adjacent (they share the tile's mesh data).
-std::vector<int2> batch_items(sw_case* const* cases, int n) {
+// Items of the persistent FP32 pass, tile by tile with the lanes of one
+// mesh adjacent (they share the tile's mesh data).  schedule 0: one mesh
+// after the other; 1: the meshes interleaved tile by tile (tile t of every
+// mesh, then tile t + 1), which spreads each mesh over all XCDs.
+std::vector<int2> batch_items(sw_case* const* cases, int n, int schedule = 0) {
   std::vector<int2> items;
   std::vector<const sw_mesh*> meshes;
   for (int l = 0; l < n; ++l)
     if (std::find(meshes.begin(), meshes.end(), cases[l]->mesh) == meshes.end()) meshes.push_back(cases[l]->mesh);
-  for (const sw_mesh* m : meshes)
-    for (int t = 0; t < m->dev.n_tiles; ++t)
-      for (int l = 0; l < n; ++l)
-        if (cases[l]->mesh == m) items.push_back(make_int2(l, t));
+  if (schedule == 0) {
+    for (const sw_mesh* m : meshes)
+      for (int t = 0; t < m->dev.n_tiles; ++t)
+        for (int l = 0; l < n; ++l)
+          if (cases[l]->mesh == m) items.push_back(make_int2(l, t));
+  } else {
+    int tmax = 0;
+    for (const sw_mesh* m : meshes) tmax = std::max(tmax, (int)m->dev.n_tiles);
+    for (int t = 0; t < tmax; ++t)
+      for (const sw_mesh* m : meshes)
+        if (t < m->dev.n_tiles)
+          for (int l = 0; l < n; ++l)
+            if (cases[l]->mesh == m) items.push_back(make_int2(l, t));
+  }
   return items;
 }
 
@@ -2110,7 +2131,7 @@ void batch_cg_iteration(sw_batch* b, int i, bool dev_index, hipStream_t s, bool 
   sw_ctx* cx = b->ctx;
   const int n = b->n;
   int ev = prof ? prof_begin(cx, SW_PROF_TILE_F32) : -1;
-  launch_tile_lanes_pipe_f32(b->d_cg32, b->d_items, b->n_items, b->max_tile_nodes, b->d_st, i, cx->grid_cap, s);
+  launch_tile_lanes_pipe_f32(b->d_cg32, b->d_items, b->n_items, b->max_tile_nodes, b->d_st, i, batch_grid_cap(b), s);
   if (prof) prof_end(cx, ev);
   ev = prof ? prof_begin(cx, SW_PROF_UPDATE_F32) : -1;
   launch_lanes_cg(true, false, n, b->max_nodes, b->d_lanes, b->d_st, i, s, dev_index);
@@ -2122,7 +2143,7 @@ void batch_cg_iteration(sw_batch* b, int i, bool dev_index, hipStream_t s, bool 
 
 // The batch's captured pair of FP32 CG iterations (see cg_pair_graph).
 int batch_pair_graph(sw_batch* b, hipGraphExec_t* out) {
-  if (b->cg_graph && b->cg_graph_cap == b->ctx->grid_cap) {
+  if (b->cg_graph && b->cg_graph_cap == batch_grid_cap(b)) {
     *out = b->cg_graph;
     return SW_OK;
   }
@@ -2143,7 +2164,7 @@ int batch_pair_graph(sw_batch* b, hipGraphExec_t* out) {
   (void)hipGraphDestroy(g);
   if (e2 != hipSuccess) return fail(SW_EHIP, "batch CG graph instantiation failed: %s", hipGetErrorString(e2));
   b->cg_graph = ex;
-  b->cg_graph_cap = b->ctx->grid_cap;
+  b->cg_graph_cap = batch_grid_cap(b);
   *out = ex;
   return SW_OK;
 }
@@ -2498,7 +2519,7 @@ extern "C" int sw_batch_apply_f32(sw_batch* b, const float* const* x, float* con
   LAUNCHED();
   int rc = batch_upload(b, b->d_st, b->st.data(), b->n * sizeof(LaneState));
   if (rc) return rc;
-  launch_tile_lanes_pipe_f32(b->d_cg32, b->d_items, b->n_items, b->max_tile_nodes, b->d_st, 1, b->ctx->grid_cap,
+  launch_tile_lanes_pipe_f32(b->d_cg32, b->d_items, b->n_items, b->max_tile_nodes, b->d_st, 1, batch_grid_cap(b),
                              s);
   for (int l = 0; l < b->n; ++l) {
     sw_case* c = b->cases[l];
@@ -2515,6 +2536,113 @@ extern "C" int sw_batch_stats(const sw_batch* b, sw_case_stats* out) {
     int rc = sw_case_stats_get(b->cases[l], out + l);
     if (rc) return rc;
   }
+  return SW_OK;
+}
+
+namespace {
+
+int cu_count(int device, int* out) {
+  int v = 0;
+  HIPC(hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, device));
+  *out = v > 0 ? v : 256;
+  return SW_OK;
+}
+
+// Mean duration (ms) of `reps` launches of fn after one untimed launch.
+template <typename F>
+int time_launches(hipStream_t s, int reps, F&& fn, double* ms) {
+  hipEvent_t e0, e1;
+  HIPC(hipEventCreate(&e0));
+  HIPC(hipEventCreate(&e1));
+  fn();
+  hipError_t e = hipEventRecord(e0, s);
+  for (int r = 0; r < reps && e == hipSuccess; ++r) fn();
+  if (e == hipSuccess) e = hipEventRecord(e1, s);
+  if (e == hipSuccess) e = hipEventSynchronize(e1);
+  float t = 0.0f;
+  if (e == hipSuccess) e = hipEventElapsedTime(&t, e0, e1);
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (e != hipSuccess) return fail(SW_EHIP, "autotune timing failed: %s", hipGetErrorString(e));
+  *ms = (double)t / reps;
+  return SW_OK;
+}
+
+}  // namespace
+
+extern "C" int sw_case_autotune(sw_case* c, int32_t reps, int32_t* choice, double* ms_out) {
+  if (!c) return fail(SW_EINVAL, "NULL case");
+  if (c->precision == SW_FP64) return fail(SW_EINVAL, "autotune tunes the FP32 pass of the mixed precisions");
+  if (reps < 1 || reps > 1000) return fail(SW_EINVAL, "reps must be in 1..1000");
+  HIPC(hipSetDevice(c->ctx->device));
+  hipStream_t s = c->ctx->stream;
+  int n_cu = 0;
+  if (int rc = cu_count(c->ctx->device, &n_cu)) return rc;
+  const int64_t nd = 3 * c->mesh->n_nodes;
+  // zero input (the same work as any other), fresh control block so every
+  // launch runs in full; the inner-solve vectors are free between steps
+  launch_fill_f32(nd, c->p32, 0.0f, s);
+  launch_fill_f32(nd, c->q32, 0.0f, s);
+  const int caps[3] = {0, 8 * std::max(1, 2 * n_cu / 8), 8 * std::max(1, n_cu / 8)};
+  double ms[3];
+  int best = 0;
+  for (int k = 0; k < 3; ++k) {
+    c->grid_cap = caps[k];
+    launch_fill_f64(sizeof(CgCtl) / 8, (double*)c->ctl32, 0.0, s);
+    int rc = time_launches(s, reps, [&] { apply_f32(c, SW_OP_A, c->p32, c->q32, c->ctl32, 1); }, &ms[k]);
+    if (rc) return rc;
+    if (ms[k] < ms[best]) best = k;
+  }
+  LAUNCHED();
+  c->grid_cap = caps[best];
+  if (choice) *choice = best;
+  if (ms_out)
+    for (int k = 0; k < 3; ++k) ms_out[k] = ms[k];
+  return SW_OK;
+}
+
+extern "C" int sw_batch_autotune(sw_batch* b, int32_t reps, int32_t* choice, double* ms_out) {
+  if (!b) return fail(SW_EINVAL, "NULL batch");
+  if (reps < 1 || reps > 1000) return fail(SW_EINVAL, "reps must be in 1..1000");
+  HIPC(hipSetDevice(b->ctx->device));
+  hipStream_t s = b->ctx->stream;
+  int n_cu = 0;
+  if (int rc = cu_count(b->ctx->device, &n_cu)) return rc;
+  for (int l = 0; l < b->n; ++l) {
+    sw_case* c = b->cases[l];
+    const int64_t nd = 3 * c->mesh->n_nodes;
+    launch_fill_f32(nd, c->p32, 0.0f, s);
+    launch_fill_f32(nd, c->q32, 0.0f, s);
+    launch_fill_f64(sizeof(CgCtl) / 8, (double*)c->ctl32, 0.0, s);
+    b->st[l].active = 1;
+  }
+  LAUNCHED();
+  int rc = batch_upload(b, b->d_st, b->st.data(), b->n * sizeof(LaneState));
+  if (rc) return rc;
+  const int caps[2] = {0, 8 * std::max(1, 2 * n_cu / 8)};
+  double ms[4];
+  int best = 0;
+  for (int sch = 0; sch < 2; ++sch) {
+    const std::vector<int2> items = batch_items(b->cases.data(), b->n, sch);
+    if ((rc = batch_upload(b, b->d_items, items.data(), items.size() * sizeof(int2)))) return rc;
+    for (int g = 0; g < 2; ++g) {
+      const int k = 2 * sch + g;
+      rc = time_launches(s, reps, [&] {
+        launch_tile_lanes_pipe_f32(b->d_cg32, b->d_items, b->n_items, b->max_tile_nodes, b->d_st, 1, caps[g], s);
+      }, &ms[k]);
+      if (rc) return rc;
+      if (ms[k] < ms[best]) best = k;
+    }
+  }
+  LAUNCHED();
+  b->schedule = best / 2;
+  b->grid_cap = caps[best % 2];
+  const std::vector<int2> items = batch_items(b->cases.data(), b->n, b->schedule);
+  if ((rc = batch_upload(b, b->d_items, items.data(), items.size() * sizeof(int2)))) return rc;
+  HIPC(hipStreamSynchronize(s));
+  if (choice) *choice = best;
+  if (ms_out)
+    for (int k = 0; k < 4; ++k) ms_out[k] = ms[k];
   return SW_OK;
 }
 
