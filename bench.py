@@ -55,6 +55,11 @@ PROFILE_EVERY = 4
 # of the gathered values are left out: under 2 % of a pass)
 FLOPS_PER_TET = 884 + 299 + 6 + 60
 
+def progress(msg):
+    """One line on stderr per phase (stdout carries only the JSON line)."""
+    print(f"[bench {time.strftime('%H:%M:%S')}] {msg}", file=sys.stderr, flush=True)
+
+
 # the HBM-traffic figure is only used while the operator kernel's sources are
 # unchanged since the counters were taken
 from paper_2404_17754_amd.profsum import kernel_hash  # noqa: E402
@@ -121,6 +126,7 @@ def cpu_baseline(cfg_name, dof_target, steps=20, step0=80):
     t0 = time.perf_counter()
     S = bsr.System(mesh, case.mat, case.tet_mat)
     t_asm = time.perf_counter() - t0
+    progress(f"CPU baseline: sample assembled in {t_asm:.1f} s on {S.threads} threads")
     out = S.march(case.dt, case.ray_alpha, case.ray_beta, case.v_in[step0:], steps, case.rec_node, v0=v0,
                   rtol=1e-8, guess="zero")
     dt_wall = float(out["secs"].sum())
@@ -195,6 +201,7 @@ def batched_study(sw, cg, ctx, per_mesh, steps, proj_dim, legs=("seq", "batched"
         for k in range(per_mesh):
             cases.append((gm, cg.make_case(m, cfg, seed=cfg.seed + 3 * k + len(cases), n_steps=steps)))
             in_sample.append(k < sample)
+        progress(f"batched study: {per_mesh} models of {name} generated")
 
     def run(batched, precision="mixed", guess="proj"):
         sel = cases if batched else [c for c, s in zip(cases, in_sample) if s]
@@ -208,6 +215,8 @@ def batched_study(sw, cg, ctx, per_mesh, steps, proj_dim, legs=("seq", "batched"
                 lane.step(steps)
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
+        progress(f"batched study leg ({'batched' if batched else 'case by case'}, {precision}/{guess}): "
+                 f"{len(sel)} models x {steps} steps in {dt:.1f} s")
         its = np.concatenate([lane.step_log()[0] for lane in lanes]).astype(np.float64)
         worst = float(max(lane.stats()["max_true_rel_res"] for lane in lanes))
         del lanes
@@ -254,6 +263,7 @@ def guess_study(sw, cg, ctx, net, n_models, steps, proj_dim):
     mesh = cg.config_mesh(cfg)
     gm = sw.Mesh(ctx, mesh)
     models = [cg.make_case(mesh, cfg, seed=2000 + k, n_steps=steps) for k in range(n_models)]
+    progress(f"learned-guess study: {n_models} held-out models generated")
     out = {"mesh": f"300x300x100 m, {mesh.n_tets} tets, {3 * mesh.n_nodes} DOF", "models": n_models,
            "seeds": f"2000-{2000 + n_models - 1}", "steps": steps}
     for g in ("poly", "mlp", "proj"):
@@ -266,6 +276,7 @@ def guess_study(sw, cg, ctx, net, n_models, steps, proj_dim):
         sw.Batch(ctx, lanes).step(steps)
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
+        progress(f"learned-guess study: guess {g} done in {dt:.1f} s")
         its = np.concatenate([lane.step_log()[0] for lane in lanes]).astype(np.float64)
         out[g] = {"cg_iters_per_step": round(float(its.mean()), 2), "p50": float(np.percentile(its, 50)),
                   "p95": float(np.percentile(its, 95)),
@@ -329,6 +340,7 @@ def solver_study(sw, ctx, gmesh, case, steps, guess, proj_dim, windows=(20, 100,
     import torch
     out = {"steps": steps, "guess": guess}
     for prec in ("mixed", "flex"):
+        progress(f"outer-solver study: {prec}")
         c = sw.Case(ctx, gmesh, case, rtol=1e-8, precision=prec, guess=guess, proj_dim=proj_dim)
         ev = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
         torch.cuda.synchronize()
@@ -429,6 +441,7 @@ def main():
     t_gen = time.perf_counter() - t_gen
     dof = 3 * mesh.n_nodes
 
+    progress("mesh generated")
     ctx = sw.Context(0)
     t_up = time.perf_counter()
     gmesh = sw.Mesh(ctx, mesh)
@@ -440,6 +453,7 @@ def main():
         net, train_info = train_network(sw, cg, ctx, cfg, args.train_cases, args.train_steps, args.adam_steps,
                                         box=tuple(float(v) for v in args.train_box.split(",")))
 
+    progress("network trained")
     # warm-up on a separate copy of the case
     if args.warmup > 0:
         w = sw.Case(ctx, gmesh, case, rtol=1e-8, precision=args.precision, guess=args.guess,
@@ -488,6 +502,7 @@ def main():
     del gc
     torch.cuda.empty_cache()
 
+    progress("timed region done")
     # the dominant kernel of the timed region: the FP32 element-by-element pass
     dom = DOMINANT
     tot_ms, n_launch, full_ms, n_full = kernels[dom]
@@ -530,6 +545,7 @@ def main():
         compare["speedup_vs_plain_fp64"] = round(compare["plain_fp64"]["ms_per_step"] / ms_window, 3)
         compare["plain_fp64"]["method"] = "FP64 block-Jacobi PCG, zero initial guess"
 
+    progress("comparison legs done")
     solvers = None
     if args.solver_study > 0:
         case_s = cg.make_case(mesh, cfg, n_steps=args.solver_study + 1)
@@ -542,6 +558,7 @@ def main():
         batched = batched_study(sw, cg, ctx, args.batched, args.batched_steps, args.proj_dim,
                                 tuple(args.batched_legs.split(",")), sample=args.batched_sample)
 
+    progress("batched study done")
     gstudy = None
     if args.guess_study > 0:
         torch.cuda.empty_cache()
@@ -552,6 +569,7 @@ def main():
         torch.cuda.empty_cache()
         fit = fit_study(sw, cg, ctx, args.fit_study, 20, args.proj_dim)
 
+    progress("studies done; CPU baseline next")
     cpu = None if args.no_cpu_baseline else cpu_baseline(args.config, dof)
 
     out = {

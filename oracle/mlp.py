@@ -11,7 +11,11 @@ step's CG solve.  The reading implemented on both sides:
   the element mean of the same component), and the node's Vs/500 and
   rho/2000 (means over the elements containing it);
 * scale s = max_k(|d_k|, |nb_k|); network input
-  x = (d_0..d_3, nb_0..nb_3) / s, Vs/500, rho/2000;
+  x = (D(d), D(nb)) / s, Vs/500, rho/2000, where D(a) = (a_0, a_0 - a_1,
+  a_0 - 2 a_1 + a_2, a_0 - 3 a_1 + 3 a_2 - a_3) are the differences of
+  increasing order (the same information as the increments, but the small
+  higher differences, which carry the extrapolation error, keep their
+  relative precision when the network rounds its inputs to FP16);
 * network: x (10) -> ReLU(64) -> ReLU(64) -> y (linear), parameters packed
   as W1[64][10], b1[64], W2[64][64], b2[64], w3[64], b3 (4929 values);
 * guess: du0 = p2 + s y with p2 = 3 d_0 - 3 d_1 + d_2 (quadratic
@@ -127,11 +131,21 @@ def node_material(tet10, n_nodes, mat, tet_mat):
     return acc[:, 0], acc[:, 1]
 
 
+def differences(a):
+    """(n, 4) newest first -> (a_0, a_0 - a_1, a_0 - 2 a_1 + a_2,
+    a_0 - 3 a_1 + 3 a_2 - a_3): backward differences of orders 0..3."""
+    return np.stack([a[:, 0], a[:, 0] - a[:, 1], a[:, 0] - 2 * a[:, 1] + a[:, 2],
+                     a[:, 0] - 3 * a[:, 1] + 3 * a[:, 2] - a[:, 3]], 1)
+
+
 def features(own, nbr, vs, rho):
     """own, nbr: (n, 4) newest first; vs, rho: (n,).  Returns X (n, 10), s (n,)."""
+    own = np.asarray(own, np.float64)
+    nbr = np.asarray(nbr, np.float64)
     s = np.maximum(np.abs(own).max(1), np.abs(nbr).max(1))
     inv = np.where(s > 0, 1.0 / np.where(s > 0, s, 1.0), 0.0)
-    X = np.concatenate([own * inv[:, None], nbr * inv[:, None], (vs / 500.0)[:, None], (rho / 2000.0)[:, None]], 1)
+    X = np.concatenate([differences(own) * inv[:, None], differences(nbr) * inv[:, None],
+                        (vs / 500.0)[:, None], (rho / 2000.0)[:, None]], 1)
     return X, s
 
 

@@ -2,10 +2,14 @@
 // (ReLU) predicting a correction to quadratic extrapolation of the last
 // increments.  Inference runs on the matrix cores (v_mfma_f32_16x16x16_f16,
 // FP16 weights and activations, FP32 accumulation); training uses FP32
-// forward / back-propagation kernels and Adam.  Feature definitions: the last
-// four increments of the DOF, their element-neighbour means, and the node's
-// Vs/500 and rho/2000, the first eight divided by their largest magnitude s;
-// guess = p2 + s * y with p2 = 3 d0 - 3 d1 + d2.
+// forward / back-propagation kernels and Adam.  Feature definitions: the
+// backward differences of orders 0..3 of the last four increments of the DOF
+// and of their element-neighbour means, divided by the largest magnitude s of
+// those increments, and the node's Vs/500 and rho/2000; guess = p2 + s * y
+// with p2 = 3 d0 - 3 d1 + d2.  The differences are formed in FP64 before the
+// rounding to FP16: the higher ones are small (the third is the error the
+// quadratic extrapolation made at the last step), and formed after the
+// rounding they would be lost in it.
 #include <hip/hip_runtime.h>
 
 #include "sw_device.h"
@@ -135,17 +139,39 @@ __device__ __forceinline__ double feat_scale(const GuessIn& g) {
   return s;
 }
 
-__device__ __forceinline__ half4 feat_quartet(const GuessIn& g, double s, int q) {
+// backward differences of orders 0..3 of a[0..3] (newest first)
+__device__ __forceinline__ void differences(const double a[4], double o[4]) {
+  o[0] = a[0];
+  o[1] = a[0] - a[1];
+  o[2] = a[0] - 2.0 * a[1] + a[2];
+  o[3] = a[0] - 3.0 * a[1] + 3.0 * a[2] - a[3];
+}
+
+// the ten features (FP32; the network rounds them to FP16)
+__device__ __forceinline__ void features(const GuessIn& g, double s, float f[MLP_IN]) {
   const double inv = s > 0.0 ? 1.0 / s : 0.0;
+  double nb[4], dd[4], dn[4];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) nb[k] = (double)g.nb[k];
+  differences(g.d, dd);
+  differences(nb, dn);
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    f[k] = (float)(dd[k] * inv);
+    f[4 + k] = (float)(dn[k] * inv);
+  }
+  f[8] = g.vs / 500.0f;
+  f[9] = g.rho / 2000.0f;
+}
+
+__device__ __forceinline__ half4 feat_quartet(const GuessIn& g, double s, int q) {
+  float f[MLP_IN];
+  features(g, s, f);
   half4 x;
 #pragma unroll
   for (int j = 0; j < 4; ++j) {
-    float v = 0.0f;
-    if (q == 0) v = (float)(g.d[j] * inv);
-    else if (q == 1) v = (float)((double)g.nb[j] * inv);
-    else if (q == 2 && j == 0) v = g.vs / 500.0f;
-    else if (q == 2 && j == 1) v = g.rho / 2000.0f;
-    x[j] = (_Float16)v;
+    const int k = 4 * q + j;
+    x[j] = (_Float16)(k < MLP_IN ? f[k] : 0.0f);
   }
   return x;
 }
@@ -201,12 +227,9 @@ __global__ __launch_bounds__(TPB) void k_mlp_collect(MlpFeat F, const double* __
   const double s = feat_scale(in);
   const double inv = s > 0.0 ? 1.0 / s : 0.0;
   float* o = out + ((row0 + j) % capacity) * MLP_ROW;
-  for (int k = 0; k < 4; ++k) {
-    o[k] = (float)(in.d[k] * inv);
-    o[4 + k] = (float)((double)in.nb[k] * inv);
-  }
-  o[8] = in.vs / 500.0f;
-  o[9] = in.rho / 2000.0f;
+  float f[MLP_IN];
+  features(in, s, f);
+  for (int k = 0; k < MLP_IN; ++k) o[k] = f[k];
   const double p2 = 3.0 * in.d[0] - 3.0 * in.d[1] + in.d[2];
   o[10] = (float)((du[dof] - p2) * inv);
   o[11] = (float)(s * s);

@@ -115,5 +115,9 @@ def test_features_normalisation(s_zero):
     if s_zero:
         assert np.all(s == 0) and np.all(X[:, :8] == 0)
     else:
-        assert np.all(s == 8.0) and np.abs(X[:, :8]).max() == 1.0
+        # backward differences of orders 0..3, by hand, over s = 8
+        assert np.all(s == 8.0)
+        own_d = [1.0, 1.0 + 4.0, 1.0 + 8.0 + 2.0, 1.0 + 12.0 + 6.0 - 0.5]
+        nbr_d = [0.0, -1.0, 0.0 - 2.0 - 8.0, 0.0 - 3.0 - 24.0]
+        assert np.array_equal(X[0, :8], np.array(own_d + nbr_d) / 8.0)
     assert np.all(X[:, 8] == 1.0) and np.all(X[:, 9] == 1.0)
