@@ -55,6 +55,10 @@ PROFILE_EVERY = 4
 # of the gathered values are left out: under 2 % of a pass)
 FLOPS_PER_TET = 884 + 299 + 6 + 60
 
+# guesses that use the trained network
+LEARNED = ("mlp", "proj_mlp")
+
+
 def progress(msg):
     """One line on stderr per phase (stdout carries only the JSON line)."""
     print(f"[bench {time.strftime('%H:%M:%S')}] {msg}", file=sys.stderr, flush=True)
@@ -143,16 +147,21 @@ def cpu_baseline(cfg_name, dof_target, steps=20, step0=80):
                        f"assembly {t_asm:.1f} s, not timed), scaled by DOF ratio {dof}/{dof_target}")}
 
 
-def train_network(sw, cg, ctx, cfg, n_cases, n_steps, train_steps, per_step=8192, box=(200.0, 200.0, 100.0)):
-    """Histories of `n_cases` training models (boxes of `box` with the
-    workload's cells, time step and input; seeded interface fields of
-    amplitude 5-20 m and correlation 50-200 m, seeds 500 on) marched together
-    as one batch with the polynomial guess, sampled, then Adam on the GPU."""
+def train_network(sw, cg, ctx, n_cases, n_steps, train_steps, per_step=4096, batch=8192,
+                  box=(200.0, 200.0, 100.0)):
+    """Histories of `n_cases` training models of the batched workload
+    (boxes of `box`, 5 m cells, its 2 Hz input and time step; seeded
+    interface fields of amplitude 5-20 m and correlation 50-200 m, seeds
+    500 on, none of them a held-out model) marched together as one batch
+    with the polynomial guess, `per_step` DOFs sampled per model and step,
+    then `train_steps` Adam steps on minibatches of `batch` rows on the
+    GPU."""
     import numpy as np
     import torch
     t0 = time.perf_counter()
-    tcfg = cg.BoxConfig("train", box, cfg.cell, 30.0, (5.0, 20.0), (50.0, 200.0), cfg.freqs,
-                        cfg.t0, cfg.dt, n_steps, 4, 500)
+    base = cg.CONFIGS["batch200"]
+    tcfg = cg.BoxConfig("train", box, base.cell, base.h0, base.amp, base.corr, base.freqs, base.t0, base.dt,
+                        n_steps, 4, 500)
     tmesh = cg.config_mesh(tcfg)
     gtm = sw.Mesh(ctx, tmesh)
     lanes = []
@@ -165,12 +174,12 @@ def train_network(sw, cg, ctx, cfg, n_cases, n_steps, train_steps, per_step=8192
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     net = sw.Mlp(ctx, seed=1)
-    losses = net.train(S, steps=train_steps, batch=per_step, lr=2e-3, seed=5)
+    losses = net.train(S, steps=train_steps, batch=batch, lr=2e-3, seed=5)
     torch.cuda.synchronize()
     t2 = time.perf_counter()
     info = {"training_models": n_cases, "mesh": f"{box[0]:.0f}x{box[1]:.0f}x{box[2]:.0f} m, {tmesh.n_tets} tets",
             "steps_each": n_steps,
-            "rows": int(S.shape[0]), "adam_steps": train_steps, "batch": per_step,
+            "rows": int(S.shape[0]), "adam_steps": train_steps, "batch": batch,
             "loss_first20": float(np.mean(losses[:20])), "loss_last20": float(np.mean(losses[-20:])),
             "collect_s": round(t1 - t0, 2), "train_s": round(t2 - t1, 2),
             "training_cg_iters_per_step": float(np.mean([c.step_log()[0].mean() for c in lanes]))}
@@ -254,9 +263,11 @@ def guess_study(sw, cg, ctx, net, n_models, steps, proj_dim):
     the 300 x 300 x 100 m mesh (5 m cells; seeded interface fields of the
     batched workload, seeds unseen in training), each marched `steps` steps
     from rest once per guess (extrapolation, the trained network, the
-    projection), every guess as one batch.  CG iterations per step (mean,
-    median, 95th percentile over models and steps), the worst true relative
-    residual and the batch's case-timesteps/s."""
+    projection, the projection with the network's direction), every guess
+    as one batch.  CG iterations per step (mean, median, 95th percentile
+    over models and steps), the worst true relative residual and the
+    batch's case-timesteps/s; and the network's loss on rows sampled from
+    the held-out marches against the extrapolation's."""
     import numpy as np
     import torch
     cfg = cg.CONFIGS["batch300"]
@@ -266,11 +277,15 @@ def guess_study(sw, cg, ctx, net, n_models, steps, proj_dim):
     progress(f"learned-guess study: {n_models} held-out models generated")
     out = {"mesh": f"300x300x100 m, {mesh.n_tets} tets, {3 * mesh.n_nodes} DOF", "models": n_models,
            "seeds": f"2000-{2000 + n_models - 1}", "steps": steps}
-    for g in ("poly", "mlp", "proj"):
+    for g in ("poly", "mlp", "proj", "proj_mlp"):
         lanes = [sw.Case(ctx, gm, c, precision="mixed", guess=g, proj_dim=proj_dim) for c in models]
-        if g == "mlp":
+        if g in LEARNED:
             for lane in lanes:
                 lane.attach_mlp(net)
+        if g == "poly":
+            # rows of the held-out marches, for the network's loss on them
+            for k, lane in enumerate(lanes):
+                lane.set_sampler(capacity=steps * 512, per_step=512, seed=7000 + k)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         sw.Batch(ctx, lanes).step(steps)
@@ -278,6 +293,14 @@ def guess_study(sw, cg, ctx, net, n_models, steps, proj_dim):
         dt = time.perf_counter() - t0
         progress(f"learned-guess study: guess {g} done in {dt:.1f} s")
         its = np.concatenate([lane.step_log()[0] for lane in lanes]).astype(np.float64)
+        if g == "poly":
+            S = torch.cat([lane.samples() for lane in lanes])
+            _, l_net = net.gradient(S)
+            _, l_ext = sw.Mlp(ctx, seed=1).gradient(S)  # zero output layer: the extrapolation itself
+            out["heldout_loss"] = {"rows": int(S.shape[0]), "trained": l_net, "extrapolation": l_ext,
+                                   "note": "loss of the guess's correction (sum s^2 (y - t)^2 / sum s^2) on rows "
+                                           "sampled from the held-out marches"}
+            del S
         out[g] = {"cg_iters_per_step": round(float(its.mean()), 2), "p50": float(np.percentile(its, 50)),
                   "p95": float(np.percentile(its, 95)),
                   "max_true_rel_res": float(max(lane.stats()["max_true_rel_res"] for lane in lanes)),
@@ -285,7 +308,8 @@ def guess_study(sw, cg, ctx, net, n_models, steps, proj_dim):
                   "case_timesteps_per_s": round(n_models * steps / dt, 2)}
         del lanes
         torch.cuda.empty_cache()
-    out["mlp_vs_poly_iters"] = round(out["mlp"]["cg_iters_per_step"] / out["poly"]["cg_iters_per_step"], 4)
+    for a, b in (("mlp", "poly"), ("proj", "poly"), ("proj_mlp", "poly"), ("proj_mlp", "proj")):
+        out[f"{a}_vs_{b}_iters"] = round(out[a]["cg_iters_per_step"] / out[b]["cg_iters_per_step"], 4)
     return out
 
 
@@ -390,7 +414,7 @@ def main():
     ap.add_argument("--steps", type=int, default=400, help="timed steps (from rest; 400 = the whole analysis)")
     ap.add_argument("--warmup", type=int, default=3, help="untimed steps on a separate copy of the case")
     ap.add_argument("--config", default="large")
-    ap.add_argument("--guess", default="proj", choices=["zero", "poly", "mlp", "proj"])
+    ap.add_argument("--guess", default="proj", choices=["zero", "poly", "mlp", "proj", "proj_mlp"])
     ap.add_argument("--precision", default="mixed", choices=["mixed", "flex"],
                     help="outer solver around the FP32 inner CG: iterative refinement or flexible CG")
     ap.add_argument("--proj-dim", type=int, default=6, help="past increments spanned by the projection guess")
@@ -413,7 +437,7 @@ def main():
                     help="steps (from rest) of the outer-solver study: refinement vs flexible CG (0 = skip)")
     ap.add_argument("--fit-study", type=int, default=0,
                     help="steps of an extra input-estimation study (Green's runs + fit) on the 300 m mesh (0 = skip)")
-    ap.add_argument("--train-cases", type=int, default=4)
+    ap.add_argument("--train-cases", type=int, default=16)
     ap.add_argument("--train-box", default="200,200,100", help="training models' box (m)")
     ap.add_argument("--train-steps", type=int, default=150)
     ap.add_argument("--adam-steps", type=int, default=3000)
@@ -449,8 +473,8 @@ def main():
     t_up = time.perf_counter() - t_up
 
     net, train_info = None, None
-    if args.guess == "mlp" or args.guess_study > 0 or (args.compare_steps > 0 and not args.no_mlp_compare):
-        net, train_info = train_network(sw, cg, ctx, cfg, args.train_cases, args.train_steps, args.adam_steps,
+    if args.guess in LEARNED or args.guess_study > 0 or (args.compare_steps > 0 and not args.no_mlp_compare):
+        net, train_info = train_network(sw, cg, ctx, args.train_cases, args.train_steps, args.adam_steps,
                                         box=tuple(float(v) for v in args.train_box.split(",")))
 
     progress("network trained")
@@ -458,7 +482,7 @@ def main():
     if args.warmup > 0:
         w = sw.Case(ctx, gmesh, case, rtol=1e-8, precision=args.precision, guess=args.guess,
                     proj_dim=args.proj_dim, inner_rtol=args.inner_rtol)
-        if args.guess == "mlp":
+        if args.guess in LEARNED:
             w.attach_mlp(net)
         w.step(args.warmup)
         torch.cuda.synchronize()
@@ -467,7 +491,7 @@ def main():
 
     gc = sw.Case(ctx, gmesh, case, rtol=1e-8, precision=args.precision, guess=args.guess, proj_dim=args.proj_dim,
                  inner_rtol=args.inner_rtol)
-    if args.guess == "mlp":
+    if args.guess in LEARNED:
         gc.attach_mlp(net)
     if args.calibrate_copy_mib > 0:
         src = torch.ones(args.calibrate_copy_mib << 18, dtype=torch.float32, device="cuda")
@@ -531,11 +555,12 @@ def main():
         compare = {"window_steps": cmp_n,
                    args.guess: {"ms_per_step": round(ms_window, 2), "value": round(1000.0 / ms_window, 3),
                                 "cg_iters_per_step": float(np.mean(it[:cmp_n]))}}
-        legs = [(g, dict(precision=args.precision, guess=g, proj_dim=args.proj_dim, net=net if g == "mlp" else None))
-                for g in ("poly", "mlp", "proj") if g != args.guess and (g != "mlp" or net is not None)]
+        legs = [(g, dict(precision=args.precision, guess=g, proj_dim=args.proj_dim,
+                         net=net if g in LEARNED else None))
+                for g in ("poly", "mlp", "proj", "proj_mlp") if g != args.guess and (g not in LEARNED or net is not None)]
         other = "flex" if args.precision == "mixed" else "mixed"
         legs.append((f"{other}_{args.guess}", dict(precision=other, guess=args.guess, proj_dim=args.proj_dim,
-                                                    net=net if args.guess == "mlp" else None)))
+                                                    net=net if args.guess in LEARNED else None)))
         legs.append(("plain_fp64", dict(precision="fp64", guess="zero")))
         for name, kw in legs:
             ms, pit, prel, pst = timed_window(sw, ctx, gmesh, case, cmp_n, **kw)

@@ -95,8 +95,14 @@ enum {
   SW_GUESS_ZERO = 0,  /* du0 = 0 */
   SW_GUESS_POLY = 1,  /* Lagrange extrapolation of the last poly_order + 1 increments */
   SW_GUESS_MLP = 2,   /* poly extrapolation plus a learned per-DOF correction */
-  SW_GUESS_PROJ = 3   /* Galerkin projection of the step's solution onto the span of the
+  SW_GUESS_PROJ = 3,  /* Galerkin projection of the step's solution onto the span of the
                          last proj_dim increments (A-norm optimal combination) */
+  SW_GUESS_PROJ_MLP = 4 /* the same projection onto the span of the last proj_dim
+                           increments and the network's correction w = s * y of
+                           SW_GUESS_MLP (one more direction, its image A w taken
+                           with one FP64 operator pass): the combination can be no
+                           worse in the A-norm than either; needs a network
+                           (sw_case_attach_mlp) */
 };
 
 /* operators for sw_case_apply (bit mask; the terms are summed) */
@@ -172,6 +178,9 @@ typedef struct {
   int32_t tile_max_nodes;     /* tile capacity of the device layout: distinct nodes per tile,
                                  64..1280 (0 = 1280) */
   int32_t tile_max_elems;     /* elements per tile, 16..1024 (0 = 1024) */
+  int32_t deterministic;      /* 1: also build, for deterministic cases, each node's list of the
+                                 element and face slots that touch it (in element order;
+                                 4 bytes per slot); 0: not */
 } sw_mesh_desc;
 
 /* Device workspace needed by sw_mesh_create for this mesh. */
@@ -204,7 +213,14 @@ typedef struct {
   const int32_t* rec_node; /* host, n_rec node ids */
   int64_t n_steps;       /* capacity of the march (steps 1..n_steps) */
   const double* v_in;    /* host, (n_steps + 1) x 3 incident velocity at t = n dt */
-  int32_t proj_dim;      /* SW_GUESS_PROJ: increments spanned, 2..16 (0 = 6) */
+  int32_t proj_dim;      /* SW_GUESS_PROJ: increments spanned, 2..16; SW_GUESS_PROJ_MLP: 2..15 (0 = 6) */
+  int32_t deterministic; /* 1: bitwise reproducible march: SW_FP64 with SW_GUESS_ZERO, _POLY or
+                            _PROJ, on a mesh created with deterministic = 1.  Every element's and
+                            face's contribution goes to a buffer of the case (240 bytes per tet,
+                            144 per face) and each node sums its own in element order, and every
+                            reduction adds in a fixed order, so the same inputs give the same
+                            bits on every run; slower (the default adds in arrival order).
+                            0: the default */
 } sw_case_desc;
 
 SW_API int sw_case_workspace_bytes(const sw_mesh* mesh, const sw_case_desc* desc, size_t* bytes);
@@ -331,7 +347,8 @@ SW_API int sw_mlp_gradient(sw_mlp* mlp, const float* S_dev, int64_t n, double* g
 SW_API int sw_mlp_train(sw_mlp* mlp, const float* S_dev, int64_t n, int32_t steps, int32_t batch, float lr,
                         uint64_t seed, float* loss_host);
 /* Use (or with NULL stop using) the network for a case created with
- * guess SW_GUESS_MLP; the network stays owned by the caller. */
+ * guess SW_GUESS_MLP or SW_GUESS_PROJ_MLP; the network stays owned by the
+ * caller. */
 SW_API int sw_case_attach_mlp(sw_case* c, sw_mlp* mlp);
 /* Record training rows while the case marches: after each step's solve,
  * per_step DOFs drawn by a counter-based generator keyed on (seed, step)

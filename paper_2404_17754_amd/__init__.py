@@ -25,7 +25,8 @@ from ._lib import SwError  # noqa: F401
 
 PRECISIONS = {"fp64": L.SW_FP64, "mixed": L.SW_MIXED_FP32, "mixed_fp32": L.SW_MIXED_FP32,
               "flex": L.SW_MIXED_FP32_FLEX}
-GUESSES = {"zero": L.SW_GUESS_ZERO, "poly": L.SW_GUESS_POLY, "mlp": L.SW_GUESS_MLP, "proj": L.SW_GUESS_PROJ}
+GUESSES = {"zero": L.SW_GUESS_ZERO, "poly": L.SW_GUESS_POLY, "mlp": L.SW_GUESS_MLP, "proj": L.SW_GUESS_PROJ,
+           "proj_mlp": L.SW_GUESS_PROJ_MLP}
 OPS = {"M": L.SW_OP_M, "K": L.SW_OP_K, "Cabs": L.SW_OP_CABS, "A": L.SW_OP_A}
 
 
@@ -98,9 +99,10 @@ class Context:
 
 class Mesh:
     """Device layout of a mesh (sw_mesh_create).  tile_nodes / tile_elems:
-    tile capacity (0 = the library's default 1280 / 1024)."""
+    tile capacity (0 = the library's default 1280 / 1024); deterministic:
+    also build the node incidence lists deterministic cases need."""
 
-    def __init__(self, ctx: Context, m, tile_nodes=0, tile_elems=0):
+    def __init__(self, ctx: Context, m, tile_nodes=0, tile_elems=0, deterministic=False):
         self.ctx = ctx
         lib = ctx.lib
         self._xyz = np.ascontiguousarray(m.xyz, np.float64)
@@ -110,7 +112,8 @@ class Mesh:
         self._fr = np.ascontiguousarray(m.face_role, np.uint8)
         self.n_nodes, self.n_tets, self.n_faces = len(self._xyz), len(self._tet), len(self._tri)
         d = L.MeshDesc(self.n_nodes, self.n_tets, self.n_faces, _ptr(self._xyz), _ptr(self._tet),
-                       _ptr(self._tri), _ptr(self._ft), _ptr(self._fr), tile_nodes, tile_elems)
+                       _ptr(self._tri), _ptr(self._ft), _ptr(self._fr), tile_nodes, tile_elems,
+                       int(bool(deterministic)))
         nb = C.c_size_t()
         L.check(lib.sw_mesh_workspace_bytes(C.byref(d), C.byref(nb)))
         self.ws = _workspace(nb.value, ctx.device)
@@ -136,7 +139,7 @@ class Case:
     v_in ((n_steps+1) x 3), dt, ray_alpha, ray_beta (and n_steps)."""
 
     def __init__(self, ctx: Context, mesh: Mesh, c, rtol=1e-8, max_iter=10000, precision="fp64",
-                 guess="zero", poly_order=2, inner_rtol=0.0, n_steps=None, proj_dim=6):
+                 guess="zero", poly_order=2, inner_rtol=0.0, n_steps=None, proj_dim=6, deterministic=False):
         self.ctx, self.mesh = ctx, mesh
         lib = ctx.lib
         v_in = np.ascontiguousarray(c.v_in, np.float64)
@@ -152,7 +155,7 @@ class Case:
         d = L.CaseDesc(float(c.dt), float(c.ray_alpha), float(c.ray_beta), float(rtol), int(max_iter),
                        PRECISIONS[precision], GUESSES[guess], int(poly_order), float(inner_rtol),
                        len(mat), _ptr(mat), _ptr(tet_mat), len(rec), _ptr(rec), n_steps, _ptr(v_in),
-                       int(proj_dim))
+                       int(proj_dim), int(bool(deterministic)))
         nb = C.c_size_t()
         L.check(lib.sw_case_workspace_bytes(mesh.h, C.byref(d), C.byref(nb)))
         self.ws_bytes = nb.value

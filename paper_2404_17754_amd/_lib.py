@@ -11,7 +11,7 @@ LIB_PATH = os.path.join(_HERE, "libsw.so")
 SW_OK, SW_EINVAL, SW_ENOWS, SW_EMESH, SW_ENOCONV, SW_EHIP, SW_ESTATE = 0, -1, -2, -3, -4, -5, -6
 SW_FLAG_NOCONV, SW_FLAG_NONFINITE, SW_FLAG_GUESS_FALLBACK = 1, 2, 4
 SW_FP64, SW_MIXED_FP32, SW_MIXED_FP32_FLEX = 0, 1, 2
-SW_GUESS_ZERO, SW_GUESS_POLY, SW_GUESS_MLP, SW_GUESS_PROJ = 0, 1, 2, 3
+SW_GUESS_ZERO, SW_GUESS_POLY, SW_GUESS_MLP, SW_GUESS_PROJ, SW_GUESS_PROJ_MLP = 0, 1, 2, 3, 4
 SW_OP_M, SW_OP_K, SW_OP_CABS, SW_OP_A = 1, 2, 4, 8
 MLP_NPARAM, MLP_ROW = 4929, 12
 MISFIT_NOALLOC_MAX_REC = 16384
@@ -31,7 +31,7 @@ class MeshDesc(C.Structure):
     _fields_ = [("n_nodes", C.c_int64), ("n_tets", C.c_int64), ("n_faces", C.c_int64),
                 ("xyz", C.c_void_p), ("tet10", C.c_void_p), ("tri6", C.c_void_p),
                 ("face_tet", C.c_void_p), ("face_role", C.c_void_p), ("tile_max_nodes", C.c_int32),
-                ("tile_max_elems", C.c_int32)]
+                ("tile_max_elems", C.c_int32), ("deterministic", C.c_int32)]
 
 
 class CaseDesc(C.Structure):
@@ -39,7 +39,7 @@ class CaseDesc(C.Structure):
                 ("max_iter", C.c_int32), ("precision", C.c_int32), ("guess", C.c_int32), ("poly_order", C.c_int32),
                 ("inner_rtol", C.c_double), ("n_mat", C.c_int32), ("mat", C.c_void_p), ("tet_mat", C.c_void_p),
                 ("n_rec", C.c_int32), ("rec_node", C.c_void_p), ("n_steps", C.c_int64), ("v_in", C.c_void_p),
-                ("proj_dim", C.c_int32)]
+                ("proj_dim", C.c_int32), ("deterministic", C.c_int32)]
 
 
 class CaseStats(C.Structure):

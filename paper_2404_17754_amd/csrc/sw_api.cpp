@@ -156,6 +156,10 @@ struct sw_mesh {
 struct sw_case {
   sw_ctx* ctx;
   sw_mesh* mesh;
+  // deterministic passes: element and face result slots (null otherwise)
+  bool det = false;
+  double* det_e = nullptr;
+  double* det_f = nullptr;
   // parameters
   double dt, alpha, beta, rtol, inner_rtol;
   int32_t max_iter, precision, guess, poly_order, n_mat, n_rec;
@@ -199,7 +203,9 @@ struct sw_case {
   uint64_t samp_seed = 0;
   // projection guess: ring of past increments X, their images Y = A X, the
   // Gram matrix X^T A X on the host
-  int proj_dim = 0, proj_count = 0, proj_head = -1;
+  // proj_slots = proj_dim, plus one for the network's direction (slot
+  // proj_dim) with SW_GUESS_PROJ_MLP
+  int proj_dim = 0, proj_slots = 0, proj_count = 0, proj_head = -1;
   double *projX = nullptr, *projY = nullptr, *proj_part = nullptr, *proj_out = nullptr, *proj_theta = nullptr;
   std::vector<double> projG, proj_h, proj_th;
   // slots stored since the last projection whose Gram rows are still to be
@@ -258,6 +264,10 @@ struct sw_batch {
 };
 
 inline int batch_grid_cap(const sw_batch* b) { return b->grid_cap >= 0 ? b->grid_cap : b->ctx->grid_cap; }
+
+// the case's guess uses the network (and so the neighbour-mean history)
+inline bool learned(const sw_case* c) { return c->guess == SW_GUESS_MLP || c->guess == SW_GUESS_PROJ_MLP; }
+inline bool needs_mlp(const sw_case* c) { return learned(c) && !c->mlp; }
 
 static int static_scratch_init(int device);
 
@@ -366,6 +376,9 @@ static int validate_mesh(const sw_mesh_desc* d) {
     return fail(SW_EINVAL, "tile_max_nodes %d outside 64..%d (0: default)", d->tile_max_nodes, TILE_MAX_NODES);
   if (d->tile_max_elems != 0 && (d->tile_max_elems < 16 || d->tile_max_elems > TILE_MAX_ELEMS))
     return fail(SW_EINVAL, "tile_max_elems %d outside 16..%d (0: default)", d->tile_max_elems, TILE_MAX_ELEMS);
+  if (d->deterministic != 0 && d->deterministic != 1) return fail(SW_EINVAL, "deterministic must be 0 or 1");
+  if (d->deterministic && (d->n_tets > (int64_t)INT32_MAX / 10 || d->n_faces > (int64_t)INT32_MAX / 6))
+    return fail(SW_EINVAL, "too many elements for the int32 slot lists of deterministic passes");
   for (int64_t i = 0; i < 3 * d->n_nodes; ++i)
     if (!std::isfinite(d->xyz[i])) return fail(SW_EMESH, "non-finite coordinate at node %lld", (long long)(i / 3));
   static const int EA[6] = {0, 1, 0, 0, 1, 2}, EB[6] = {1, 2, 2, 3, 3, 3};
@@ -479,7 +492,7 @@ const HostLayout& layout_for(const sw_mesh_desc* d) {
   return g_layout.L;
 }
 
-size_t mesh_layout(const HostLayout& L, Carver& cv, MeshDev* md) {
+size_t mesh_layout(const HostLayout& L, bool det, Carver& cv, MeshDev* md) {
   const int32_t nT = L.n_tiles;
   auto conn_loc = cv.take<uint16_t>(10 * L.tet_stride);
   auto teo = cv.take<int32_t>(nT + 1);
@@ -498,6 +511,14 @@ size_t mesh_layout(const HostLayout& L, Carver& cv, MeshDev* md) {
   auto u2i = cv.take<int32_t>(L.n_nodes);
   auto i2u = cv.take<int32_t>(L.n_nodes);
   auto inv_val = cv.take<float>(L.n_nodes);
+  // incidence lists of the deterministic passes (sizes known from the counts)
+  int32_t *inc_off = nullptr, *inc = nullptr, *finc_off = nullptr, *finc = nullptr;
+  if (det) {
+    inc_off = cv.take<int32_t>(L.n_nodes + 1);
+    inc = cv.take<int32_t>(10 * L.n_tets);
+    finc_off = cv.take<int32_t>(L.n_nodes + 1);
+    finc = cv.take<int32_t>(std::max<int64_t>(6 * L.n_faces, 1));
+  }
   if (md) {
     md->n_nodes = L.n_nodes;
     md->n_tets = L.n_tets;
@@ -524,6 +545,10 @@ size_t mesh_layout(const HostLayout& L, Carver& cv, MeshDev* md) {
     md->node_u2i = u2i;
     md->node_i2u = i2u;
     md->inv_valence = inv_val;
+    md->inc_off = inc_off;
+    md->inc = inc;
+    md->finc_off = finc_off;
+    md->finc = finc;
   }
   return cv.off;
 }
@@ -541,7 +566,7 @@ extern "C" int sw_mesh_workspace_bytes(const sw_mesh_desc* d, size_t* bytes) {
   int rc = validate_mesh(d);
   if (rc) return rc;
   Carver cv(nullptr);
-  *bytes = mesh_layout(layout_for(d), cv, nullptr);
+  *bytes = mesh_layout(layout_for(d), d->deterministic != 0, cv, nullptr);
   return SW_OK;
 }
 
@@ -551,14 +576,15 @@ extern "C" int sw_mesh_create(sw_ctx* ctx, const sw_mesh_desc* d, void* ws, size
   if (rc) return rc;
   const HostLayout& L = layout_for(d);
   if (L.max_tile_nodes > TILE_MAX_NODES) return fail(SW_EMESH, "tile exceeds the LDS node capacity");
+  const bool det = d->deterministic != 0;
   Carver dry(nullptr);
-  const size_t need = mesh_layout(L, dry, nullptr);
+  const size_t need = mesh_layout(L, det, dry, nullptr);
   if (!ws || ((uintptr_t)ws & 255)) return fail(SW_ENOWS, "mesh workspace NULL or not 256-byte aligned");
   if (ws_bytes < need) return fail(SW_ENOWS, "mesh workspace %zu bytes < %zu needed", ws_bytes, need);
   HIPC(hipSetDevice(ctx->device));
   Carver cv(ws);
   MeshDev md;
-  mesh_layout(L, cv, &md);
+  mesh_layout(L, det, cv, &md);
   hipStream_t s = ctx->stream;
   HIPC(up(md.conn_loc, L.conn_loc, s));
   HIPC(up(md.tile_elem_off, L.tile_elem_off, s));
@@ -575,6 +601,16 @@ extern "C" int sw_mesh_create(sw_ctx* ctx, const sw_mesh_desc* d, void* ws, size
   HIPC(up(md.node_u2i, L.node_u2i, s));
   HIPC(up(md.node_i2u, L.node_i2u, s));
   HIPC(up(md.inv_valence, L.inv_valence, s));
+  if (det) {
+    Incidence I;
+    build_incidence(L, I);
+    HIPC(up(md.inc_off, I.elem_off, s));
+    HIPC(up(md.inc, I.elem, s));
+    HIPC(up(md.finc_off, I.face_off, s));
+    HIPC(up(md.finc, I.face, s));
+    // the uploads read the host lists: finish them before I goes away
+    HIPC(hipStreamSynchronize(s));
+  }
   launch_geom(md, (float*)md.geo32, (double*)md.geo64, s);
   HIPC(hipGetLastError());
   HIPC(hipStreamSynchronize(s));
@@ -629,18 +665,25 @@ static size_t case_layout(const sw_mesh* m, const sw_case_desc* d, Carver& cv, s
   auto mis_buf = cv.take<double>(2 * 3 * std::max(d->n_rec, 1) + 2);
   float* nbh = nullptr;
   float* node_mat = nullptr;
-  if (d->guess == SW_GUESS_POLY || d->guess == SW_GUESS_MLP) {
+  if (d->guess == SW_GUESS_POLY || d->guess == SW_GUESS_MLP || d->guess == SW_GUESS_PROJ_MLP) {
     nbh = cv.take<float>(4 * nd);
     node_mat = cv.take<float>(2 * nn);
   }
+  double *det_e = nullptr, *det_f = nullptr;
+  if (d->deterministic) {
+    det_e = cv.take<double>(30 * m->n_tets);
+    det_f = cv.take<double>(18 * std::max<int64_t>(m->n_faces, 1));
+  }
   double *pX = nullptr, *pY = nullptr, *ppart = nullptr, *pout = nullptr, *pth = nullptr;
-  const int L = d->guess == SW_GUESS_PROJ ? (d->proj_dim > 0 ? d->proj_dim : 6) : 0;
+  const bool proj_guess = d->guess == SW_GUESS_PROJ || d->guess == SW_GUESS_PROJ_MLP;
+  const int L = proj_guess ? (d->proj_dim > 0 ? d->proj_dim : 6) : 0;
+  const int LS = L + (d->guess == SW_GUESS_PROJ_MLP ? 1 : 0);
   if (L > 0) {
-    pX = cv.take<double>((size_t)L * nd);
-    pY = cv.take<double>((size_t)L * nd);
-    ppart = cv.take<double>((size_t)PROJ_BLOCKS * 2 * L);
-    pout = cv.take<double>(2 * L);
-    pth = cv.take<double>(L);
+    pX = cv.take<double>((size_t)LS * nd);
+    pY = cv.take<double>((size_t)LS * nd);
+    ppart = cv.take<double>((size_t)PROJ_BLOCKS * 2 * LS);
+    pout = cv.take<double>(2 * LS);
+    pth = cv.take<double>(LS);
   }
   if (c) {
     c->mats = mats;
@@ -680,7 +723,11 @@ static size_t case_layout(const sw_mesh* m, const sw_case_desc* d, Carver& cv, s
     c->mis_buf = mis_buf;
     c->nbh = nbh;
     c->node_mat = node_mat;
+    c->det = d->deterministic != 0;
+    c->det_e = det_e;
+    c->det_f = det_f;
     c->proj_dim = L;
+    c->proj_slots = LS;
     c->projX = pX;
     c->projY = pY;
     c->proj_part = ppart;
@@ -699,11 +746,20 @@ static int validate_case(const sw_mesh* m, const sw_case_desc* d) {
   if (d->precision != SW_FP64 && d->precision != SW_MIXED_FP32 && d->precision != SW_MIXED_FP32_FLEX)
     return fail(SW_EINVAL, "unknown precision %d", d->precision);
   if (d->guess != SW_GUESS_ZERO && d->guess != SW_GUESS_POLY && d->guess != SW_GUESS_MLP &&
-      d->guess != SW_GUESS_PROJ)
+      d->guess != SW_GUESS_PROJ && d->guess != SW_GUESS_PROJ_MLP)
     return fail(SW_EINVAL, "unknown guess kind %d", d->guess);
   if (d->guess == SW_GUESS_PROJ && d->proj_dim != 0 && (d->proj_dim < 2 || d->proj_dim > PROJ_MAX))
     return fail(SW_EINVAL, "proj_dim must be 0 or 2..%d", PROJ_MAX);
+  if (d->guess == SW_GUESS_PROJ_MLP && d->proj_dim != 0 && (d->proj_dim < 2 || d->proj_dim > PROJ_MAX - 1))
+    return fail(SW_EINVAL, "proj_dim must be 0 or 2..%d with the network's direction", PROJ_MAX - 1);
   if (d->poly_order < 0 || d->poly_order > 3) return fail(SW_EINVAL, "poly_order must be 0..3");
+  if (d->deterministic != 0 && d->deterministic != 1) return fail(SW_EINVAL, "deterministic must be 0 or 1");
+  if (d->deterministic) {
+    if (d->precision != SW_FP64) return fail(SW_EINVAL, "deterministic cases need SW_FP64");
+    if (d->guess != SW_GUESS_ZERO && d->guess != SW_GUESS_POLY && d->guess != SW_GUESS_PROJ)
+      return fail(SW_EINVAL, "deterministic cases take the zero, polynomial or projection guess");
+    if (!m->dev.inc) return fail(SW_EINVAL, "deterministic cases need a mesh created with deterministic = 1");
+  }
   if (!(d->inner_rtol >= 0.0 && d->inner_rtol < 1.0)) return fail(SW_EINVAL, "inner_rtol must be in [0, 1)");
   if (d->n_mat < 1 || d->n_mat > 255 || !d->mat) return fail(SW_EINVAL, "n_mat must be 1..255 with a table");
   for (int i = 0; i < d->n_mat; ++i) {
@@ -755,6 +811,8 @@ int apply_f64(sw_case* c, int op, const double* x, double* y, CgCtl* ctl, int it
   A.a1 = 1.0;
   A.xf = x;
   A.y = y;
+  A.eout = c->det_e;
+  A.fout = c->det_f;
   launch_tile_f64(c->mesh->dev, c->emat, c->mats, A, ctl, iter, s);
   LAUNCHED();
   return SW_OK;
@@ -803,6 +861,8 @@ int build_rhs(sw_case* c, double* y) {
   A.vin = c->vin + 3 * (c->step + 1);
   A.y = y;
   A.accumulate = 0;
+  A.eout = c->det_e;
+  A.fout = c->det_f;
   launch_tile_f64(c->mesh->dev, c->emat, c->mats, A, nullptr, -1, s);
   TileArgs<double> B{};
   B.sM = 0.0;
@@ -814,6 +874,8 @@ int build_rhs(sw_case* c, double* y) {
   B.a2 = -c->beta;
   B.y = y;
   B.accumulate = 1;
+  B.eout = c->det_e;
+  B.fout = c->det_f;
   launch_tile_f64(c->mesh->dev, c->emat, c->mats, B, nullptr, -1, s);
   LAUNCHED();
   return SW_OK;
@@ -898,7 +960,7 @@ extern "C" int sw_case_create(sw_ctx* ctx, sw_mesh* m, const sw_case_desc* d, vo
   // preconditioner: inverse 3x3 diagonal blocks of A
   launch_fill_f64(6 * nn, c->diag6, 0.0, s);
   HIPX(hipMemsetAsync(c->bad, 0, 4, s));
-  launch_tile_diag(m->dev, c->emat, c->mats, c->cM, c->cK, c->cC, c->diag6, s);
+  launch_tile_diag(m->dev, c->emat, c->mats, c->cM, c->cK, c->cC, c->diag6, s, c->det_e, c->det_f);
   launch_invert_blocks(nn, c->diag6, c->pinv64, c->pinv16, c->pmax, c->bad, s);
   HIPX(hipGetLastError());
   int32_t bad = 0;
@@ -906,11 +968,11 @@ extern "C" int sw_case_create(sw_ctx* ctx, sw_mesh* m, const sw_case_desc* d, vo
   HIPX(hipStreamSynchronize(s));
   if (bad) return cleanup(fail(SW_EINVAL, "a diagonal block of the step operator is not positive definite"));
   if (c->proj_dim > 0) {
-    launch_fill_f64((int64_t)c->proj_dim * nd, c->projX, 0.0, s);
-    launch_fill_f64((int64_t)c->proj_dim * nd, c->projY, 0.0, s);
+    launch_fill_f64((int64_t)c->proj_slots * nd, c->projX, 0.0, s);
+    launch_fill_f64((int64_t)c->proj_slots * nd, c->projY, 0.0, s);
     c->projG.assign((size_t)c->proj_dim * c->proj_dim, 0.0);
-    c->proj_h.assign(2 * (size_t)c->proj_dim, 0.0);
-    c->proj_th.assign(c->proj_dim, 0.0);
+    c->proj_h.assign(2 * (size_t)c->proj_slots, 0.0);
+    c->proj_th.assign(c->proj_slots, 0.0);
     c->proj_rows.assign((size_t)c->proj_dim * c->proj_dim, 0.0);
     c->proj_pend.clear();
     HIPX(hipGetLastError());
@@ -1028,7 +1090,7 @@ int cg_iteration(sw_case* c, CgCtl* ctl, int iter, int iter_abs, hipStream_t s, 
     if (prof) prof_end(cx, ev);
     if (rc) return rc;
     ev = prof ? prof_begin(cx, SW_PROF_UPDATE_F64) : -1;
-    launch_cg_update_f64(nn, iter & 1, c->pinv64, c->r, c->z, c->q, ctl, s);
+    launch_cg_update_f64(nn, iter & 1, c->pinv64, c->r, c->z, c->q, ctl, s, c->det);
     if (prof) prof_end(cx, ev);
     ev = prof ? prof_begin(cx, SW_PROF_DIR_F64) : -1;
     launch_cg_dir_f64(nn, iter & 1, iter_abs, c->max_iter, c->z, c->p, c->x, ctl, s);
@@ -1127,7 +1189,7 @@ int true_residual(sw_case* c, CgCtl* hctl, bool zero_q) {
   launch_fill_f64(1, &c->ctl64->rr_true, 0.0, s);
   int rc = apply_f64(c, SW_OP_A, c->x, c->q, nullptr, -1);
   if (rc) return rc;
-  launch_true_residual(nd, c->b, c->q, c->r, c->ctl64, s);
+  launch_true_residual(nd, c->b, c->q, c->r, c->ctl64, s, c->det);
   if (zero_q) {
     const int64_t ni3 = 3 * c->mesh->dev.n_interior;
     launch_fill_f64(nd - ni3, c->q + ni3, 0.0, s);
@@ -1147,39 +1209,65 @@ MlpFeat mlp_features(const sw_case* c) {
   return F;
 }
 
-enum { GUESS_NONE = 0, GUESS_EXTRAP = 1, GUESS_NET = 2, GUESS_PROJ = 3 };
+// GUESS_PROJ_NET: the projection with the network's correction as one more
+// direction (SW_GUESS_PROJ_MLP once the network has its four increments)
+enum { GUESS_NONE = 0, GUESS_EXTRAP = 1, GUESS_NET = 2, GUESS_PROJ = 3, GUESS_PROJ_NET = 4 };
+
+inline bool projected(int g) { return g == GUESS_PROJ || g == GUESS_PROJ_NET; }
+
+// The network's direction for GUESS_PROJ_NET: its correction w = s * y into
+// the extra slot X_L and the image A w into Y_L (one FP64 operator pass).
+int proj_net_direction(sw_case* c) {
+  hipStream_t s = c->ctx->stream;
+  const int L = c->proj_dim;
+  const int64_t nd = 3 * c->mesh->n_nodes;
+  double* Xw = c->projX + (size_t)L * nd;
+  double* Yw = c->projY + (size_t)L * nd;
+  launch_mlp_guess(mlp_features(c), c->mlp->theta, Xw, c->ctl64, true, s);
+  launch_fill_f64(nd, Yw, 0.0, s);
+  LAUNCHED();
+  return apply_f64(c, SW_OP_A, Xw, Yw, nullptr, -1);
+}
 
 // Projection guess, first half: X_i . b for the ring, copied to the host,
 // together with the Gram rows X_i . A X_s = X_i . Y_s of the slots stored
 // since the last projection (the last of them in the same pass over the
-// ring as X_i . b).
-int proj_begin(sw_case* c) {
+// ring as X_i . b).  extra: the network's direction in slot L joins, with
+// X_i . b and X_i . Y_L over all L + 1 slots in one pass (the ring's new
+// rows then each take a pass of their own).
+int proj_begin(sw_case* c, bool extra = false) {
   hipStream_t s = c->ctx->stream;
   const int L = c->proj_dim;
   const int64_t nd = 3 * c->mesh->n_nodes;
   const int np = (int)c->proj_pend.size();
-  for (int k = 0; k + 1 < np; ++k) {
+  for (int k = 0; k + (extra ? 0 : 1) < np; ++k) {
     const int p = c->proj_pend[k];
     launch_proj_dots(L, nd, c->projX, c->projY + (size_t)p * nd, nullptr, c->proj_part, c->proj_out, s);
     HIPC(hipMemcpyAsync(c->proj_rows.data() + (size_t)p * L, c->proj_out, L * sizeof(double),
                         hipMemcpyDeviceToHost, s));
   }
-  if (np > 0) {
+  int nout;
+  if (extra) {
+    launch_proj_dots2(L + 1, nd, c->projX, c->b, c->projY + (size_t)L * nd, c->proj_part, c->proj_out, s);
+    nout = 2 * (L + 1);
+  } else if (np > 0) {
     const int p = c->proj_pend[np - 1];
     launch_proj_dots2(L, nd, c->projX, c->b, c->projY + (size_t)p * nd, c->proj_part, c->proj_out, s);
+    nout = 2 * L;
   } else {
     launch_proj_dots(L, nd, c->projX, c->b, nullptr, c->proj_part, c->proj_out, s);
+    nout = L;
   }
   LAUNCHED();
-  HIPC(hipMemcpyAsync(c->proj_h.data(), c->proj_out, (np > 0 ? 2 : 1) * L * sizeof(double), hipMemcpyDeviceToHost,
-                      s));
+  HIPC(hipMemcpyAsync(c->proj_h.data(), c->proj_out, nout * sizeof(double), hipMemcpyDeviceToHost, s));
   return SW_OK;
 }
 
 // Second half (after a synchronisation): theta from the Gram matrix of the
-// filled slots, x = X theta; with_res: also r = b - Y theta and its norm in
-// ctl64->rr_true (the residual of x from the stored images).
-int proj_finish(sw_case* c, bool with_res) {
+// filled slots (and the network's direction with extra), x = X theta;
+// with_res: also r = b - Y theta and its norm in ctl64->rr_true (the
+// residual of x from the stored images).
+int proj_finish(sw_case* c, bool with_res, bool extra = false) {
   hipStream_t s = c->ctx->stream;
   const int L = c->proj_dim;
   const int64_t nd = 3 * c->mesh->n_nodes;
@@ -1188,7 +1276,7 @@ int proj_finish(sw_case* c, bool with_res) {
   const int np = (int)c->proj_pend.size();
   for (int k = 0; k < np; ++k) {
     const int p = c->proj_pend[k];
-    const double* row = k + 1 < np ? c->proj_rows.data() + (size_t)p * L : c->proj_h.data() + L;
+    const double* row = (extra || k + 1 < np) ? c->proj_rows.data() + (size_t)p * L : c->proj_h.data() + L;
     for (int i = 0; i < L; ++i) {
       c->projG[(size_t)i * L + p] = row[i];
       c->projG[(size_t)p * L + i] = row[i];
@@ -1198,23 +1286,36 @@ int proj_finish(sw_case* c, bool with_res) {
   int idx[PROJ_MAX];
   const int m = c->proj_count;
   for (int j = 0; j < m; ++j) idx[j] = ((c->proj_head - j) % L + L) % L;
+  // with extra the system gains row and column m: the network's direction
+  // (its right-hand side X_L . b and Gram entries X_i . Y_L from the pass)
+  const int M = m + (extra ? 1 : 0);
+  const int LS = L + 1;
   double Gs[PROJ_MAX * PROJ_MAX], hs[PROJ_MAX], ts[PROJ_MAX];
   for (int i = 0; i < m; ++i) {
     hs[i] = c->proj_h[idx[i]];
-    for (int j = 0; j < m; ++j) Gs[i * m + j] = c->projG[(size_t)idx[i] * L + idx[j]];
+    for (int j = 0; j < m; ++j) Gs[i * M + j] = c->projG[(size_t)idx[i] * L + idx[j]];
+  }
+  if (extra) {
+    const double* hb = c->proj_h.data();       // X_i . b, i = 0..L
+    const double* hw = c->proj_h.data() + LS;  // X_i . Y_L, i = 0..L
+    hs[m] = hb[L];
+    for (int i = 0; i < m; ++i) Gs[i * M + m] = Gs[m * M + i] = hw[idx[i]];
+    Gs[m * M + m] = hw[L];
   }
   // directions are kept down to FP64 resolution of the unit-diagonal Gram
   // matrix: the increments of a smooth march are nearly dependent, and the
   // step's new component lies in the directions of smallest energy
-  psd_solve(m, Gs, m, hs, ts, 1e-16);
+  psd_solve(M, Gs, M, hs, ts, 1e-16);
   std::fill(c->proj_th.begin(), c->proj_th.end(), 0.0);
   for (int i = 0; i < m; ++i) c->proj_th[idx[i]] = std::isfinite(ts[i]) ? ts[i] : 0.0;
-  HIPC(hipMemcpyAsync(c->proj_theta, c->proj_th.data(), L * sizeof(double), hipMemcpyHostToDevice, s));
+  if (extra) c->proj_th[L] = std::isfinite(ts[m]) ? ts[m] : 0.0;
+  const int K = extra ? LS : L;
+  HIPC(hipMemcpyAsync(c->proj_theta, c->proj_th.data(), K * sizeof(double), hipMemcpyHostToDevice, s));
   if (with_res)
-    launch_proj_combine_res(L, nd, c->projX, c->projY, c->proj_theta, c->b, c->x, c->r, c->proj_part,
+    launch_proj_combine_res(K, nd, c->projX, c->projY, c->proj_theta, c->b, c->x, c->r, c->proj_part,
                             &c->ctl64->rr_true, s);
   else
-    launch_proj_combine(L, nd, c->projX, c->proj_theta, c->x, s);
+    launch_proj_combine(K, nd, c->projX, c->proj_theta, c->x, s);
   LAUNCHED();
   return SW_OK;
 }
@@ -1240,8 +1341,10 @@ int proj_record(sw_case* c) {
 
 // Guess kind for the coming step of c.
 int guess_kind(const sw_case* c) {
+  const bool net = c->mlp && c->hist_count >= 4 && c->nb_count >= 4;
+  if (c->guess == SW_GUESS_PROJ_MLP && c->proj_count >= 2) return net ? GUESS_PROJ_NET : GUESS_PROJ;
   if (c->guess == SW_GUESS_PROJ && c->proj_count >= 2) return GUESS_PROJ;
-  if (c->guess == SW_GUESS_MLP && c->mlp && c->hist_count >= 4 && c->nb_count >= 4) return GUESS_NET;
+  if (c->guess == SW_GUESS_MLP && net) return GUESS_NET;
   if (c->guess != SW_GUESS_ZERO && c->hist_count > 0) return GUESS_EXTRAP;
   return GUESS_NONE;
 }
@@ -1251,14 +1354,16 @@ int guess_kind(const sw_case* c) {
 int set_guess(sw_case* c, int g, bool with_res = false) {
   hipStream_t s = c->ctx->stream;
   const int64_t nd = 3 * c->mesh->n_nodes;
-  if (g == GUESS_PROJ) {
-    int rc = proj_begin(c);
+  if (projected(g)) {
+    const bool extra = g == GUESS_PROJ_NET;
+    int rc = extra ? proj_net_direction(c) : SW_OK;
+    if (!rc) rc = proj_begin(c, extra);
     if (rc) return rc;
     HIPC(hipStreamSynchronize(s));
-    return proj_finish(c, with_res);
+    return proj_finish(c, with_res, extra);
   }
   if (g == GUESS_NET) {
-    launch_mlp_guess(mlp_features(c), c->mlp->theta, c->x, c->ctl64, s);
+    launch_mlp_guess(mlp_features(c), c->mlp->theta, c->x, c->ctl64, false, s);
   } else if (g == GUESS_EXTRAP) {
     const int order = std::min(c->poly_order, c->hist_count - 1);
     launch_guess_poly(nd, c->hist, c->hist_head, order, c->x, c->ctl64, s);
@@ -1278,7 +1383,7 @@ int solve_step(sw_case* c, int* iters, int* outer, double* relres, int* flags) {
   int rc = build_rhs(c, c->b);
   if (rc) return rc;
   launch_fill_f64(1, &c->ctl64->bb, 0.0, s);
-  launch_norm2(nd, c->b, &c->ctl64->bb, s);
+  launch_norm2(nd, c->b, &c->ctl64->bb, s, c->det);
   launch_ctl_prepare(c->ctl64, c->rtol, s);
   // guess: the projection needs two past increments, the network four and
   // their neighbour means, extrapolation one; otherwise zero
@@ -1291,12 +1396,12 @@ int solve_step(sw_case* c, int* iters, int* outer, double* relres, int* flags) {
       if (g != GUESS_NONE) {
         rc = apply_f64(c, SW_OP_A, c->x, c->q, nullptr, -1);
         if (rc) return rc;
-        launch_cg_init_f64(nn, c->b, c->q, c->pinv64, c->r, c->z, c->p, c->q, c->ctl64, s);
+        launch_cg_init_f64(nn, c->b, c->q, c->pinv64, c->r, c->z, c->p, c->q, c->ctl64, s, c->det);
       } else {
-        launch_cg_init_f64(nn, c->b, nullptr, c->pinv64, c->r, c->z, c->p, nullptr, c->ctl64, s);
+        launch_cg_init_f64(nn, c->b, nullptr, c->pinv64, c->r, c->z, c->p, nullptr, c->ctl64, s, c->det);
       }
       LAUNCHED();
-      if ((g != GUESS_NET && g != GUESS_PROJ) || attempt > 0) break;
+      if ((g != GUESS_NET && !projected(g)) || attempt > 0) break;
       // reject a learned or projected guess whose residual exceeds that of
       // the zero guess
       rc = read_ctl(c, c->ctl64, &h);
@@ -1335,7 +1440,7 @@ int solve_step(sw_case* c, int* iters, int* outer, double* relres, int* flags) {
       }
       // restart CG from the current iterate on the true residual b - A x
       launch_ctl_prepare(c->ctl64, c->rtol, s);
-      launch_cg_init_f64(nn, c->b, c->q, c->pinv64, c->r, c->z, c->p, c->q, c->ctl64, s);
+      launch_cg_init_f64(nn, c->b, c->q, c->pinv64, c->r, c->z, c->p, c->q, c->ctl64, s, c->det);
       LAUNCHED();
     }
   } else {
@@ -1352,7 +1457,7 @@ int solve_step(sw_case* c, int* iters, int* outer, double* relres, int* flags) {
     int inner_est = std::max(1, c->last_iters / 2);
     bool first = true;
     // a projected guess comes with its residual from the stored images
-    bool image_res = g == GUESS_PROJ;
+    bool image_res = projected(g);
     bool recursive = false;  // residual from the flexible recurrence
     int k = 0;               // flexible iterations since the last true residual
     for (;;) {
@@ -1368,7 +1473,7 @@ int solve_step(sw_case* c, int* iters, int* outer, double* relres, int* flags) {
       }
       if (rc) return rc;
       ++*outer;
-      if (first && (g == GUESS_NET || g == GUESS_PROJ) && !(h.rr_true <= h.bb)) {
+      if (first && (g == GUESS_NET || projected(g)) && !(h.rr_true <= h.bb)) {
         // reject a learned or projected guess whose residual exceeds that of
         // the zero guess
         *flags |= SW_FLAG_GUESS_FALLBACK;
@@ -1440,7 +1545,7 @@ extern "C" int sw_case_step(sw_case* c, int32_t n) {
   if (c->step + n > c->n_steps)
     return fail(SW_ESTATE, "stepping to %lld exceeds the case capacity of %lld steps", (long long)(c->step + n),
                 (long long)c->n_steps);
-  if (c->guess == SW_GUESS_MLP && !c->mlp) return fail(SW_ESTATE, "SW_GUESS_MLP needs sw_case_attach_mlp first");
+  if (needs_mlp(c)) return fail(SW_ESTATE, "SW_GUESS_MLP and SW_GUESS_PROJ_MLP need sw_case_attach_mlp first");
   HIPC(hipSetDevice(c->ctx->device));
   hipStream_t s = c->ctx->stream;
   const int64_t nd = 3 * c->mesh->n_nodes;
@@ -1465,7 +1570,7 @@ extern "C" int sw_case_step(sw_case* c, int32_t n) {
     LAUNCHED();
     c->hist_head = head;
     c->hist_count = std::min(c->hist_count + 1, 4);
-    if (c->nbh && (c->guess == SW_GUESS_MLP || c->samp)) {
+    if (c->nbh && (learned(c) || c->samp)) {
       const int nh = (c->nb_head + 1) & 3;
       launch_fill_f32(nd, c->nbh + nh * nd, 0.0f, s);
       launch_neighbour_mean(c->mesh->dev, c->hist + head * nd, c->nbh + nh * nd, s);
@@ -1583,14 +1688,14 @@ extern "C" int sw_case_rhs(sw_case* c, double* y) {
 extern "C" int sw_case_guess(sw_case* c, double* y) {
   if (!c || !y) return fail(SW_EINVAL, "NULL argument");
   if (c->step >= c->n_steps) return fail(SW_ESTATE, "no further step in the case capacity");
-  if (c->guess == SW_GUESS_MLP && !c->mlp) return fail(SW_ESTATE, "SW_GUESS_MLP needs sw_case_attach_mlp first");
+  if (needs_mlp(c)) return fail(SW_ESTATE, "SW_GUESS_MLP and SW_GUESS_PROJ_MLP need sw_case_attach_mlp first");
   HIPC(hipSetDevice(c->ctx->device));
   hipStream_t s = c->ctx->stream;
   const int64_t nd = 3 * c->mesh->n_nodes;
   int rc = build_rhs(c, c->b);
   if (rc) return rc;
   launch_fill_f64(1, &c->ctl64->bb, 0.0, s);
-  launch_norm2(nd, c->b, &c->ctl64->bb, s);
+  launch_norm2(nd, c->b, &c->ctl64->bb, s, c->det);
   rc = set_guess(c, guess_kind(c));
   if (rc) return rc;
   launch_permute_f64(c->mesh->n_nodes, 3, c->x, c->mesh->dev.node_u2i, y, s);
@@ -2002,7 +2107,7 @@ extern "C" int sw_case_set_sampler(sw_case* c, float* buf, int64_t capacity, int
   if (!c) return fail(SW_EINVAL, "NULL case");
   if (buf && (capacity <= 0 || per_step <= 0 || per_step > capacity)) return fail(SW_EINVAL, "bad sampler sizes");
   if (buf && !c->nbh) return fail(SW_ESTATE, "the case was created with the zero guess (no feature buffers)");
-  if (buf && c->nb_count < 4 && c->step > 0 && c->guess != SW_GUESS_MLP)
+  if (buf && c->nb_count < 4 && c->step > 0 && !learned(c))
     c->nb_count = 0;  // neighbour means start accumulating now
   c->samp = buf;
   c->samp_cap = capacity;
@@ -2183,7 +2288,7 @@ int batch_step_once(sw_batch* b) {
     LaneDev& L = b->lanes[l];
     L.step = c->step;
     L.hist_head = c->hist_head;
-    L.guess_order = (g[l] == GUESS_NET || g[l] == GUESS_PROJ)
+    L.guess_order = (g[l] == GUESS_NET || projected(g[l]))
                         ? -2
                         : (g[l] == GUESS_EXTRAP ? std::min(c->poly_order, c->hist_count - 1) : -1);
     b->rhs1[l].A.vin = c->vin + 3 * (c->step + 1);
@@ -2203,8 +2308,10 @@ int batch_step_once(sw_batch* b) {
   bool any_proj = false;
   for (int l = 0; l < n; ++l) {
     if (g[l] == GUESS_NET && (rc = set_guess(b->cases[l], GUESS_NET))) return rc;
-    if (g[l] == GUESS_PROJ) {
-      if ((rc = proj_begin(b->cases[l]))) return rc;
+    if (projected(g[l])) {
+      const bool extra = g[l] == GUESS_PROJ_NET;
+      if (extra && (rc = proj_net_direction(b->cases[l]))) return rc;
+      if ((rc = proj_begin(b->cases[l], extra))) return rc;
       any_proj = true;
     }
   }
@@ -2213,8 +2320,8 @@ int batch_step_once(sw_batch* b) {
   if (any_proj) {
     HIPC(hipStreamSynchronize(s));
     for (int l = 0; l < n; ++l)
-      if (g[l] == GUESS_PROJ) {
-        if ((rc = proj_finish(b->cases[l], true))) return rc;
+      if (projected(g[l])) {
+        if ((rc = proj_finish(b->cases[l], true, g[l] == GUESS_PROJ_NET))) return rc;
         image_res[l] = 1;
       }
   }
@@ -2243,7 +2350,7 @@ int batch_step_once(sw_batch* b) {
       image_res[l] = 0;
       ++outer[l];
       S.active = 0;
-      if (first[l] && (g[l] == GUESS_NET || g[l] == GUESS_PROJ) && !(h.rr_true <= h.bb)) {
+      if (first[l] && (g[l] == GUESS_NET || projected(g[l])) && !(h.rr_true <= h.bb)) {
         // reject a learned or projected guess whose residual exceeds that of
         // the zero guess; the lane's true residual is taken again next round
         flags[l] |= SW_FLAG_GUESS_FALLBACK;
@@ -2342,7 +2449,7 @@ int batch_step_once(sw_batch* b) {
     const int head = (c->hist_head + 1) & 3;
     c->hist_head = head;
     c->hist_count = std::min(c->hist_count + 1, 4);
-    if (c->nbh && (c->guess == SW_GUESS_MLP || c->samp)) {
+    if (c->nbh && (learned(c) || c->samp)) {
       const int nh = (c->nb_head + 1) & 3;
       launch_fill_f32(nd, c->nbh + nh * nd, 0.0f, s);
       launch_neighbour_mean(c->mesh->dev, c->hist + head * nd, c->nbh + nh * nd, s);
@@ -2651,7 +2758,7 @@ extern "C" int sw_batch_step(sw_batch* b, int32_t n_steps) {
   if (n_steps < 0) return fail(SW_EINVAL, "negative step count");
   for (sw_case* c : b->cases) {
     if (c->step + n_steps > c->n_steps) return fail(SW_ESTATE, "a case would exceed its step capacity");
-    if (c->guess == SW_GUESS_MLP && !c->mlp) return fail(SW_ESTATE, "SW_GUESS_MLP needs sw_case_attach_mlp first");
+    if (needs_mlp(c)) return fail(SW_ESTATE, "SW_GUESS_MLP and SW_GUESS_PROJ_MLP need sw_case_attach_mlp first");
   }
   HIPC(hipSetDevice(b->ctx->device));
   for (int k = 0; k < n_steps; ++k) {

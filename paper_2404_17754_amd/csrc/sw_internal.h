@@ -62,6 +62,13 @@ struct MeshDev {
   const int32_t* node_u2i;       // [n_nodes]
   const int32_t* node_i2u;       // [n_nodes]
   const float* inv_valence;      // [n_nodes] 1 / number of elements containing the node
+  // deterministic passes (null unless the mesh was created for them): per
+  // node, the element slots e * 10 + k and face slots f * 6 + k touching it,
+  // in increasing order
+  const int32_t* inc_off;        // [n_nodes + 1]
+  const int32_t* inc;
+  const int32_t* finc_off;       // [n_nodes + 1]
+  const int32_t* finc;
 };
 
 // One tiled operator pass:
@@ -79,6 +86,11 @@ struct TileArgs {
   T* y;
   int accumulate;      // interior nodes: 0 overwrite, 1 add
   int n_mat;           // materials in the table (0: not given)
+  // deterministic FP64 passes: each element's 10 x 3 results and each
+  // face's 6 x 3 go here (slot-major), then every node sums its slots in
+  // increasing order (null: LDS and global atomics, arrival order)
+  double* eout;
+  double* fout;
 };
 
 // ---- several cases marched together (lanes) ------------------------------
@@ -166,6 +178,9 @@ void launch_lanes_cg(bool f32, bool dir, int n_lanes, int64_t max_nodes, const L
 
 // Launches (sw_kernels.hip).  iter >= 0: CG iteration `iter` of the solve in
 // ctl (early exit when done, p.Ap accumulated into ctl); iter < 0: plain.
+// With a.eout set: the deterministic form (element and face results to
+// a.eout / a.fout, a node pass summing them in slot order, p.Ap from a
+// fixed-order dot product; the mesh needs its incidence lists).
 void launch_tile_f64(const MeshDev& m, const uint8_t* emat, const MatDev* mats, const TileArgs<double>& a,
                      CgCtl* ctl, int iter, hipStream_t s);
 // grid_cap > 0 limits the workgroups of the persistent FP32 pass (a multiple
@@ -175,24 +190,28 @@ void launch_tile_f32(const MeshDev& m, const uint8_t* emat, const MatDev* mats, 
 // FP32 element geometry for the FP32 operator (once per mesh).
 void launch_geom(const MeshDev& m, float* geo32, double* geo64, hipStream_t s);
 // Diagonal 3x3 blocks (6 values per node) of cM M + cK K + cC C_abs.
+// eout / fout set: the deterministic form (two passes of three values per
+// node through the slot buffers, as launch_tile_f64).
 void launch_tile_diag(const MeshDev& m, const uint8_t* emat, const MatDev* mats, double cM, double cK, double cC,
-                      double* diag6, hipStream_t s);
+                      double* diag6, hipStream_t s, double* eout = nullptr, double* fout = nullptr);
 // pinv64 = inverse blocks; pinv16 = the same divided by their largest
 // diagonal entry (pmax, one double of scratch), in FP16 for the FP32 CG (a
 // constant factor on the preconditioner leaves the CG iterates unchanged)
 void launch_invert_blocks(int64_t n_nodes, const double* diag6, double* pinv64, __half* pinv16, double* pmax,
                           int* bad, hipStream_t s);
 
-// CG vector kernels (node-parallel), T = double or float vectors
+// CG vector kernels (node-parallel), T = double or float vectors.  det: one
+// workgroup per scalar slot, so that each slot receives one workgroup's sum
+// (a fixed-order reduction; fewer workgroups than the default grid).
 void launch_cg_init_f64(int64_t n_nodes, const double* b, const double* q, const double* pinv, double* r, double* z,
-                        double* p, double* qz, CgCtl* ctl, hipStream_t s);
+                        double* p, double* qz, CgCtl* ctl, hipStream_t s, bool det = false);
 void launch_cg_init_f32(int64_t n_nodes, const float* b, const float* q, const __half* pinv, float* r, float* z,
                         float* p, float* qz, CgCtl* ctl, hipStream_t s);
 // update: r -= alpha q, z = P r, dot products; direction: x += alpha p,
 // then p = z + beta p unless the solve stops (each iteration launches the
 // update, then the direction kernel)
 void launch_cg_update_f64(int64_t n_nodes, int par, const double* pinv, double* r, double* z, double* q, CgCtl* ctl,
-                          hipStream_t s);
+                          hipStream_t s, bool det = false);
 // q is cleared only for nodes >= n_interior (the next operator pass
 // overwrites interior nodes)
 void launch_cg_update_f32(int64_t n_nodes, int64_t n_interior, int par, const __half* pinv, float* r, float* z,
@@ -204,10 +223,12 @@ void launch_cg_dir_f32(int64_t n_nodes, int par, int iter_abs, int max_iter, con
 
 // ctl setup: bb must already be in ctl; sets tol2 = rtol^2 bb, clears the rest
 void launch_ctl_prepare(CgCtl* ctl, double rtol, hipStream_t s);
-void launch_norm2(int64_t n, const double* x, double* out, hipStream_t s);
+// *out += x.x (det: one workgroup, a fixed-order sum)
+void launch_norm2(int64_t n, const double* x, double* out, hipStream_t s, bool det = false);
 
-// r = b - q, rr_true -> ctl
-void launch_true_residual(int64_t n, const double* b, const double* q, double* r, CgCtl* ctl, hipStream_t s);
+// r = b - q, rr_true -> ctl (det: one workgroup)
+void launch_true_residual(int64_t n, const double* b, const double* q, double* r, CgCtl* ctl, hipStream_t s,
+                          bool det = false);
 // r32 = r64 / ||r64|| (||r64|| from ctl->rr_true, kept in ctl->scale)
 void launch_ir_begin(int64_t n_nodes, const double* r64, const __half* P, float* r32, float* z32, float* p32,
                      float* d32, CgCtl* ctl64, CgCtl* ctl32, hipStream_t s);
@@ -258,7 +279,7 @@ struct MlpFeat {
 };
 
 void launch_mlp_forward(int64_t n, const float* X, const float* theta, float* y, hipStream_t s);
-void launch_mlp_guess(const MlpFeat& F, const float* theta, double* x, const CgCtl* ctl, hipStream_t s);
+void launch_mlp_guess(const MlpFeat& F, const float* theta, double* x, const CgCtl* ctl, bool corr, hipStream_t s);
 void launch_mlp_collect(const MlpFeat& F, const double* du, int count, uint64_t seed, int64_t step, int64_t row0,
                         int64_t capacity, float* out, hipStream_t s);
 void launch_mlp_grad(const float* S, int64_t n, int64_t nb, uint64_t seed, int64_t batch, const float* theta,

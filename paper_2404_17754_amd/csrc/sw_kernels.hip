@@ -230,17 +230,18 @@ __global__ __launch_bounds__(TPB) void k_cg_dir(int64_t n, int par, int iter_abs
 }
 
 void launch_cg_init_f64(int64_t n, const double* b, const double* q, const double* P, double* r, double* z, double* p,
-                        double* qz, CgCtl* ctl, hipStream_t s) {
-  hipLaunchKernelGGL((k_cg_init<double, double>), dim3(vgrid(n)), dim3(TPB), 0, s, n, b, q, P, r, z, p, qz, ctl);
+                        double* qz, CgCtl* ctl, hipStream_t s, bool det) {
+  hipLaunchKernelGGL((k_cg_init<double, double>), dim3(det ? NSLOT : vgrid(n)), dim3(TPB), 0, s, n, b, q, P, r, z, p,
+                     qz, ctl);
 }
 void launch_cg_init_f32(int64_t n, const float* b, const float* q, const __half* P, float* r, float* z, float* p,
                         float* qz, CgCtl* ctl, hipStream_t s) {
   hipLaunchKernelGGL((k_cg_init<float, __half>), dim3(vgrid(n)), dim3(TPB), 0, s, n, b, q, P, r, z, p, qz, ctl);
 }
 void launch_cg_update_f64(int64_t n, int par, const double* P, double* r, double* z, double* q, CgCtl* ctl,
-                          hipStream_t s) {
-  hipLaunchKernelGGL((k_cg_update<double, double>), dim3(vgrid(n)), dim3(TPB), 0, s, n, (int64_t)0, par, P, r, z, q,
-                     ctl);
+                          hipStream_t s, bool det) {
+  hipLaunchKernelGGL((k_cg_update<double, double>), dim3(det ? NSLOT : vgrid(n)), dim3(TPB), 0, s, n, (int64_t)0, par,
+                     P, r, z, q, ctl);
 }
 void launch_cg_update_f32(int64_t n, int64_t n_int, int par, const __half* P, float* r, float* z, float* q,
                           CgCtl* ctl, hipStream_t s) {
@@ -283,9 +284,10 @@ __global__ __launch_bounds__(TPB) void k_norm2(int64_t n, const double* __restri
   acc = block_sum(acc, sh);
   if (threadIdx.x == 0) atomic_add(out, acc);
 }
-void launch_norm2(int64_t n, const double* x, double* out, hipStream_t s) {
+void launch_norm2(int64_t n, const double* x, double* out, hipStream_t s, bool det) {
   unsigned g = nblocks(n);
   if (g > 4096) g = 4096;
+  if (det || g == 0) g = 1;
   hipLaunchKernelGGL(k_norm2, dim3(g), dim3(TPB), 0, s, n, x, out);
 }
 
@@ -302,9 +304,11 @@ __global__ __launch_bounds__(TPB) void k_true_res(int64_t n, const double* __res
   acc = block_sum(acc, sh);
   if (threadIdx.x == 0) atomic_add(&ctl->rr_true, acc);
 }
-void launch_true_residual(int64_t n, const double* b, const double* q, double* r, CgCtl* ctl, hipStream_t s) {
+void launch_true_residual(int64_t n, const double* b, const double* q, double* r, CgCtl* ctl, hipStream_t s,
+                          bool det) {
   unsigned g = nblocks(n);
   if (g > 8192) g = 8192;
+  if (det || g == 0) g = 1;
   hipLaunchKernelGGL(k_true_res, dim3(g), dim3(TPB), 0, s, n, b, q, r, ctl);
 }
 

@@ -42,6 +42,16 @@ struct HostLayout {
   std::vector<float> inv_valence;      // [n_nodes] 1 / elements containing the node (0 if none)
 };
 
+// Per node, the element slots (internal element e's node k: e * 10 + k) and
+// face slots (f * 6 + k) that touch it, each list in increasing order: a
+// node sums the contributions in this fixed order in deterministic passes.
+struct Incidence {
+  std::vector<int32_t> elem_off, elem;  // [n_nodes + 1], [10 n_tets]
+  std::vector<int32_t> face_off, face;  // [n_nodes + 1], [6 n_faces]
+};
+
+void build_incidence(const HostLayout& L, Incidence& I);
+
 // Tiles close at max_nodes distinct nodes or max_elems elements (at most
 // TILE_MAX_NODES / TILE_MAX_ELEMS; smaller tiles are a tuning and test knob).
 void build_layout(int64_t n_nodes, int64_t n_tets, int64_t n_faces, const double* xyz, const int32_t* tet10,

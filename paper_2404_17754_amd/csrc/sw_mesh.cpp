@@ -240,4 +240,32 @@ void build_layout(int64_t n_nodes, int64_t n_tets, int64_t n_faces, const double
   }
 }
 
+void build_incidence(const HostLayout& L, Incidence& I) {
+  const int64_t nn = L.n_nodes;
+  // element slots: slot e * 10 + k of internal element e's node k
+  I.elem_off.assign(nn + 1, 0);
+  auto node_of = [&](int32_t t, int64_t e, int k) {
+    return L.tile_nodes[L.tile_node_off[t] + L.conn_loc[k * (size_t)L.tet_stride + e] / 3];
+  };
+  for (int32_t t = 0; t < L.n_tiles; ++t)
+    for (int64_t e = L.tile_elem_off[t]; e < L.tile_elem_off[t + 1]; ++e)
+      for (int k = 0; k < 10; ++k) ++I.elem_off[node_of(t, e, k) + 1];
+  for (int64_t i = 0; i < nn; ++i) I.elem_off[i + 1] += I.elem_off[i];
+  I.elem.assign(I.elem_off[nn], 0);
+  std::vector<int32_t> pos(I.elem_off.begin(), I.elem_off.end() - 1);
+  // elements in increasing order, so every node's list is sorted
+  for (int32_t t = 0; t < L.n_tiles; ++t)
+    for (int64_t e = L.tile_elem_off[t]; e < L.tile_elem_off[t + 1]; ++e)
+      for (int k = 0; k < 10; ++k) I.elem[pos[node_of(t, e, k)]++] = (int32_t)(e * 10 + k);
+  // face slots: f * 6 + k
+  I.face_off.assign(nn + 1, 0);
+  for (int64_t f = 0; f < L.n_faces; ++f)
+    for (int k = 0; k < 6; ++k) ++I.face_off[L.fconn[k * (size_t)L.face_stride + f] + 1];
+  for (int64_t i = 0; i < nn; ++i) I.face_off[i + 1] += I.face_off[i];
+  I.face.assign(std::max<int32_t>(I.face_off[nn], 1), 0);
+  pos.assign(I.face_off.begin(), I.face_off.end() - 1);
+  for (int64_t f = 0; f < L.n_faces; ++f)
+    for (int k = 0; k < 6; ++k) I.face[pos[L.fconn[k * (size_t)L.face_stride + f]]++] = (int32_t)(f * 6 + k);
+}
+
 }  // namespace sw

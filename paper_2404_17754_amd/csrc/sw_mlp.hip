@@ -176,9 +176,10 @@ __device__ __forceinline__ half4 feat_quartet(const GuessIn& g, double s, int q)
   return x;
 }
 
-// x = p2 + s * net(features) per DOF; x = 0 when ||b|| = 0 or s = 0
+// x = p2 + s * net(features) per DOF (corr: the correction s * net alone);
+// x = 0 when ||b|| = 0 or s = 0
 __global__ __launch_bounds__(TPB) void k_mlp_guess(MlpFeat F, const float* __restrict__ theta,
-                                                   double* __restrict__ x, const CgCtl* ctl) {
+                                                   double* __restrict__ x, const CgCtl* ctl, int corr) {
   MlpRegs R;
   mlp_load(theta, R);
   const bool zero = !(ctl->bb > 0.0);
@@ -192,16 +193,16 @@ __global__ __launch_bounds__(TPB) void k_mlp_guess(MlpFeat F, const float* __res
     const double s = feat_scale(in);
     const float y = mlp_eval16(feat_quartet(in, s, q), R);
     if (q == 0 && dof < F.n_dof) {
-      const double p2 = 3.0 * in.d[0] - 3.0 * in.d[1] + in.d[2];
+      const double p2 = corr ? 0.0 : 3.0 * in.d[0] - 3.0 * in.d[1] + in.d[2];
       x[dof] = (zero || !(s > 0.0)) ? 0.0 : p2 + s * (double)y;
     }
   }
 }
 
-void launch_mlp_guess(const MlpFeat& F, const float* theta, double* x, const CgCtl* ctl, hipStream_t s) {
+void launch_mlp_guess(const MlpFeat& F, const float* theta, double* x, const CgCtl* ctl, bool corr, hipStream_t s) {
   unsigned g = (unsigned)((F.n_dof / 16 + 3) / 4 + 1);
   if (g > 8192) g = 8192;
-  hipLaunchKernelGGL(k_mlp_guess, dim3(g), dim3(TPB), 0, s, F, theta, x, ctl);
+  hipLaunchKernelGGL(k_mlp_guess, dim3(g), dim3(TPB), 0, s, F, theta, x, ctl, corr ? 1 : 0);
 }
 
 // Counter-based sampling: SplitMix64 finaliser of (seed, step, j).

@@ -91,8 +91,9 @@ __device__ __forceinline__ void elem_geometry(const ElemIn<T>& in, Geo<T>& G) {
 // pipelined pass issues its next tile's gather there, behind them).  MATL:
 // the material constants come from an LDS copy (matl: lam, mu, rho per
 // material) rather than from global memory, a load that would wait on the
-// element's material id.
-template <typename T, int NT, bool PF, bool STIFF, bool MASS, bool DYN, bool MATL, typename Hook>
+// element's material id.  DET: each element's ten nodal results go to its
+// slots of A.eout instead of the LDS accumulator (no energy).
+template <typename T, int NT, bool PF, bool STIFF, bool MASS, bool DYN, bool MATL, bool DET, typename Hook>
 __device__ __forceinline__ double tile_element_loop(const MeshDev& m, const uint8_t* __restrict__ emat,
                                                     const MatDev* __restrict__ mats, const float* matl,
                                                     const TileArgs<T>& A, int t, const int32_t* gid, const T* xs,
@@ -135,11 +136,18 @@ __device__ __forceinline__ double tile_element_loop(const MeshDev& m, const uint
     T eloc = (T)0;
     element_apply<T, STIFF, MASS, DYN>(G, lam, mu, A.sK, A.sM * rho * G.vol, w,
                                   [&](int k, T f0, T f1, T f2) {
-                                    double* yk = &ys[ln[k]];
-                                    atomicAdd(yk, (double)f0);
-                                    atomicAdd(yk + 1, (double)f1);
-                                    atomicAdd(yk + 2, (double)f2);
-                                    eloc += w[k][0] * f0 + w[k][1] * f1 + w[k][2] * f2;
+                                    if constexpr (DET) {
+                                      double* eo = A.eout + (size_t)elem_of(i) * 30 + 3 * k;
+                                      eo[0] = (double)f0;
+                                      eo[1] = (double)f1;
+                                      eo[2] = (double)f2;
+                                    } else {
+                                      double* yk = &ys[ln[k]];
+                                      atomicAdd(yk, (double)f0);
+                                      atomicAdd(yk + 1, (double)f1);
+                                      atomicAdd(yk + 2, (double)f2);
+                                      eloc += w[k][0] * f0 + w[k][1] * f1 + w[k][2] * f2;
+                                    }
                                   });
     energy += (double)eloc;
   }
@@ -147,8 +155,9 @@ __device__ __forceinline__ double tile_element_loop(const MeshDev& m, const uint
 }
 
 // Element and face work of tile t (see tile_element_loop), plus the
-// boundary faces owned by the tile's elements.
-template <typename T, int NT, bool PF, bool MATL, typename Hook>
+// boundary faces owned by the tile's elements (DET: their results to the
+// face slots of A.fout).
+template <typename T, int NT, bool PF, bool MATL, bool DET, typename Hook>
 __device__ __forceinline__ double tile_elements(const MeshDev& m, const uint8_t* __restrict__ emat,
                                                 const MatDev* __restrict__ mats, const float* matl,
                                                 const TileArgs<T>& A, int t, const int32_t* gid, const T* xs,
@@ -158,16 +167,20 @@ __device__ __forceinline__ double tile_elements(const MeshDev& m, const uint8_t*
     // FP64: per-element checks (the branch-free form needs more registers
     // than the FP64 passes can spare; measured slower)
     if (A.sK != (T)0 || A.sM != (T)0)
-      energy = tile_element_loop<T, NT, PF, true, true, true, MATL>(m, emat, mats, matl, A, t, gid, xs, ys, hook);
+      energy = tile_element_loop<T, NT, PF, true, true, true, MATL, DET>(m, emat, mats, matl, A, t, gid, xs, ys,
+                                                                        hook);
     else
       hook();
   } else {
     if (A.sK != (T)0 && A.sM != (T)0)
-      energy = tile_element_loop<T, NT, PF, true, true, false, MATL>(m, emat, mats, matl, A, t, gid, xs, ys, hook);
+      energy = tile_element_loop<T, NT, PF, true, true, false, MATL, false>(m, emat, mats, matl, A, t, gid, xs, ys,
+                                                                           hook);
     else if (A.sK != (T)0)
-      energy = tile_element_loop<T, NT, PF, true, false, false, MATL>(m, emat, mats, matl, A, t, gid, xs, ys, hook);
+      energy = tile_element_loop<T, NT, PF, true, false, false, MATL, false>(m, emat, mats, matl, A, t, gid, xs, ys,
+                                                                            hook);
     else if (A.sM != (T)0)
-      energy = tile_element_loop<T, NT, PF, false, true, false, MATL>(m, emat, mats, matl, A, t, gid, xs, ys, hook);
+      energy = tile_element_loop<T, NT, PF, false, true, false, MATL, false>(m, emat, mats, matl, A, t, gid, xs, ys,
+                                                                            hook);
     else
       hook();
   }
@@ -219,10 +232,19 @@ __device__ __forceinline__ double tile_elements(const MeshDev& m, const uint8_t*
           out[5][c] += f3;
         }
       }
+      if constexpr (DET) {
+        double* fo = A.fout + (size_t)f * 18;
 #pragma unroll
-      for (int k = 0; k < 6; ++k) {
+        for (int k = 0; k < 6; ++k) {
 #pragma unroll
-        for (int c = 0; c < 3; ++c) atomicAdd(&ys[3 * ln[k] + c], (double)out[k][c]);
+          for (int c = 0; c < 3; ++c) fo[3 * k + c] = (double)out[k][c];
+        }
+      } else {
+#pragma unroll
+        for (int k = 0; k < 6; ++k) {
+#pragma unroll
+          for (int c = 0; c < 3; ++c) atomicAdd(&ys[3 * ln[k] + c], (double)out[k][c]);
+        }
       }
     }
   }
@@ -233,7 +255,7 @@ template <typename T, int NT, bool PF>
 __device__ __forceinline__ double tile_elements(const MeshDev& m, const uint8_t* __restrict__ emat,
                                                 const MatDev* __restrict__ mats, const TileArgs<T>& A, int t,
                                                 const int32_t* gid, const T* xs, double* ys) {
-  return tile_elements<T, NT, PF, false>(m, emat, mats, nullptr, A, t, gid, xs, ys, [] {});
+  return tile_elements<T, NT, PF, false, false>(m, emat, mats, nullptr, A, t, gid, xs, ys, [] {});
 }
 
 // Results of tile t: interior nodes (one contiguous range) with plain
@@ -259,8 +281,10 @@ __device__ __forceinline__ void tile_scatter(const MeshDev& m, const TileArgs<T>
 }
 
 // One workgroup's share of an operator pass: tile t of mesh m.  smem_raw is
-// the dynamic LDS (sized for m.max_tile_nodes), sh NT/64 doubles.
-template <typename T, int NT>
+// the dynamic LDS (sized for m.max_tile_nodes), sh NT/64 doubles.  DET: the
+// element and face results go to their slots (no scatter, no energy; the
+// node pass and a fixed-order dot product follow).
+template <typename T, int NT, bool DET = false>
 __device__ __forceinline__ void tile_body(const MeshDev& m, const uint8_t* __restrict__ emat,
                                           const MatDev* __restrict__ mats, const TileArgs<T>& A, CgCtl* ctl,
                                           int iter, int t, unsigned char* smem_raw, double* sh) {
@@ -316,7 +340,9 @@ __device__ __forceinline__ void tile_body(const MeshDev& m, const uint8_t* __res
     }
     __syncthreads();
   };
-  double energy = tile_elements<T, NT, sizeof(T) == 4, false>(m, emat, mats, nullptr, A, t, gid, xs, ys, gather);
+  double energy =
+      tile_elements<T, NT, sizeof(T) == 4, false, DET>(m, emat, mats, nullptr, A, t, gid, xs, ys, gather);
+  if constexpr (DET) return;
   __syncthreads();
   tile_scatter<T, NT>(m, A, t, gid, ys);
   if (iter >= 0) {
@@ -325,12 +351,56 @@ __device__ __forceinline__ void tile_body(const MeshDev& m, const uint8_t* __res
   }
 }
 
-template <typename T, int NT>
+template <typename T, int NT, bool DET = false>
 __global__ __launch_bounds__(NT) void k_tile(MeshDev m, const uint8_t* __restrict__ emat,
                                               const MatDev* __restrict__ mats, TileArgs<T> A, CgCtl* ctl, int iter) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   __shared__ double sh[NT / 64];
-  tile_body<T, NT>(m, emat, mats, A, ctl, iter, blockIdx.x, smem_raw, sh);
+  tile_body<T, NT, DET>(m, emat, mats, A, ctl, iter, blockIdx.x, smem_raw, sh);
+}
+
+// Deterministic node pass: y[ystride * i + yoff + c] (= or +=) the sum over
+// node i's element slots, then its face slots, in increasing slot order
+// (elems / faces: whether the pass wrote them).  A CG iteration (iter >= 0)
+// whose solve is done does nothing.
+__global__ __launch_bounds__(TPB) void k_node_gather(MeshDev m, const double* __restrict__ eout,
+                                                     const double* __restrict__ fout, double* __restrict__ y,
+                                                     int ystride, int yoff, int accumulate, int elems, int faces,
+                                                     const CgCtl* ctl, int iter) {
+  if (iter >= 0 && ctl->done) return;
+  for (int64_t i = (int64_t)blockIdx.x * TPB + threadIdx.x; i < m.n_nodes; i += (int64_t)gridDim.x * TPB) {
+    double a[3] = {0.0, 0.0, 0.0};
+    if (elems)
+      for (int j = m.inc_off[i]; j < m.inc_off[i + 1]; ++j) {
+        const double* e = eout + 3 * (size_t)m.inc[j];
+        a[0] += e[0];
+        a[1] += e[1];
+        a[2] += e[2];
+      }
+    if (faces)
+      for (int j = m.finc_off[i]; j < m.finc_off[i + 1]; ++j) {
+        const double* f = fout + 3 * (size_t)m.finc[j];
+        a[0] += f[0];
+        a[1] += f[1];
+        a[2] += f[2];
+      }
+    double* yi = y + (int64_t)ystride * i + yoff;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) yi[c] = accumulate ? yi[c] + a[c] : a[c];
+  }
+}
+
+// slots[b] = workgroup b's share of x.y, one workgroup per slot (a
+// fixed-order sum); nothing when the CG solve in ctl is done.
+__global__ __launch_bounds__(TPB) void k_dot_slots(int64_t n, const double* __restrict__ x,
+                                                   const double* __restrict__ y, double* __restrict__ slots,
+                                                   const CgCtl* ctl) {
+  __shared__ double sh[2 * TPB / 64];
+  if (ctl->done) return;
+  double acc = 0.0;
+  for (int64_t k = (int64_t)blockIdx.x * TPB + threadIdx.x; k < n; k += (int64_t)gridDim.x * TPB) acc += x[k] * y[k];
+  acc = block_sum(acc, sh);
+  if (threadIdx.x == 0) slots[blockIdx.x] = acc;
 }
 
 // The same pass for several cases (lanes) in one launch: work item b is
@@ -445,7 +515,7 @@ __global__ __launch_bounds__(NT) void k_tile_pipe(MeshDev m, const uint8_t* __re
         for (int c = 0; c < 3; ++c) px[q][c] = x[g3 + c];
       }
     };
-    energy += tile_elements<float, NT, PF, true>(m, emat, mats, matl, A, t, gid, xs, ys, gather_next);
+    energy += tile_elements<float, NT, PF, true, false>(m, emat, mats, matl, A, t, gid, xs, ys, gather_next);
     __syncthreads();
     tile_scatter<float, NT>(m, A, t, gid, ys);
     __syncthreads();
@@ -641,9 +711,27 @@ static void launch_tile(const MeshDev& m, const uint8_t* emat, const MatDev* mat
   hipLaunchKernelGGL((k_tile<T, NT>), dim3(m.n_tiles), dim3(NT), lds, s, m, emat, mats, a, ctl, iter);
 }
 
+static unsigned node_grid(int64_t n_nodes) {
+  unsigned g = nblocks(n_nodes);
+  return g > 8192 ? 8192 : (g == 0 ? 1 : g);
+}
+
 void launch_tile_f64(const MeshDev& m, const uint8_t* emat, const MatDev* mats, const TileArgs<double>& a,
                      CgCtl* ctl, int iter, hipStream_t s) {
-  launch_tile<double>(m, emat, mats, a, ctl, iter, s);
+  if (!a.eout) {
+    launch_tile<double>(m, emat, mats, a, ctl, iter, s);
+    return;
+  }
+  // deterministic: element and face slots, the node pass in slot order, and
+  // p.Ap as a fixed-order dot product (a CG pass has x1 = p, a1 = 1)
+  constexpr int NT = 256;
+  hipLaunchKernelGGL((k_tile<double, NT, true>), dim3(m.n_tiles), dim3(NT), tile_lds<double>(m.max_tile_nodes), s, m,
+                     emat, mats, a, ctl, iter);
+  const int elems = a.sK != 0.0 || a.sM != 0.0, faces = a.sC != 0.0 || a.vin != nullptr;
+  hipLaunchKernelGGL(k_node_gather, dim3(node_grid(m.n_nodes)), dim3(TPB), 0, s, m, a.eout, a.fout, a.y, 3, 0,
+                     a.accumulate, elems, faces, ctl, iter);
+  if (iter >= 0)
+    hipLaunchKernelGGL(k_dot_slots, dim3(NSLOT), dim3(TPB), 0, s, 3 * m.n_nodes, a.x1, a.y, ctl->pAp, ctl);
 }
 void launch_tile_f32(const MeshDev& m, const uint8_t* emat, const MatDev* mats, const TileArgs<float>& a,
                      CgCtl* ctl, int iter, int grid_cap, hipStream_t s) {
@@ -698,9 +786,14 @@ void launch_geom(const MeshDev& m, float* geo32, double* geo64, hipStream_t s) {
 
 // ------------------------------------------------------------ diagonal
 
+// DET: values 3 half .. 3 half + 2 of each node's block go to the element
+// and face slots (eout, fout) instead of the LDS accumulator; a node pass
+// sums them in slot order.
+template <bool DET>
 __global__ __launch_bounds__(TPB) void k_tile_diag(MeshDev m, const uint8_t* __restrict__ emat,
                                                    const MatDev* __restrict__ mats, double cM, double cK, double cC,
-                                                   double* __restrict__ diag6) {
+                                                   double* __restrict__ diag6, int half, double* __restrict__ eout,
+                                                   double* __restrict__ fout) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   double* ds = reinterpret_cast<double*>(smem_raw);
   const int t = blockIdx.x;
@@ -723,8 +816,13 @@ __global__ __launch_bounds__(TPB) void k_tile_diag(MeshDev m, const uint8_t* __r
     const MatDev mt = mats[emat[e]];
     double out[10][6];
     diag_blocks<double>(G, mt.lam, mt.mu, mt.rho, cM, cK, out);
-    for (int k = 0; k < 10; ++k)
-      for (int j = 0; j < 6; ++j) atomicAdd(&ds[6 * ln[k] + j], out[k][j]);
+    if constexpr (DET) {
+      for (int k = 0; k < 10; ++k)
+        for (int c = 0; c < 3; ++c) eout[30 * (size_t)e + 3 * k + c] = out[k][3 * half + c];
+    } else {
+      for (int k = 0; k < 10; ++k)
+        for (int j = 0; j < 6; ++j) atomicAdd(&ds[6 * ln[k] + j], out[k][j]);
+    }
   }
   if (cC != 0.0) {
     const int f1 = m.tile_face_off[t + 1];
@@ -740,10 +838,15 @@ __global__ __launch_bounds__(TPB) void k_tile_diag(MeshDev m, const uint8_t* __r
       for (int k = 0; k < 6; ++k) {
         const int l = m.fconn_loc[k * m.face_stride + f];
         const double sc = cC * g.area / 180.0 * (k < 3 ? 6.0 : 32.0);
-        for (int j = 0; j < 6; ++j) atomicAdd(&ds[6 * l + j], sc * Z[j]);
+        if constexpr (DET) {
+          for (int c = 0; c < 3; ++c) fout[18 * (size_t)f + 3 * k + c] = sc * Z[3 * half + c];
+        } else {
+          for (int j = 0; j < 6; ++j) atomicAdd(&ds[6 * l + j], sc * Z[j]);
+        }
       }
     }
   }
+  if constexpr (DET) return;
   __syncthreads();
   for (int k = threadIdx.x; k < 6 * nint; k += TPB) diag6[ib6 + k] = ds[k];
   for (int k = 6 * nint + threadIdx.x; k < 6 * nt; k += TPB) {
@@ -753,9 +856,19 @@ __global__ __launch_bounds__(TPB) void k_tile_diag(MeshDev m, const uint8_t* __r
 }
 
 void launch_tile_diag(const MeshDev& m, const uint8_t* emat, const MatDev* mats, double cM, double cK, double cC,
-                      double* diag6, hipStream_t s) {
+                      double* diag6, hipStream_t s, double* eout, double* fout) {
   const size_t lds = 6 * (size_t)m.max_tile_nodes * sizeof(double);
-  hipLaunchKernelGGL(k_tile_diag, dim3(m.n_tiles), dim3(TPB), lds, s, m, emat, mats, cM, cK, cC, diag6);
+  if (!eout) {
+    hipLaunchKernelGGL(k_tile_diag<false>, dim3(m.n_tiles), dim3(TPB), lds, s, m, emat, mats, cM, cK, cC, diag6, 0,
+                       nullptr, nullptr);
+    return;
+  }
+  for (int half = 0; half < 2; ++half) {
+    hipLaunchKernelGGL(k_tile_diag<true>, dim3(m.n_tiles), dim3(TPB), lds, s, m, emat, mats, cM, cK, cC, diag6, half,
+                       eout, fout);
+    hipLaunchKernelGGL(k_node_gather, dim3(node_grid(m.n_nodes)), dim3(TPB), 0, s, m, eout, fout, diag6, 6, 3 * half,
+                       0, 1, cC != 0.0 ? 1 : 0, nullptr, -1);
+  }
 }
 
 // Inverse of each symmetric 3x3 block [[a xy xz][xy b yz][xz yz c]] by

@@ -52,6 +52,30 @@ def trace(db, out, command, top=16):
             full = [x for x in d if x >= 0.5 * mx]
             lines.append(f"{pat}: {len(d)} launches, mean over all {sum(d) / len(d) / 1e3:.1f} us, "
                          f"mean over {len(full)} full launches {sum(full) / len(full) / 1e3:.1f} us")
+    # device busy fraction over the march: the union of every kernel's
+    # interval within the span from the first to the last launch of the
+    # operator pass (host decisions, synchronisations and launch gaps are
+    # the idle rest)
+    for pat in ("k_tile_pipe<", "k_tile_lanes_pipe<"):
+        w = con.execute("select min(start), max(end) from kernels where name like ?", (f"%{pat}%",)).fetchone()
+        if not w or w[0] is None:
+            continue
+        t0, t1 = w
+        iv = con.execute("select start, end from kernels where end > ? and start < ? order by start",
+                         (t0, t1)).fetchall()
+        busy, cur_s, cur_e = 0, None, None
+        for a, b in iv:
+            a, b = max(a, t0), min(b, t1)
+            if cur_e is None or a > cur_e:
+                if cur_e is not None:
+                    busy += cur_e - cur_s
+                cur_s, cur_e = a, b
+            else:
+                cur_e = max(cur_e, b)
+        if cur_e is not None:
+            busy += cur_e - cur_s
+        lines.append(f"device busy over the span of the {pat} launches ({(t1 - t0) / 1e6:.1f} ms): "
+                     f"{100.0 * busy / (t1 - t0):.1f} % (idle {100.0 * (1 - busy / (t1 - t0)):.1f} %)")
     open(out, "w").write("\n".join(lines) + "\n")
     print("\n".join(lines))
 

@@ -4,7 +4,9 @@
 // returns 0, or the number of the first property that fails.  plant != 0
 // first plants one mistake in the built layout (a test that the checks see
 // it): 1 a wrong tile-local index, 2 an interior node id out of its range,
-// 3 a wrong inverse valence, 4 a face moved to another tile's element.
+// 3 a wrong inverse valence, 4 a face moved to another tile's element, 5 two
+// slots of a node's incidence list swapped, 6 an element slot listed under
+// the wrong node.
 #include <algorithm>
 #include <cmath>
 #include <cstdint>
@@ -104,6 +106,42 @@ extern "C" int check_layout(int64_t nn, int64_t nt, int64_t nf, const double* xy
   for (int64_t g = 0; g < nn; ++g) {
     const float want = valence[g] > 0 ? 1.0f / (float)valence[g] : 0.0f;
     if (L.inv_valence[g] != want) return 17;
+  }
+  // 18-19: the incidence lists of the deterministic passes: every element
+  // slot e * 10 + k (face slot f * 6 + k) listed once, under the internal id
+  // of that slot's node, each list in increasing order
+  sw::Incidence I;
+  sw::build_incidence(L, I);
+  if (plant == 5) {
+    for (int64_t g = 0; g < nn; ++g)
+      if (I.elem_off[g + 1] - I.elem_off[g] >= 2) {
+        std::swap(I.elem[I.elem_off[g]], I.elem[I.elem_off[g] + 1]);
+        break;
+      }
+  }
+  if (plant == 6) std::swap(I.elem[0], I.elem[I.elem.size() - 1]);
+  if ((int64_t)I.elem_off.size() != nn + 1 || I.elem_off[0] != 0 || I.elem_off[nn] != 10 * nt) return 18;
+  {
+    std::vector<int> hit(10 * nt, 0);
+    for (int64_t g = 0; g < nn; ++g)
+      for (int32_t j = I.elem_off[g]; j < I.elem_off[g + 1]; ++j) {
+        const int32_t sl = I.elem[j];
+        if (sl < 0 || sl >= 10 * nt || hit[sl]++) return 18;
+        if (j > I.elem_off[g] && I.elem[j - 1] >= sl) return 18;
+        const int64_t e = sl / 10, k = sl % 10;
+        if (L.node_u2i[tet10[10 * (int64_t)L.elem_order[e] + k]] != g) return 18;
+      }
+  }
+  if ((int64_t)I.face_off.size() != nn + 1 || I.face_off[nn] != 6 * nf) return 19;
+  {
+    std::vector<int> hit(std::max<int64_t>(6 * nf, 1), 0);
+    for (int64_t g = 0; g < nn; ++g)
+      for (int32_t j = I.face_off[g]; j < I.face_off[g + 1]; ++j) {
+        const int32_t sl = I.face[j];
+        if (sl < 0 || sl >= 6 * nf || hit[sl]++) return 19;
+        if (j > I.face_off[g] && I.face[j - 1] >= sl) return 19;
+        if (L.fconn[(sl % 6) * L.face_stride + sl / 6] != g) return 19;
+      }
   }
   stats[0] = L.n_tiles;
   stats[1] = L.max_tile_nodes;

@@ -7,7 +7,9 @@ contiguous id range (in tile order, covering [0, n_interior)) and its shared
 nodes lie address-sorted in the shared suffix, every element's tile-local
 indices name its own nodes, faces sit in their owner's tile, interior nodes
 are touched by one tile only and shared nodes by several, and the per-node
-inverse valence is exact."""
+inverse valence is exact; and the node incidence lists of the
+deterministic passes list every element and face slot once, under its
+node, in increasing order."""
 import ctypes as C
 import os
 import shutil
@@ -39,6 +41,8 @@ FAILS = {
     15: "interior ranges do not cover the interior",
     16: "interior node touched by another tile, or shared node by one tile only",
     17: "inverse valence wrong",
+    18: "element incidence lists wrong (a slot missing, repeated, out of order or under another node)",
+    19: "face incidence lists wrong",
 }
 
 
@@ -109,7 +113,7 @@ def test_one_tile_mesh(lib):
     assert s["n_tiles"] == 1 and s["n_interior"] == m.n_nodes and s["shared"] == 0
 
 
-@pytest.mark.parametrize("plant,code", [(1, 10), (2, 7), (3, 17), (4, 12)])
+@pytest.mark.parametrize("plant,code", [(1, 10), (2, 7), (3, 17), (4, 12), (5, 18), (6, 18)])
 def test_checker_sees_planted_mistakes(lib, plant, code):
     """One mistake planted in the built layout (a swapped tile-local index,
     a shifted interior node id, a halved inverse valence, a face moved out of

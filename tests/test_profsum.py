@@ -70,3 +70,22 @@ def test_bench_reads_traffic_only_for_current_sources(tmp_path, monkeypatch):
     assert bench.read_traffic("tile_f32") == 1.25e9
     p.write_text("hbm_bytes_per_launch: 1.25e+09\nkernel_sources_sha256_16: 0000000000000000\n")
     assert bench.read_traffic("tile_f32") is None          # taken on other sources
+
+
+def test_trace_device_busy_fraction(tmp_path):
+    # operator passes span 0 .. 1000 us; kernels cover 0-300, 250-400 (an
+    # overlap), 600-700 and 900-1000 us: busy 600 of 1000 us.  A kernel
+    # outside the span does not count.
+    db = tmp_path / "trace.db"
+    con = sqlite3.connect(db)
+    con.execute("create table kernels (name text, start integer, end integer)")
+    tile = "void sw::k_tile_pipe<256, 5, false>(...)"
+    rows = [(tile, 0, 300_000), ("sw::k_cg_update(...)", 250_000, 400_000), ("sw::k_cg_dir(...)", 600_000, 700_000),
+            (tile, 900_000, 1_000_000), ("sw::k_newmark(...)", 2_000_000, 2_500_000)]
+    con.executemany("insert into kernels values (?, ?, ?)", rows)
+    con.commit()
+    con.close()
+    out = tmp_path / "trace.txt"
+    profsum.trace(str(db), str(out), "trace cmd")
+    txt = out.read_text()
+    assert "device busy over the span of the k_tile_pipe< launches (1.0 ms): 60.0 % (idle 40.0 %)" in txt
