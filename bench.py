@@ -212,13 +212,23 @@ def batched_study(sw, cg, ctx, per_mesh, steps, proj_dim, legs=("seq", "batched"
             in_sample.append(k < sample)
         progress(f"batched study: {per_mesh} models of {name} generated")
 
+    tuned = {}
+
     def run(batched, precision="mixed", guess="proj"):
         sel = cases if batched else [c for c, s in zip(cases, in_sample) if s]
         lanes = [sw.Case(ctx, gm, c, precision=precision, guess=guess, proj_dim=proj_dim) for gm, c in sel]
+        b = None
+        if batched:
+            # set-up-time choice of the lane pass's schedule (not timed)
+            b = sw.Batch(ctx, lanes)
+            choice, ms = b.autotune(reps=3)
+            tuned.update({"choice": int(choice), "candidates_ms": [round(float(v), 4) for v in ms],
+                          "candidates": ["mesh after mesh, 3 workgroups/CU", "mesh after mesh, 2/CU",
+                                         "meshes interleaved tile by tile, 3/CU", "interleaved, 2/CU"]})
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         if batched:
-            sw.Batch(ctx, lanes).step(steps)
+            b.step(steps)
         else:
             for lane in lanes:
                 lane.step(steps)
@@ -228,7 +238,7 @@ def batched_study(sw, cg, ctx, per_mesh, steps, proj_dim, legs=("seq", "batched"
                  f"{len(sel)} models x {steps} steps in {dt:.1f} s")
         its = np.concatenate([lane.step_log()[0] for lane in lanes]).astype(np.float64)
         worst = float(max(lane.stats()["max_true_rel_res"] for lane in lanes))
-        del lanes
+        del lanes, b
         torch.cuda.empty_cache()
         return len(sel) * steps / dt, float(its.mean()), worst
 
@@ -255,6 +265,8 @@ def batched_study(sw, cg, ctx, per_mesh, steps, proj_dim, legs=("seq", "batched"
     if "plain" in legs and "batched" in legs:
         out["batched_vs_plain_fp64"] = round(bat / plain, 3)
     out["max_true_rel_res"] = worst
+    if tuned:
+        out["batch_autotune"] = tuned
     return out
 
 
@@ -493,6 +505,10 @@ def main():
                  inner_rtol=args.inner_rtol)
     if args.guess in LEARNED:
         gc.attach_mlp(net)
+    # set-up-time choice of the FP32 pass's workgroups per CU (not timed)
+    tune_choice, tune_ms = gc.autotune(reps=5)
+    case_tune = {"choice": ["3 workgroups/CU", "2/CU", "1/CU"][int(tune_choice)],
+                 "candidates_ms": [round(float(v), 4) for v in tune_ms]}
     if args.calibrate_copy_mib > 0:
         src = torch.ones(args.calibrate_copy_mib << 18, dtype=torch.float32, device="cuda")
         dst = torch.empty_like(src)
@@ -613,6 +629,7 @@ def main():
         "max_true_rel_res": float(np.max(rel)),
         "flags": stats["flags"], "wall_s_timed": round(wall, 3),
         "setup_s": {"host_generation": round(t_gen, 2), "mesh_upload_and_layout": round(t_up, 2)},
+        "autotune": case_tune,
         "learned_guess_training": train_info,
         "kernels_ms": {k: {"total_ms": round(v[0], 3), "launches": v[1], "full_launch_us": round(1e3 * v[2], 1),
                            "timed_one_launch_in": PROFILE_EVERY}

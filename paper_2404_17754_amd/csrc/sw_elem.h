@@ -84,8 +84,12 @@ SW_HD bool tet_geometry(const double x[4][3], Geo<T>& G) {
 template <typename T, bool STIFF, bool MASS, bool DYN, typename Sink>
 SW_HD void element_apply(const Geo<T>& G, T lam, T mu, T sK, T sMV, const T w[10][3], Sink&& sink) {
   const bool stiff = STIFF && (!DYN || sK != (T)0), mass = MASS && (!DYN || sMV != (T)0);
+  // S'_k = sigma_k + sum_i sigma_i; with gs_j = 4 (V/20) sK g_j the forces
+  // are f_i = (S'_i - 5/4 sum_k sigma_k) gs_i and f_ij = S'_i gs_j + S'_j gs_i
+  // (the V/20 and the factor 4 folded into the twelve gradient values)
   T S[4][6];
-  T Ssum[6] = {0, 0, 0, 0, 0, 0};
+  T s54[6] = {0, 0, 0, 0, 0, 0};
+  T gs[4][3];
   if (stiff) {
     T sum[6] = {0, 0, 0, 0, 0, 0};
 #pragma unroll
@@ -118,14 +122,17 @@ SW_HD void element_apply(const Geo<T>& G, T lam, T mu, T sK, T sMV, const T w[10
 #pragma unroll
       for (int m = 0; m < 6; ++m) sum[m] += S[k][m];
     }
-    const T c20 = sK * G.vol * (T)0.05;
+    const T c4 = sK * G.vol * (T)0.2;
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
+    for (int j = 0; j < 4; ++j) {
 #pragma unroll
-      for (int m = 0; m < 6; ++m) {
-        S[k][m] = c20 * (S[k][m] + sum[m]);
-        Ssum[m] += S[k][m];
-      }
+      for (int d = 0; d < 3; ++d) gs[j][d] = c4 * G.g[j][d];
+    }
+#pragma unroll
+    for (int m = 0; m < 6; ++m) {
+      s54[m] = (T)1.25 * sum[m];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) S[k][m] += sum[m];
     }
   }
   // mass: per component the vertex sum, edge sum and each vertex's incident-edge sum
@@ -151,8 +158,8 @@ SW_HD void element_apply(const Geo<T>& G, T lam, T mu, T sK, T sMV, const T w[10
     if (stiff) {
       T sy[6];
 #pragma unroll
-      for (int m = 0; m < 6; ++m) sy[m] = (T)4 * S[i][m] - Ssum[m];
-      smv(sy, G.g[i], f);
+      for (int m = 0; m < 6; ++m) sy[m] = S[i][m] - s54[m];
+      smv(sy, gs[i], f);
     }
     if (mass) {
 #pragma unroll
@@ -169,10 +176,10 @@ SW_HD void element_apply(const Geo<T>& G, T lam, T mu, T sK, T sMV, const T w[10
     T f[3] = {(T)0, (T)0, (T)0};
     if (stiff) {
       T f1[3], f2[3];
-      smv(S[ea[e]], G.g[eb[e]], f1);
-      smv(S[eb[e]], G.g[ea[e]], f2);
+      smv(S[ea[e]], gs[eb[e]], f1);
+      smv(S[eb[e]], gs[ea[e]], f2);
 #pragma unroll
-      for (int c = 0; c < 3; ++c) f[c] = (T)4 * (f1[c] + f2[c]);
+      for (int c = 0; c < 3; ++c) f[c] = f1[c] + f2[c];
     }
     if (mass) {
 #pragma unroll

@@ -79,8 +79,8 @@ __device__ __forceinline__ void elem_geometry(const ElemIn<T>& in, Geo<T>& G) {
 }
 
 // Element work of tile t on the values gathered in LDS (xs, node ids gid),
-// accumulated into ys; returns the tile's share of x.A x (only the CG passes
-// use it).  Work-item i takes the tile's element i: the layout has
+// accumulated into ys (x.A x, which CG passes need, is taken afterwards from
+// the tile's node values: tile_scatter).  Work-item i takes the tile's element i: the layout has
 // interleaved the elements so that consecutive ones rarely share a node (few
 // LDS atomic collisions) while their loads stay coalesced.  PF: software
 // pipeline, the next element's connectivity, geometry and material are
@@ -92,13 +92,12 @@ __device__ __forceinline__ void elem_geometry(const ElemIn<T>& in, Geo<T>& G) {
 // the material constants come from an LDS copy (matl: lam, mu, rho per
 // material) rather than from global memory, a load that would wait on the
 // element's material id.  DET: each element's ten nodal results go to its
-// slots of A.eout instead of the LDS accumulator (no energy).
+// slots of A.eout instead of the LDS accumulator.
 template <typename T, int NT, bool PF, bool STIFF, bool MASS, bool DYN, bool MATL, bool DET, typename Hook>
-__device__ __forceinline__ double tile_element_loop(const MeshDev& m, const uint8_t* __restrict__ emat,
-                                                    const MatDev* __restrict__ mats, const float* matl,
-                                                    const TileArgs<T>& A, int t, const int32_t* gid, const T* xs,
-                                                    double* ys, Hook&& hook) {
-  double energy = 0.0;
+__device__ __forceinline__ void tile_element_loop(const MeshDev& m, const uint8_t* __restrict__ emat,
+                                                  const MatDev* __restrict__ mats, const float* matl,
+                                                  const TileArgs<T>& A, int t, const int32_t* gid, const T* xs,
+                                                  double* ys, Hook&& hook) {
   const int eb = ldc(m.tile_elem_off, t);
   const int n_e = ldc(m.tile_elem_off, t + 1) - eb;
   auto elem_of = [&](int i) { return eb + i; };
@@ -133,7 +132,6 @@ __device__ __forceinline__ double tile_element_loop(const MeshDev& m, const uint
     }
     // each node's force goes to the LDS accumulator as soon as it is
     // complete (no 30-value force array held in registers)
-    T eloc = (T)0;
     element_apply<T, STIFF, MASS, DYN>(G, lam, mu, A.sK, A.sM * rho * G.vol, w,
                                   [&](int k, T f0, T f1, T f2) {
                                     if constexpr (DET) {
@@ -146,40 +144,36 @@ __device__ __forceinline__ double tile_element_loop(const MeshDev& m, const uint
                                       atomicAdd(yk, (double)f0);
                                       atomicAdd(yk + 1, (double)f1);
                                       atomicAdd(yk + 2, (double)f2);
-                                      eloc += w[k][0] * f0 + w[k][1] * f1 + w[k][2] * f2;
                                     }
                                   });
-    energy += (double)eloc;
   }
-  return energy;
 }
 
 // Element and face work of tile t (see tile_element_loop), plus the
 // boundary faces owned by the tile's elements (DET: their results to the
 // face slots of A.fout).
 template <typename T, int NT, bool PF, bool MATL, bool DET, typename Hook>
-__device__ __forceinline__ double tile_elements(const MeshDev& m, const uint8_t* __restrict__ emat,
-                                                const MatDev* __restrict__ mats, const float* matl,
-                                                const TileArgs<T>& A, int t, const int32_t* gid, const T* xs,
-                                                double* ys, Hook&& hook) {
-  double energy = 0.0;
+__device__ __forceinline__ void tile_elements(const MeshDev& m, const uint8_t* __restrict__ emat,
+                                              const MatDev* __restrict__ mats, const float* matl,
+                                              const TileArgs<T>& A, int t, const int32_t* gid, const T* xs,
+                                              double* ys, Hook&& hook) {
   if constexpr (sizeof(T) == 8) {
     // FP64: per-element checks (the branch-free form needs more registers
     // than the FP64 passes can spare; measured slower)
     if (A.sK != (T)0 || A.sM != (T)0)
-      energy = tile_element_loop<T, NT, PF, true, true, true, MATL, DET>(m, emat, mats, matl, A, t, gid, xs, ys,
+      tile_element_loop<T, NT, PF, true, true, true, MATL, DET>(m, emat, mats, matl, A, t, gid, xs, ys,
                                                                         hook);
     else
       hook();
   } else {
     if (A.sK != (T)0 && A.sM != (T)0)
-      energy = tile_element_loop<T, NT, PF, true, true, false, MATL, false>(m, emat, mats, matl, A, t, gid, xs, ys,
+      tile_element_loop<T, NT, PF, true, true, false, MATL, false>(m, emat, mats, matl, A, t, gid, xs, ys,
                                                                            hook);
     else if (A.sK != (T)0)
-      energy = tile_element_loop<T, NT, PF, true, false, false, MATL, false>(m, emat, mats, matl, A, t, gid, xs, ys,
+      tile_element_loop<T, NT, PF, true, false, false, MATL, false>(m, emat, mats, matl, A, t, gid, xs, ys,
                                                                             hook);
     else if (A.sM != (T)0)
-      energy = tile_element_loop<T, NT, PF, false, true, false, MATL, false>(m, emat, mats, matl, A, t, gid, xs, ys,
+      tile_element_loop<T, NT, PF, false, true, false, MATL, false>(m, emat, mats, matl, A, t, gid, xs, ys,
                                                                             hook);
     else
       hook();
@@ -214,11 +208,6 @@ __device__ __forceinline__ double tile_elements(const MeshDev& m, const uint8_t*
         }
         const T n[3] = {(T)g.n[0], (T)g.n[1], (T)g.n[2]};
         face_dashpot_apply<T>(n, (T)g.area, (T)mt.zp, (T)mt.zs, A.sC, w, out);
-#pragma unroll
-        for (int k = 0; k < 6; ++k) {
-#pragma unroll
-          for (int c = 0; c < 3; ++c) energy += (double)w[k][c] * (double)out[k][c];
-        }
       }
       if (A.vin != nullptr && m.face_role[f] == 2) {
         // incident wave: traction 2 Z v_in, consistent load A/3 on the edge nodes
@@ -248,36 +237,45 @@ __device__ __forceinline__ double tile_elements(const MeshDev& m, const uint8_t*
       }
     }
   }
-  return energy;
 }
 
 template <typename T, int NT, bool PF>
-__device__ __forceinline__ double tile_elements(const MeshDev& m, const uint8_t* __restrict__ emat,
-                                                const MatDev* __restrict__ mats, const TileArgs<T>& A, int t,
-                                                const int32_t* gid, const T* xs, double* ys) {
-  return tile_elements<T, NT, PF, false, false>(m, emat, mats, nullptr, A, t, gid, xs, ys, [] {});
+__device__ __forceinline__ void tile_elements(const MeshDev& m, const uint8_t* __restrict__ emat,
+                                              const MatDev* __restrict__ mats, const TileArgs<T>& A, int t,
+                                              const int32_t* gid, const T* xs, double* ys) {
+  tile_elements<T, NT, PF, false, false>(m, emat, mats, nullptr, A, t, gid, xs, ys, [] {});
 }
 
 // Results of tile t: interior nodes (one contiguous range) with plain
-// stores, shared nodes with address-sorted global atomics.
+// stores, shared nodes with address-sorted global atomics.  Returns this
+// work-item's share of the tile's x.(A x)_tile = sum over the tile's nodes
+// of the input value times the tile's partial sum: summed over the tiles it
+// is x.A x (a node's full value is the sum of its tiles' partials), with one
+// product per node value instead of one per element entry.
 template <typename T, int NT>
-__device__ __forceinline__ void tile_scatter(const MeshDev& m, const TileArgs<T>& A, int t, const int32_t* gid,
-                                             const double* ys) {
+__device__ __forceinline__ double tile_scatter(const MeshDev& m, const TileArgs<T>& A, int t, const int32_t* gid,
+                                               const T* xs, const double* ys) {
   const int nt = ldc(m.tile_node_off, t + 1) - ldc(m.tile_node_off, t);
   const int nint = ldc(m.tile_nint, t);
   const int64_t ib3 = 3 * (int64_t)ldc(m.tile_int_base, t);
   T* __restrict__ y = A.y;
+  double energy = 0.0;
   for (int k = threadIdx.x; k < 3 * nint; k += NT) {
+    const double v = ys[k];
+    energy += (double)xs[k] * v;
     if (A.accumulate)
-      y[ib3 + k] += (T)ys[k];
+      y[ib3 + k] += (T)v;
     else
-      y[ib3 + k] = (T)ys[k];
+      y[ib3 + k] = (T)v;
   }
   // shared nodes: address-sorted global atomics
   for (int k = 3 * nint + threadIdx.x; k < 3 * nt; k += NT) {
     const int j = k / 3;
-    atomic_add(&y[3 * (int64_t)gid[j] + (k - 3 * j)], (T)ys[k]);
+    const double v = ys[k];
+    energy += (double)xs[k] * v;
+    atomic_add(&y[3 * (int64_t)gid[j] + (k - 3 * j)], (T)v);
   }
+  return energy;
 }
 
 // One workgroup's share of an operator pass: tile t of mesh m.  smem_raw is
@@ -340,11 +338,10 @@ __device__ __forceinline__ void tile_body(const MeshDev& m, const uint8_t* __res
     }
     __syncthreads();
   };
-  double energy =
-      tile_elements<T, NT, sizeof(T) == 4, false, DET>(m, emat, mats, nullptr, A, t, gid, xs, ys, gather);
+  tile_elements<T, NT, sizeof(T) == 4, false, DET>(m, emat, mats, nullptr, A, t, gid, xs, ys, gather);
   if constexpr (DET) return;
   __syncthreads();
-  tile_scatter<T, NT>(m, A, t, gid, ys);
+  const double energy = tile_scatter<T, NT>(m, A, t, gid, xs, ys);
   if (iter >= 0) {
     const double s = block_sum_n<NT>(energy, sh);
     if (threadIdx.x == 0) atomic_add(&ctl->pAp[t % NSLOT], s);
@@ -515,9 +512,9 @@ __global__ __launch_bounds__(NT) void k_tile_pipe(MeshDev m, const uint8_t* __re
         for (int c = 0; c < 3; ++c) px[q][c] = x[g3 + c];
       }
     };
-    energy += tile_elements<float, NT, PF, true, false>(m, emat, mats, matl, A, t, gid, xs, ys, gather_next);
+    tile_elements<float, NT, PF, true, false>(m, emat, mats, matl, A, t, gid, xs, ys, gather_next);
     __syncthreads();
-    tile_scatter<float, NT>(m, A, t, gid, ys);
+    energy += tile_scatter<float, NT>(m, A, t, gid, xs, ys);
     __syncthreads();
     if (!more) break;
 #pragma unroll
@@ -642,9 +639,9 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(3, 3))) void
         for (int c = 0; c < 3; ++c) px[q][c] = (threadIdx.x + q * NT < ntn) ? xn[g3 + c] : 0.0f;
       }
     }
-    const double energy = tile_elements<float, NT, false>(L.m, L.emat, L.mats, L.A, t, gid, xs, ys);
+    tile_elements<float, NT, false>(L.m, L.emat, L.mats, L.A, t, gid, xs, ys);
     __syncthreads();
-    tile_scatter<float, NT>(L.m, L.A, t, gid, ys);
+    const double energy = tile_scatter<float, NT>(L.m, L.A, t, gid, xs, ys);
     const double e = block_sum_n<NT>(energy, sh);
     if (threadIdx.x == 0) atomic_add(&L.ctl->pAp[t % NSLOT], e);
     __syncthreads();
@@ -817,8 +814,12 @@ __global__ __launch_bounds__(TPB) void k_tile_diag(MeshDev m, const uint8_t* __r
     double out[10][6];
     diag_blocks<double>(G, mt.lam, mt.mu, mt.rho, cM, cK, out);
     if constexpr (DET) {
+      // static register indices (a run-time index would put out[][] in scratch)
+#pragma unroll
       for (int k = 0; k < 10; ++k)
-        for (int c = 0; c < 3; ++c) eout[30 * (size_t)e + 3 * k + c] = out[k][3 * half + c];
+#pragma unroll
+        for (int c = 0; c < 3; ++c)
+          eout[30 * (size_t)e + 3 * k + c] = half ? out[k][3 + c] : out[k][c];
     } else {
       for (int k = 0; k < 10; ++k)
         for (int j = 0; j < 6; ++j) atomicAdd(&ds[6 * ln[k] + j], out[k][j]);
@@ -839,7 +840,8 @@ __global__ __launch_bounds__(TPB) void k_tile_diag(MeshDev m, const uint8_t* __r
         const int l = m.fconn_loc[k * m.face_stride + f];
         const double sc = cC * g.area / 180.0 * (k < 3 ? 6.0 : 32.0);
         if constexpr (DET) {
-          for (int c = 0; c < 3; ++c) fout[18 * (size_t)f + 3 * k + c] = sc * Z[3 * half + c];
+#pragma unroll
+          for (int c = 0; c < 3; ++c) fout[18 * (size_t)f + 3 * k + c] = sc * (half ? Z[3 + c] : Z[c]);
         } else {
           for (int j = 0; j < 6; ++j) atomicAdd(&ds[6 * l + j], sc * Z[j]);
         }

@@ -4,6 +4,8 @@ counter runs) for the profiles/ folder.
     python -m paper_2404_17754_amd.profsum trace <results.db> <out.txt> "<command>"
     python -m paper_2404_17754_amd.profsum traffic <fetch.db> <write.db> <kernel substring> \
         <calibration MiB> <out.txt> "<fetch command>" "<write command>"
+    python -m paper_2404_17754_amd.profsum counters <db1,db2,...> <kernel substring> \
+        <elements per launch> <out.txt> "<command>" ...
 
 The traffic summary scales FETCH_SIZE and WRITE_SIZE by what the same
 counters read for the calibration copy of known size made in the same run
@@ -116,10 +118,58 @@ def traffic(fetch_db, write_db, pat, calib_mib, out, cmd_f, cmd_w):
     print("\n".join(lines))
 
 
+# shares of the waves' cycles (ratios of counters of the same block)
+WAVE_SHARES = [("SQ_WAIT_ANY", "waiting for anything (memory or LDS results, barriers, dependencies)"),
+               ("SQ_WAIT_INST_ANY", "waiting to issue any instruction"),
+               ("SQ_ACTIVE_INST_VALU", "issuing VALU instructions"),
+               ("SQ_ACTIVE_INST_LDS", "issuing LDS instructions"),
+               ("SQ_WAIT_INST_LDS", "waiting to issue LDS instructions"),
+               ("SQ_ACTIVE_INST_VMEM", "issuing vector memory instructions"),
+               ("SQ_ACTIVE_INST_ANY", "issuing any instruction")]
+
+
+def counters(dbs, pat, n_elems, out, cmds):
+    """Mean per full launch of every counter the runs took on the kernels
+    matching `pat` (launches under half a counter's largest value are left
+    out), with the shares of SQ_WAVE_CYCLES and per-element figures."""
+    vals = collections.defaultdict(list)
+    for db in dbs:
+        con = sqlite3.connect(db)
+        for k, c, v in con.execute("select kernel_name, counter_name, value from counters_collection"):
+            if pat in k:
+                vals[c].append(v)
+    mean = {}
+    lines = ["# rocprofv3 SQ counters of one launch", f"kernel: {pat}"] + [f"command: {c}" for c in cmds] + [""]
+    for c in sorted(vals):
+        v = vals[c]
+        full = [x for x in v if x >= 0.5 * max(v)] if max(v) > 0 else v
+        mean[c] = sum(full) / len(full)
+        lines.append(f"{c:28s} {mean[c]:16.6e}   (mean of {len(full)} of {len(v)} launches)")
+    lines.append("")
+    wc = mean.get("SQ_WAVE_CYCLES")
+    if wc:
+        for c, what in WAVE_SHARES:
+            if c in mean:
+                lines.append(f"share of wave cycles {what}: {100.0 * mean[c] / wc:.1f} % ({c})")
+    if "SQ_INSTS_VALU" in mean and n_elems > 0:
+        lines.append(f"VALU instructions per wave step of 64 elements: {mean['SQ_INSTS_VALU'] * 64.0 / n_elems:.0f}")
+    if "SQ_INSTS_LDS" in mean and n_elems > 0:
+        lines.append(f"LDS instructions per wave step of 64 elements: {mean['SQ_INSTS_LDS'] * 64.0 / n_elems:.0f}")
+    if "SQ_LDS_BANK_CONFLICT" in mean and mean.get("SQ_ACTIVE_INST_LDS"):
+        lines.append(f"LDS bank-conflict cycles per LDS issue cycle: "
+                     f"{mean['SQ_LDS_BANK_CONFLICT'] / mean['SQ_ACTIVE_INST_LDS']:.2f}")
+    lines.append(f"kernel_sources_sha256_16: {kernel_hash()}")
+    open(out, "w").write("\n".join(lines) + "\n")
+    print("\n".join(lines))
+
+
 if __name__ == "__main__":
     if sys.argv[1] == "trace":
         trace(sys.argv[2], sys.argv[3], sys.argv[4])
     elif sys.argv[1] == "traffic":
         traffic(sys.argv[2], sys.argv[3], sys.argv[4], int(sys.argv[5]), sys.argv[6], sys.argv[7], sys.argv[8])
+    elif sys.argv[1] == "counters":
+        # counters <db1,db2,...> <kernel substring> <elements per launch> <out.txt> "<command>" ...
+        counters(sys.argv[2].split(","), sys.argv[3], int(sys.argv[4]), sys.argv[5], sys.argv[6:])
     else:
         raise SystemExit(__doc__)

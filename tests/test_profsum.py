@@ -89,3 +89,23 @@ def test_trace_device_busy_fraction(tmp_path):
     profsum.trace(str(db), str(out), "trace cmd")
     txt = out.read_text()
     assert "device busy over the span of the k_tile_pipe< launches (1.0 ms): 60.0 % (idle 40.0 %)" in txt
+
+
+def test_counter_summary_shares_and_per_element(tmp_path):
+    tile = "void sw::k_tile_pipe<256, 5, false>(...)"
+    a = tmp_path / "p1.db"
+    b = tmp_path / "p2.db"
+    _counter_db(a, "SQ_WAVE_CYCLES", [(tile, 1000.0), (tile, 1000.0), (tile, 3.0), ("other", 5.0)])
+    con = sqlite3.connect(a)
+    con.executemany("insert into counters_collection values (?, ?, ?)",
+                    [(tile, "SQ_INSTS_VALU", 7000.0), (tile, "SQ_INSTS_VALU", 7000.0)])
+    con.commit()
+    con.close()
+    _counter_db(b, "SQ_ACTIVE_INST_VALU", [(tile, 200.0), (tile, 200.0)])
+    out = tmp_path / "c.txt"
+    profsum.counters([str(a), str(b)], "k_tile_pipe", 640, str(out), ["cmd1", "cmd2"])
+    txt = out.read_text()
+    # 7000 VALU instructions over 640 elements = 10 wave steps: 700 per step
+    assert "VALU instructions per wave step of 64 elements: 700" in txt
+    assert "issuing VALU instructions: 20.0 %" in txt
+    assert "(mean of 2 of 3 launches)" in txt
