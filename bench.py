@@ -57,6 +57,8 @@ FLOPS_PER_TET = 884 + 299 + 6 + 60
 
 # guesses that use the trained network
 LEARNED = ("mlp", "proj_mlp")
+# steps per call of a long batched march (one progress line each)
+CHUNK_STEPS = 50
 
 
 def progress(msg):
@@ -228,10 +230,20 @@ def batched_study(sw, cg, ctx, per_mesh, steps, proj_dim, legs=("seq", "batched"
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         if batched:
-            b.step(steps)
+            # chunks of steps with a progress line each (a long march is
+            # otherwise silent for minutes)
+            done = 0
+            while done < steps:
+                n = min(CHUNK_STEPS, steps - done)
+                b.step(n)
+                done += n
+                if done < steps:
+                    progress(f"batched study: {len(sel)} models at step {done} of {steps}")
         else:
-            for lane in lanes:
+            for k, lane in enumerate(lanes):
                 lane.step(steps)
+                if steps > CHUNK_STEPS:
+                    progress(f"batched study ({precision}/{guess}, case by case): model {k + 1} of {len(lanes)}")
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
         progress(f"batched study leg ({'batched' if batched else 'case by case'}, {precision}/{guess}): "
@@ -322,6 +334,58 @@ def guess_study(sw, cg, ctx, net, n_models, steps, proj_dim):
         torch.cuda.empty_cache()
     for a, b in (("mlp", "poly"), ("proj", "poly"), ("proj_mlp", "poly"), ("proj_mlp", "proj")):
         out[f"{a}_vs_{b}_iters"] = round(out[a]["cg_iters_per_step"] / out[b]["cg_iters_per_step"], 4)
+    return out
+
+
+def sweep_study(sw, cg, ctx, n_models, steps, proj_dim):
+    """The full sweep's batch shape: the sweep's reference model (seed 2999)
+    and `n_models` - 1 candidates (seeds 3000 on) of the 1000 x 1000 x 100 m
+    mesh (5 m cells, 19.78 M DOF; 50 x 50 receivers; Ricker 1 + 2 + 4 Hz,
+    t0 = 1 s) marched `steps` steps from rest as one batch; each candidate's
+    ERR against the reference model's surface velocities over those steps
+    and the ranking; the batch's throughput, and the time of the whole sweep
+    (1000 models x 2000 steps in batches of this size) at that rate, which
+    is an extrapolation (later steps, with the wave in the model, need
+    fewer CG iterations than the first ones)."""
+    import numpy as np
+    import torch
+    cfg = cg.CONFIGS["sweep"]
+    mesh = cg.config_mesh(cfg)
+    gm = sw.Mesh(ctx, mesh)
+    seeds = [cfg.seed - 1] + [cfg.seed + k for k in range(n_models - 1)]
+    lanes = [sw.Case(ctx, gm, cg.make_case(mesh, cfg, seed=sd, n_steps=steps), precision="mixed", guess="proj",
+                     proj_dim=proj_dim) for sd in seeds]
+    progress(f"sweep study: {n_models} models of the sweep mesh set up")
+    b = sw.Batch(ctx, lanes)
+    choice, ms = b.autotune(reps=3)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    done = 0
+    while done < steps:
+        n = min(CHUNK_STEPS, steps - done)
+        b.step(n)
+        done += n
+        progress(f"sweep study: step {done} of {steps}")
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    obs = lanes[0].waveform_device()
+    errs = [lane.misfit(obs)[0] for lane in lanes[1:]]
+    order = np.argsort(errs)
+    its = np.concatenate([lane.step_log()[0] for lane in lanes]).astype(np.float64)
+    rate = n_models * steps / dt
+    out = {"mesh": f"1000x1000x100 m, {mesh.n_tets} tets, {3 * mesh.n_nodes} DOF", "models": n_models,
+           "reference_seed": seeds[0], "candidate_seeds": f"{seeds[1]}-{seeds[-1]}", "steps": steps,
+           "receivers": len(lanes[0].waveforms(0, 1)[0]), "case_timesteps_per_s": round(rate, 2),
+           "dof_steps_per_s": float(f"{rate * 3 * mesh.n_nodes:.4g}"),
+           "cg_iters_per_step": round(float(its.mean()), 2), "p95": float(np.percentile(its, 95)),
+           "max_true_rel_res": float(max(lane.stats()["max_true_rel_res"] for lane in lanes)),
+           "flags": int(np.bitwise_or.reduce([lane.stats()["flags"] for lane in lanes])),
+           "err_best5": [(int(seeds[1 + i]), round(float(errs[i]), 4)) for i in order[:5]],
+           "err_median": round(float(np.median(errs)), 4),
+           "batch_autotune_choice": int(choice), "batch_autotune_ms": [round(float(v), 3) for v in ms],
+           "whole_sweep_h_extrapolated": round(1000 * 2000 / rate / 3600.0, 2)}
+    del lanes, b, obs
+    torch.cuda.empty_cache()
     return out
 
 
@@ -447,6 +511,9 @@ def main():
     ap.add_argument("--guess-study-steps", type=int, default=100)
     ap.add_argument("--solver-study", type=int, default=0,
                     help="steps (from rest) of the outer-solver study: refinement vs flexible CG (0 = skip)")
+    ap.add_argument("--sweep-study", default="",
+                    help="models,steps of an extra sweep study (reference + candidates of the 1000 m sweep mesh "
+                         "in one batch; empty = skip)")
     ap.add_argument("--fit-study", type=int, default=0,
                     help="steps of an extra input-estimation study (Green's runs + fit) on the 300 m mesh (0 = skip)")
     ap.add_argument("--train-cases", type=int, default=16)
@@ -594,7 +661,7 @@ def main():
 
     batched = None
     if args.batched > 0:
-        del gmesh
+        gmesh = None
         torch.cuda.empty_cache()
         batched = batched_study(sw, cg, ctx, args.batched, args.batched_steps, args.proj_dim,
                                 tuple(args.batched_legs.split(",")), sample=args.batched_sample)
@@ -609,6 +676,13 @@ def main():
     if args.fit_study > 0:
         torch.cuda.empty_cache()
         fit = fit_study(sw, cg, ctx, args.fit_study, 20, args.proj_dim)
+
+    sweep = None
+    if args.sweep_study:
+        gmesh = None
+        torch.cuda.empty_cache()
+        k, n = (int(v) for v in args.sweep_study.split(","))
+        sweep = sweep_study(sw, cg, ctx, k, n, args.proj_dim)
 
     progress("studies done; CPU baseline next")
     cpu = None if args.no_cpu_baseline else cpu_baseline(args.config, dof)
@@ -636,7 +710,7 @@ def main():
                        for k, v in kernels.items() if v[1]},
         "roofline": roofline, "compare": compare, "outer_solvers": solvers, "batched": batched,
         "learned_guess_study": gstudy,
-        "input_estimation": fit, "cpu_baseline": cpu,
+        "input_estimation": fit, "sweep": sweep, "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
 
