@@ -205,7 +205,7 @@ typedef struct {
   int32_t precision;     /* SW_FP64, SW_MIXED_FP32 or SW_MIXED_FP32_FLEX */
   int32_t guess;         /* SW_GUESS_* */
   int32_t poly_order;    /* 0..3, used by SW_GUESS_POLY / SW_GUESS_MLP */
-  double inner_rtol;     /* mixed precisions: floor of the inner CG relative tolerance (0 = default 1e-3) */
+  double inner_rtol;     /* mixed precisions: floor of the inner CG relative tolerance (0 = default 1e-4) */
   int32_t n_mat;         /* rows of mat, 1..255 */
   const double* mat;     /* host, n_mat x 3 rows (Vp, Vs, rho), Vp^2 > 2 Vs^2 */
   const uint8_t* tet_mat;/* host, n_tets material ids */

@@ -900,7 +900,7 @@ extern "C" int sw_case_create(sw_ctx* ctx, sw_mesh* m, const sw_case_desc* d, vo
   c->alpha = d->ray_alpha;
   c->beta = d->ray_beta;
   c->rtol = d->rtol;
-  c->inner_rtol = d->inner_rtol > 0.0 ? d->inner_rtol : 1e-3;
+  c->inner_rtol = d->inner_rtol > 0.0 ? d->inner_rtol : 1e-4;
   c->max_iter = d->max_iter;
   c->precision = d->precision;
   c->guess = d->guess;

