@@ -21,7 +21,7 @@ with the tolerance (by at least 30x from 1e-8 to 1e-11) and be within 1e-6
 relative L2 at 1e-11 (the discretisation and the arithmetic are the
 oracle's).  At 1e-8 the bound is stated per workload (TOL_BENCH): from rest
 the waveforms meet 1e-6; from the rough initial fields of the windows the
-error at 1e-8 is a few 1e-5 (measured 2.8e-5 on the large case, 9e-5 on a
+error at 1e-8 is a few 1e-5 (measured 3.6e-5 on the large case, 8e-5 on a
 sweep model), the relative residual amplified by the conditioning of the
 step operator on the field's slow components."""
 import os
