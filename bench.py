@@ -49,11 +49,14 @@ ALU_PEAK_TFLOPS = 78.6
 # the kernel class whose launches the timed region brackets with HIP events
 DOMINANT = "tile_f32"
 PROFILE_EVERY = 4
-# FP32 flops of the element-by-element operator per tetrahedron, counted
-# from its formulas: stiffness 884, consistent mass 299, fourth vertex
-# gradient 6, element energy p.Ap 60 (boundary faces and the input scaling
-# of the gathered values are left out: under 2 % of a pass)
-FLOPS_PER_TET = 884 + 299 + 6 + 60
+# FP32 flops of the element-by-element operator per tetrahedron: the
+# element arithmetic's stiffness and mass action (element_apply counted on a
+# counting number type, tests/flop_count.cpp), the fourth vertex gradient
+# (6), and p.Ap taken from the tile's node values (3 products and 3 sums per
+# node, 1.36 nodes per tet: 8).  Boundary faces and the input scaling of
+# the gathered values are left out (under 2 % of a pass).
+ELEMENT_FLOPS = 1143
+FLOPS_PER_TET = ELEMENT_FLOPS + 6 + 8
 
 # guesses that use the trained network
 LEARNED = ("mlp", "proj_mlp")
