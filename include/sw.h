@@ -177,7 +177,7 @@ typedef struct {
   const uint8_t* face_role;   /* host, n_faces: 1 side, 2 base */
   int32_t tile_max_nodes;     /* tile capacity of the device layout: distinct nodes per tile,
                                  64..1280 (0 = 1280) */
-  int32_t tile_max_elems;     /* elements per tile, 16..1024 (0 = 1024) */
+  int32_t tile_max_elems;     /* elements per tile, 16..1024 (0 = 512: two per work-item) */
   int32_t deterministic;      /* 1: also build, for deterministic cases, each node's list of the
                                  element and face slots that touch it (in element order;
                                  4 bytes per slot); 0: not */

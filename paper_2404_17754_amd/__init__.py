@@ -99,7 +99,7 @@ class Context:
 
 class Mesh:
     """Device layout of a mesh (sw_mesh_create).  tile_nodes / tile_elems:
-    tile capacity (0 = the library's default 1280 / 1024); deterministic:
+    tile capacity (0 = the library's default 1280 / 512); deterministic:
     also build the node incidence lists deterministic cases need."""
 
     def __init__(self, ctx: Context, m, tile_nodes=0, tile_elems=0, deterministic=False):

@@ -481,7 +481,7 @@ const HostLayout& layout_for(const sw_mesh_desc* d) {
   if (!g_layout.matches(d, dig)) {
     build_layout(d->n_nodes, d->n_tets, d->n_faces, d->xyz, d->tet10, d->tri6, d->face_tet, d->face_role,
                  g_layout.L, d->tile_max_nodes ? d->tile_max_nodes : TILE_MAX_NODES,
-                 d->tile_max_elems ? d->tile_max_elems : TILE_MAX_ELEMS);
+                 d->tile_max_elems ? d->tile_max_elems : TILE_DEFAULT_ELEMS);
     g_layout.cap_nodes = d->tile_max_nodes;
     g_layout.cap_elems = d->tile_max_elems;
     g_layout.digest = dig;
