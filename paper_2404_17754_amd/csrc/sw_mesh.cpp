@@ -12,7 +12,10 @@
 //    cleared); only shared nodes, one range at the end, need atomics and
 //    clearing.
 // 4. Inside a tile, elements are interleaved (stride S along the curve) so
-//    that the elements of one wavefront rarely share nodes.
+//    that the elements of one wavefront rarely share nodes; then elements are
+//    grouped into half-wavefronts and the tile's interior nodes relabelled so
+//    that the nodes one LDS instruction reaches fall into different banks
+//    (spread_banks).
 // 5. Element connectivity is stored as 16-bit indices into the tile's node
 //    list; boundary faces are attached to the tile of their owning element.
 #include <algorithm>
@@ -20,6 +23,7 @@
 #include <cstdint>
 #include <cstring>
 #include <numeric>
+#include <thread>
 #include <vector>
 
 #include "sw_layout.h"
@@ -34,6 +38,132 @@ static inline uint64_t spread3(uint64_t v) {
   v = (v | v << 4) & 0x10c30c30c30c30c3ULL;
   v = (v | v << 2) & 0x1249249249249249ULL;
   return v;
+}
+
+// LDS bank spreading of one tile.  A work-item handles the tile's elements
+// i, i + 256, ...; so element position p runs in wavefront p / 64 (64 lanes)
+// and half-wavefront p / 32, and the k-th node of every element of a
+// wavefront is read (three FP32 values at dword 3 l + c of the tile's node
+// arrays) and accumulated (three FP64 atomics at dwords 2 (3 l + c), +1) by
+// one LDS instruction each.  Two lanes of one instruction at different
+// addresses in one bank serialise: for the FP32 reads when their local
+// indices l agree mod 64 (3 is invertible mod 64), for the FP64 atomics when
+// they agree mod 32.  The tile's shared nodes keep their local indices (the
+// address-sorted suffix); two greedy passes spread the rest:
+//  * elements, in the interleaved order, each go to the half-wavefront
+//    (with room) where their shared nodes collide least with those already
+//    there (node k against node k: collisions mod 64 over the wavefront plus
+//    mod 32 over the half), a node repeated at the same k costing most;
+//  * interior nodes, most-referenced first, each take the residue mod 64
+//    (with a free slot in [0, nint)) that collides least over the groups it
+//    appears in, and the slots of each residue are handed out in order.
+// Reorders the tile's elements (conn columns, elem_order) and returns the new
+// local index of each interior node in newloc.
+static void spread_banks(int32_t e0, int32_t ne, int32_t nint, int32_t nt, int64_t stride, std::vector<uint16_t>& conn,
+                         std::vector<int32_t>& elem_order, std::vector<int32_t>& newloc) {
+  const int nh = (ne + 31) / 32, nw = (ne + 63) / 64;
+  auto node = [&](int i, int k) { return (int)(conn[k * (size_t)stride + e0 + i] / 3); };
+  // --- elements into half-wavefronts
+  std::vector<int32_t> pos(ne), fill(nh, 0);
+  std::vector<uint32_t> inhalf((size_t)nt * 10, 0);  // bit h: node at position k in half h
+  std::vector<int32_t> c64((size_t)nw * 10 * 64, 0), c32((size_t)nh * 10 * 32, 0);
+  for (int i = 0; i < ne; ++i) {
+    int best = -1;
+    int64_t bc = INT64_MAX;
+    for (int h = 0; h < nh; ++h) {
+      if (fill[h] >= std::min(32, ne - 32 * h)) continue;
+      const int w = h / 2;
+      int64_t c = 0;
+      for (int k = 0; k < 10; ++k) {
+        const int j = node(i, k);
+        if ((inhalf[(size_t)j * 10 + k] >> h) & 1u)
+          c += 8;
+        else if (j >= nint)
+          c += c64[((size_t)w * 10 + k) * 64 + j % 64] + c32[((size_t)h * 10 + k) * 32 + j % 32];
+      }
+      if (c < bc) {
+        bc = c;
+        best = h;
+      }
+    }
+    const int h = best, w = h / 2;
+    pos[i] = 32 * h + fill[h]++;
+    for (int k = 0; k < 10; ++k) {
+      const int j = node(i, k);
+      inhalf[(size_t)j * 10 + k] |= 1u << h;
+      if (j >= nint) {
+        c64[((size_t)w * 10 + k) * 64 + j % 64]++;
+        c32[((size_t)h * 10 + k) * 32 + j % 32]++;
+      }
+    }
+  }
+  std::vector<int32_t> tmp(ne);
+  std::vector<uint16_t> col(ne);
+  for (int k = 0; k < 10; ++k) {
+    uint16_t* ck = conn.data() + k * (size_t)stride + e0;
+    std::copy(ck, ck + ne, col.begin());
+    for (int i = 0; i < ne; ++i) ck[pos[i]] = col[i];
+  }
+  std::copy(elem_order.begin() + e0, elem_order.begin() + e0 + ne, tmp.begin());
+  for (int i = 0; i < ne; ++i) elem_order[e0 + pos[i]] = tmp[i];
+  // --- interior nodes onto residues
+  std::vector<int32_t> goff(nt + 1, 0), gw, gh;
+  for (int i = 0; i < ne; ++i)
+    for (int k = 0; k < 10; ++k) ++goff[node(i, k) + 1];
+  for (int j = 0; j < nt; ++j) goff[j + 1] += goff[j];
+  gw.resize(goff[nt]);
+  gh.resize(goff[nt]);
+  {
+    std::vector<int32_t> at(goff.begin(), goff.end() - 1);
+    for (int i = 0; i < ne; ++i)
+      for (int k = 0; k < 10; ++k) {
+        const int j = node(i, k);
+        gw[at[j]] = (i / 64) * 10 + k;
+        gh[at[j]++] = (i / 32) * 10 + k;
+      }
+  }
+  std::fill(c64.begin(), c64.end(), 0);
+  std::fill(c32.begin(), c32.end(), 0);
+  for (int j = nint; j < nt; ++j)
+    for (int q = goff[j]; q < goff[j + 1]; ++q) {
+      c64[(size_t)gw[q] * 64 + j % 64]++;
+      c32[(size_t)gh[q] * 32 + j % 32]++;
+    }
+  int cap[64] = {0};
+  for (int j = 0; j < nint; ++j) ++cap[j % 64];
+  std::vector<int32_t> ord(nint), res(nint);
+  std::iota(ord.begin(), ord.end(), 0);
+  std::stable_sort(ord.begin(), ord.end(),
+                   [&](int a, int b) { return goff[a + 1] - goff[a] > goff[b + 1] - goff[b]; });
+  int32_t cost[64];
+  for (int j : ord) {
+    std::fill(cost, cost + 64, 0);
+    for (int q = goff[j]; q < goff[j + 1]; ++q) {
+      const int32_t* a = &c64[(size_t)gw[q] * 64];
+      const int32_t* b = &c32[(size_t)gh[q] * 32];
+      for (int r = 0; r < 64; ++r) cost[r] += a[r] + b[r & 31];
+    }
+    int best = -1;
+    int32_t bc = INT32_MAX;
+    for (int r = 0; r < 64; ++r)
+      if (cap[r] && cost[r] < bc) {
+        bc = cost[r];
+        best = r;
+      }
+    res[j] = best;
+    --cap[best];
+    for (int q = goff[j]; q < goff[j + 1]; ++q) {
+      c64[(size_t)gw[q] * 64 + best]++;
+      c32[(size_t)gh[q] * 32 + best % 32]++;
+    }
+  }
+  int next[64];
+  for (int r = 0; r < 64; ++r) next[r] = r;
+  newloc.resize(nint);
+  for (int j = 0; j < nint; ++j) {
+    newloc[j] = next[res[j]];
+    next[res[j]] += 64;
+  }
 }
 
 void build_layout(int64_t n_nodes, int64_t n_tets, int64_t n_faces, const double* xyz, const int32_t* tet10,
@@ -187,12 +317,48 @@ void build_layout(int64_t n_nodes, int64_t n_tets, int64_t n_faces, const double
     L.max_tile_nodes = std::max(L.max_tile_nodes, nt);
     for (int32_t i = L.tile_elem_off[t]; i < L.tile_elem_off[t + 1]; ++i) {
       const int32_t e = L.elem_order[i];
-      L.elem_u2i[e] = i;
       for (int k = 0; k < 10; ++k)
         L.conn_loc[k * (size_t)L.tet_stride + i] = (uint16_t)(3 * loc[tet10[10 * (int64_t)e + k]]);
     }
     // reset loc for this tile's nodes
     for (int32_t j = L.tile_node_off[t]; j < L.tile_node_off[t + 1]; ++j) loc[L.node_i2u[L.tile_nodes[j]]] = -1;
+  }
+  // --- bank spreading, tile by tile on host threads (a tile touches only its
+  // own elements' positions and connectivity and its interior node ids): the
+  // new element order, and the interior nodes' new local indices, which
+  // their ids follow (id = tile_int_base + local index)
+  {
+    auto run = [&](int32_t t_lo, int32_t t_hi) {
+      std::vector<int32_t> newloc, moved;
+      for (int32_t t = t_lo; t < t_hi; ++t) {
+        const int32_t base = L.tile_int_base[t], nint = L.tile_nint[t];
+        const int32_t nt = L.tile_node_off[t + 1] - L.tile_node_off[t];
+        const int32_t e0 = L.tile_elem_off[t], ne = L.tile_elem_off[t + 1] - e0;
+        spread_banks(e0, ne, nint, nt, L.tet_stride, L.conn_loc, L.elem_order, newloc);
+        for (int32_t i = e0; i < e0 + ne; ++i) {
+          L.elem_u2i[L.elem_order[i]] = i;
+          for (int k = 0; k < 10; ++k) {
+            uint16_t& v = L.conn_loc[k * (size_t)L.tet_stride + i];
+            if (v / 3 < nint) v = (uint16_t)(3 * newloc[v / 3]);
+          }
+        }
+        moved.resize(nint);
+        for (int32_t j = 0; j < nint; ++j) moved[newloc[j]] = L.node_i2u[base + j];
+        for (int32_t j = 0; j < nint; ++j) {
+          L.node_i2u[base + j] = moved[j];
+          L.node_u2i[moved[j]] = base + j;
+        }
+      }
+    };
+    const int nth = (int)std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+    if (n_tiles < 4 * nth) {
+      run(0, n_tiles);
+    } else {
+      std::vector<std::thread> pool;
+      for (int k = 0; k < nth; ++k)
+        pool.emplace_back(run, (int32_t)((int64_t)n_tiles * k / nth), (int32_t)((int64_t)n_tiles * (k + 1) / nth));
+      for (auto& th : pool) th.join();
+    }
   }
   // --- coordinates in internal order
   L.xyz.resize(3 * (size_t)n_nodes);

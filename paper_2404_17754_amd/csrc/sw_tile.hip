@@ -80,9 +80,11 @@ __device__ __forceinline__ void elem_geometry(const ElemIn<T>& in, Geo<T>& G) {
 
 // Element work of tile t on the values gathered in LDS (xs, node ids gid),
 // accumulated into ys (x.A x, which CG passes need, is taken afterwards from
-// the tile's node values: tile_scatter).  Work-item i takes the tile's element i: the layout has
-// interleaved the elements so that consecutive ones rarely share a node (few
-// LDS atomic collisions) while their loads stay coalesced.  PF: software
+// the tile's node values: tile_scatter).  Work-item i takes the tile's
+// element i, i + NT, ...: the layout has grouped the elements of each
+// half-wavefront and numbered the tile's interior nodes so that the nodes one
+// LDS instruction reaches rarely share a bank (and rarely coincide), while
+// the element loads stay coalesced.  PF: software
 // pipeline, the next element's connectivity, geometry and material are
 // loaded before the current one is computed (FP32; in FP64 the registers
 // would halve the occupancy).  STIFF / MASS / DYN: which operator terms are

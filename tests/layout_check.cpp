@@ -151,3 +151,43 @@ extern "C" int check_layout(int64_t nn, int64_t nt, int64_t nf, const double* xy
   stats[5] = L.n_interior;
   return 0;
 }
+
+// Modelled LDS bank cycles of the element work: for every wavefront of 64
+// element positions of a tile and every node k of the element, the largest
+// number of distinct dwords that one instruction sends to one of 64
+// dword-wide banks: out[0] for the FP32 node-value reads (dword 3 l + c),
+// out[1] for the FP64 accumulator atomics (dwords 2 (3 l + c) and the next),
+// averaged over instructions.  Tiles close at max_elems elements.
+extern "C" int bank_cycles(int64_t nn, int64_t nt, int64_t nf, const double* xyz, const int32_t* tet10,
+                           const int32_t* tri6, const int32_t* face_tet, const uint8_t* face_role, int32_t max_elems,
+                           double* out) {
+  HostLayout L;
+  sw::build_layout(nn, nt, nf, xyz, tet10, tri6, face_tet, face_role, L, sw::TILE_MAX_NODES, max_elems);
+  double rd = 0.0, at = 0.0;
+  int64_t n = 0;
+  for (int32_t t = 0; t < L.n_tiles; ++t) {
+    const int32_t e0 = L.tile_elem_off[t], ne = L.tile_elem_off[t + 1] - e0;
+    for (int32_t w0 = 0; w0 < ne; w0 += 64) {
+      const int nl = std::min(64, ne - w0);
+      for (int k = 0; k < 10; ++k)
+        for (int c = 0; c < 3; ++c) {
+          int rcnt[64] = {0}, acnt[64] = {0};
+          std::vector<int> seen;
+          for (int l = 0; l < nl; ++l) {
+            const int a = L.conn_loc[k * (size_t)L.tet_stride + e0 + w0 + l] + c;
+            acnt[(2 * a) % 64]++;
+            acnt[(2 * a + 1) % 64]++;
+            if (std::find(seen.begin(), seen.end(), a) != seen.end()) continue;
+            seen.push_back(a);
+            rcnt[a % 64]++;
+          }
+          rd += *std::max_element(rcnt, rcnt + 64);
+          at += *std::max_element(acnt, acnt + 64);
+          ++n;
+        }
+    }
+  }
+  out[0] = rd / n;
+  out[1] = at / n;
+  return 0;
+}
