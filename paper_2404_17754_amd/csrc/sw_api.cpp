@@ -19,6 +19,8 @@
 #include <cstring>
 #include <mutex>
 #include <string>
+#include <new>
+#include <stdexcept>
 #include <vector>
 
 #include "sw.h"
@@ -561,7 +563,21 @@ hipError_t up(const T* dst, const std::vector<T>& src, hipStream_t s) {
 
 }  // namespace
 
-extern "C" int sw_mesh_workspace_bytes(const sw_mesh_desc* d, size_t* bytes) {
+namespace {
+
+// The host-side layout allocates; no C++ exception may cross the C-ABI.
+template <typename F>
+int host_guarded(F&& f) {
+  try {
+    return f();
+  } catch (const std::bad_alloc&) {
+    return fail(SW_EINVAL, "host memory exhausted while building the mesh layout");
+  } catch (const std::exception& e) {
+    return fail(SW_EINVAL, "mesh layout: %s", e.what());
+  }
+}
+
+int mesh_workspace_bytes(const sw_mesh_desc* d, size_t* bytes) {
   if (!d || !bytes) return fail(SW_EINVAL, "NULL argument");
   int rc = validate_mesh(d);
   if (rc) return rc;
@@ -570,7 +586,7 @@ extern "C" int sw_mesh_workspace_bytes(const sw_mesh_desc* d, size_t* bytes) {
   return SW_OK;
 }
 
-extern "C" int sw_mesh_create(sw_ctx* ctx, const sw_mesh_desc* d, void* ws, size_t ws_bytes, sw_mesh** out) {
+int mesh_create(sw_ctx* ctx, const sw_mesh_desc* d, void* ws, size_t ws_bytes, sw_mesh** out) {
   if (!ctx || !out) return fail(SW_EINVAL, "NULL argument");
   int rc = validate_mesh(d);
   if (rc) return rc;
@@ -617,6 +633,16 @@ extern "C" int sw_mesh_create(sw_ctx* ctx, const sw_mesh_desc* d, void* ws, size
   sw_mesh* m = new sw_mesh{ctx, md, d->n_nodes, d->n_tets, d->n_faces, L.elem_order, L.node_u2i, L.node_i2u};
   *out = m;
   return SW_OK;
+}
+
+}  // namespace
+
+extern "C" int sw_mesh_workspace_bytes(const sw_mesh_desc* d, size_t* bytes) {
+  return host_guarded([&] { return mesh_workspace_bytes(d, bytes); });
+}
+
+extern "C" int sw_mesh_create(sw_ctx* ctx, const sw_mesh_desc* d, void* ws, size_t ws_bytes, sw_mesh** out) {
+  return host_guarded([&] { return mesh_create(ctx, d, ws, ws_bytes, out); });
 }
 
 extern "C" int sw_mesh_info(const sw_mesh* m, int32_t* n_tiles, int32_t* max_tile_nodes) {

@@ -23,6 +23,7 @@
 #include <cstdint>
 #include <cstring>
 #include <numeric>
+#include <system_error>
 #include <thread>
 #include <vector>
 
@@ -59,6 +60,7 @@ static inline uint64_t spread3(uint64_t v) {
 //    appears in, and the slots of each residue are handed out in order.
 // Reorders the tile's elements (conn columns, elem_order) and returns the new
 // local index of each interior node in newloc.
+static_assert(TILE_MAX_ELEMS <= 32 * 32, "a tile's half-wavefronts must fit the 32-bit group mask");
 static void spread_banks(int32_t e0, int32_t ne, int32_t nint, int32_t nt, int64_t stride, std::vector<uint16_t>& conn,
                          std::vector<int32_t>& elem_order, std::vector<int32_t>& newloc) {
   const int nh = (ne + 31) / 32, nw = (ne + 63) / 64;
@@ -351,14 +353,21 @@ void build_layout(int64_t n_nodes, int64_t n_tets, int64_t n_faces, const double
       }
     };
     const int nth = (int)std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
-    if (n_tiles < 4 * nth) {
-      run(0, n_tiles);
-    } else {
-      std::vector<std::thread> pool;
-      for (int k = 0; k < nth; ++k)
-        pool.emplace_back(run, (int32_t)((int64_t)n_tiles * k / nth), (int32_t)((int64_t)n_tiles * (k + 1) / nth));
-      for (auto& th : pool) th.join();
+    // chunk k of nth; a chunk whose thread cannot be started runs here
+    auto lo = [&](int k) { return (int32_t)((int64_t)n_tiles * k / nth); };
+    std::vector<std::thread> pool;
+    int started = 0;
+    if (n_tiles >= 4 * nth) {
+      for (; started < nth; ++started) {
+        try {
+          pool.emplace_back(run, lo(started), lo(started + 1));
+        } catch (const std::system_error&) {
+          break;
+        }
+      }
     }
+    run(lo(started), n_tiles);
+    for (auto& th : pool) th.join();
   }
   // --- coordinates in internal order
   L.xyz.resize(3 * (size_t)n_nodes);
