@@ -494,8 +494,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=3, help="untimed steps on a separate copy of the case")
     ap.add_argument("--config", default="large")
     ap.add_argument("--guess", default="proj", choices=["zero", "poly", "mlp", "proj", "proj_mlp"])
-    ap.add_argument("--precision", default="mixed", choices=["mixed", "flex"],
-                    help="outer solver around the FP32 inner CG: iterative refinement or flexible CG")
+    ap.add_argument("--precision", default="mixed", choices=["mixed", "flex", "fp16"],
+                    help="outer solver around the FP32 inner CG: iterative refinement, flexible CG, or "
+                         "refinement with the inner CG's direction stored in 16 bits")
     ap.add_argument("--proj-dim", type=int, default=6, help="past increments spanned by the projection guess")
     ap.add_argument("--inner-rtol", type=float, default=0.0,
                     help="floor of the inner FP32 CG tolerance (0 = the library default)")
@@ -644,9 +645,10 @@ def main():
         legs = [(g, dict(precision=args.precision, guess=g, proj_dim=args.proj_dim,
                          net=net if g in LEARNED else None))
                 for g in ("poly", "mlp", "proj", "proj_mlp") if g != args.guess and (g not in LEARNED or net is not None)]
-        other = "flex" if args.precision == "mixed" else "mixed"
-        legs.append((f"{other}_{args.guess}", dict(precision=other, guess=args.guess, proj_dim=args.proj_dim,
-                                                    net=net if args.guess in LEARNED else None)))
+        for other in ("mixed", "flex", "fp16"):
+            if other != args.precision:
+                legs.append((f"{other}_{args.guess}", dict(precision=other, guess=args.guess, proj_dim=args.proj_dim,
+                                                            net=net if args.guess in LEARNED else None)))
         legs.append(("plain_fp64", dict(precision="fp64", guess="zero")))
         for name, kw in legs:
             ms, pit, prel, pst = timed_window(sw, ctx, gmesh, case, cmp_n, **kw)
@@ -694,12 +696,14 @@ def main():
         "metric": METRIC, "value": round(value, 3), "unit": "case-timesteps/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 3),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "f32+f64", "data": "synthetic",
+        "dtype": "bf16+f32+f64" if args.precision == "fp16" else "f32+f64", "data": "synthetic",
         "config": {"workload": (f"{args.config}: {cfg.box[0]:.0f}x{cfg.box[1]:.0f}x{cfg.box[2]:.0f} m, "
                                 f"{cfg.cell:g} m cells, {mesh.n_tets} P2 tets, {dof} DOF, dt {cfg.dt} s, "
                                 f"Ricker {cfg.freqs} Hz, one case, steps 0-{args.steps} from rest"),
-                   "precision": ("FP32 inner CG in FP64 refinement" if args.precision == "mixed"
-                                 else "FP32 inner CG preconditioning FP64 flexible CG"),
+                   "precision": {"mixed": "FP32 inner CG in FP64 refinement",
+                                 "flex": "FP32 inner CG preconditioning FP64 flexible CG",
+                                 "fp16": "FP32 inner CG with a bfloat16 direction vector in FP64 refinement"}[
+                                     args.precision],
                    "guess": args.guess, "rtol": 1e-8,
                    "parallelism": "single GPU"},
         "cg_iters_per_step": float(np.mean(it)), "refinement_rounds_per_step": round(stats["ir_outer"] / stats["steps"], 3),

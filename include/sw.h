@@ -83,11 +83,15 @@ enum {
   SW_FP64 = 0,        /* FP64 preconditioned CG on the FP64 operator */
   SW_MIXED_FP32 = 1,  /* FP32 inner CG (FP32 operator, FP32 vectors) inside FP64
                          iterative refinement; FP64 true residual and update */
-  SW_MIXED_FP32_FLEX = 2  /* the same FP32 inner CG as the variable preconditioner of
+  SW_MIXED_FP32_FLEX = 2, /* the same FP32 inner CG as the variable preconditioner of
                              an FP64 flexible CG (one previous direction kept; the
                              CG with variable preconditioning of Section 3); FP64
                              true residual confirms convergence.  Single cases only
                              (batches march SW_MIXED_FP32 lanes) */
+  SW_MIXED_FP16 = 3       /* SW_MIXED_FP32 with the inner CG's direction vector stored
+                             in 16 bits (bfloat16, FP32 arithmetic and accumulation):
+                             the operator pass gathers it, and x += alpha p and
+                             p = z + beta p use the stored values.  Single cases only */
 };
 
 /* initial guess of each step's solve */
@@ -202,7 +206,7 @@ typedef struct {
   double ray_beta;       /* Rayleigh stiffness coefficient (s), >= 0 */
   double rtol;           /* relative residual target, in (0, 1) */
   int32_t max_iter;      /* CG iteration cap per step (inner + outer) */
-  int32_t precision;     /* SW_FP64, SW_MIXED_FP32 or SW_MIXED_FP32_FLEX */
+  int32_t precision;     /* SW_FP64, SW_MIXED_FP32, SW_MIXED_FP32_FLEX or SW_MIXED_FP16 */
   int32_t guess;         /* SW_GUESS_* */
   int32_t poly_order;    /* 0..3, used by SW_GUESS_POLY / SW_GUESS_MLP */
   double inner_rtol;     /* mixed precisions: floor of the inner CG relative tolerance (0 = default 1e-4) */

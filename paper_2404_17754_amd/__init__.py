@@ -24,7 +24,7 @@ from . import _lib as L
 from ._lib import SwError  # noqa: F401
 
 PRECISIONS = {"fp64": L.SW_FP64, "mixed": L.SW_MIXED_FP32, "mixed_fp32": L.SW_MIXED_FP32,
-              "flex": L.SW_MIXED_FP32_FLEX}
+              "flex": L.SW_MIXED_FP32_FLEX, "fp16": L.SW_MIXED_FP16}
 GUESSES = {"zero": L.SW_GUESS_ZERO, "poly": L.SW_GUESS_POLY, "mlp": L.SW_GUESS_MLP, "proj": L.SW_GUESS_PROJ,
            "proj_mlp": L.SW_GUESS_PROJ_MLP}
 OPS = {"M": L.SW_OP_M, "K": L.SW_OP_K, "Cabs": L.SW_OP_CABS, "A": L.SW_OP_A}

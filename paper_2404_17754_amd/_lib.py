@@ -10,7 +10,7 @@ LIB_PATH = os.path.join(_HERE, "libsw.so")
 
 SW_OK, SW_EINVAL, SW_ENOWS, SW_EMESH, SW_ENOCONV, SW_EHIP, SW_ESTATE = 0, -1, -2, -3, -4, -5, -6
 SW_FLAG_NOCONV, SW_FLAG_NONFINITE, SW_FLAG_GUESS_FALLBACK = 1, 2, 4
-SW_FP64, SW_MIXED_FP32, SW_MIXED_FP32_FLEX = 0, 1, 2
+SW_FP64, SW_MIXED_FP32, SW_MIXED_FP32_FLEX, SW_MIXED_FP16 = 0, 1, 2, 3
 SW_GUESS_ZERO, SW_GUESS_POLY, SW_GUESS_MLP, SW_GUESS_PROJ, SW_GUESS_PROJ_MLP = 0, 1, 2, 3, 4
 SW_OP_M, SW_OP_K, SW_OP_CABS, SW_OP_A = 1, 2, 4, 8
 MLP_NPARAM, MLP_ROW = 4929, 12

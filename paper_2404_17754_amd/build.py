@@ -16,7 +16,7 @@ ROOT = os.path.dirname(PKG)
 LIB = os.path.join(PKG, "libsw.so")
 
 SOURCES = ["sw_tile.hip", "sw_kernels.hip", "sw_mlp.hip", "sw_proj.hip", "sw_fit.hip", "sw_mesh.cpp", "sw_api.cpp"]
-HEADERS = ["sw_elem.h", "sw_internal.h", "sw_device.h", "sw_layout.h", "sw_linalg.h"]
+HEADERS = ["sw_elem.h", "sw_internal.h", "sw_device.h", "sw_layout.h", "sw_linalg.h", "sw_bf16.h"]
 
 HIPCC_FLAGS = [
     "-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",

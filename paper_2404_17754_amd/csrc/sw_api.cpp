@@ -177,6 +177,7 @@ struct sw_case {
   double *diag6, *pinv64, *pmax;
   __half* pinv16;  // block-Jacobi inverse / its largest diagonal entry, FP16 (FP32 CG)
   float *r32, *d32, *z32, *p32, *q32;
+  uint16_t* p16;  // SW_MIXED_FP16: the inner CG's direction in bfloat16 (else null)
   // flexible outer CG (SW_MIXED_FP32_FLEX): directions and their images of
   // the current and the previous iteration (by parity), dot products
   double *fp[2] = {nullptr, nullptr}, *fq[2] = {nullptr, nullptr}, *fdots = nullptr;
@@ -677,6 +678,7 @@ static size_t case_layout(const sw_mesh* m, const sw_case_desc* d, Carver& cv, s
   float* f32[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
   if (mixed)
     for (int i = 0; i < 5; ++i) f32[i] = cv.take<float>(nd);
+  uint16_t* p16 = d->precision == SW_MIXED_FP16 ? cv.take<uint16_t>(nd) : nullptr;
   double* fvec[4] = {nullptr, nullptr, nullptr, nullptr};
   double* fdots = nullptr;
   if (flex) {
@@ -735,6 +737,7 @@ static size_t case_layout(const sw_mesh* m, const sw_case_desc* d, Carver& cv, s
     c->z32 = f32[2];
     c->p32 = f32[3];
     c->q32 = f32[4];
+    c->p16 = p16;
     c->fp[0] = fvec[0];
     c->fp[1] = fvec[1];
     c->fq[0] = fvec[2];
@@ -769,7 +772,8 @@ static int validate_case(const sw_mesh* m, const sw_case_desc* d) {
   if (!(d->ray_alpha >= 0.0) || !(d->ray_beta >= 0.0)) return fail(SW_EINVAL, "Rayleigh coefficients must be >= 0");
   if (!(d->rtol > 0.0 && d->rtol < 1.0)) return fail(SW_EINVAL, "rtol must be in (0, 1)");
   if (d->max_iter <= 0) return fail(SW_EINVAL, "max_iter must be > 0");
-  if (d->precision != SW_FP64 && d->precision != SW_MIXED_FP32 && d->precision != SW_MIXED_FP32_FLEX)
+  if (d->precision != SW_FP64 && d->precision != SW_MIXED_FP32 && d->precision != SW_MIXED_FP32_FLEX &&
+      d->precision != SW_MIXED_FP16)
     return fail(SW_EINVAL, "unknown precision %d", d->precision);
   if (d->guess != SW_GUESS_ZERO && d->guess != SW_GUESS_POLY && d->guess != SW_GUESS_MLP &&
       d->guess != SW_GUESS_PROJ && d->guess != SW_GUESS_PROJ_MLP)
@@ -865,6 +869,21 @@ int apply_f32(sw_case* c, int op, const float* x, float* y, CgCtl* ctl, int iter
 }
 int apply_f32(sw_case* c, int op, const float* x, float* y, CgCtl* ctl, int iter) {
   return apply_f32(c, op, x, y, ctl, iter, c->ctx->stream);
+}
+
+// y = A x with x in bfloat16 (the SW_MIXED_FP16 inner CG's direction)
+int apply_f32_h(sw_case* c, const uint16_t* x, float* y, CgCtl* ctl, int iter, hipStream_t s) {
+  TileArgs<float> A{};
+  A.sM = (float)c->cM;
+  A.sK = (float)c->cK;
+  A.sC = (float)c->cC;
+  A.x1h = x;
+  A.a1 = 1.0f;
+  A.y = y;
+  A.n_mat = c->n_mat;
+  launch_tile_f32(c->mesh->dev, c->emat, c->mats, A, ctl, iter, case_grid_cap(c), s);
+  LAUNCHED();
+  return SW_OK;
 }
 
 // Right-hand side of step c->step -> c->step + 1 (internal order) into y:
@@ -973,6 +992,7 @@ extern "C" int sw_case_create(sw_ctx* ctx, sw_mesh* m, const sw_case_desc* d, vo
   if (c->precision != SW_FP64) {
     float* zf[] = {c->r32, c->d32, c->z32, c->p32, c->q32};
     for (float* zv : zf) launch_fill_f32(nd, zv, 0.0f, s);
+    if (c->p16) HIPX(hipMemsetAsync(c->p16, 0, 2 * (size_t)nd, s));
   }
   if (c->precision == SW_MIXED_FP32_FLEX) {
     double* zf[] = {c->fp[0], c->fp[1], c->fq[0], c->fq[1]};
@@ -1101,14 +1121,17 @@ int cg_iteration(sw_case* c, CgCtl* ctl, int iter, int iter_abs, hipStream_t s, 
   int rc;
   if (F32) {
     int ev = prof ? prof_begin(cx, SW_PROF_TILE_F32) : -1;
-    rc = apply_f32(c, SW_OP_A, c->p32, c->q32, ctl, iter, s);
+    rc = c->p16 ? apply_f32_h(c, c->p16, c->q32, ctl, iter, s) : apply_f32(c, SW_OP_A, c->p32, c->q32, ctl, iter, s);
     if (prof) prof_end(cx, ev);
     if (rc) return rc;
     ev = prof ? prof_begin(cx, SW_PROF_UPDATE_F32) : -1;
     launch_cg_update_f32(nn, c->mesh->dev.n_interior, iter & 1, c->pinv16, c->r32, c->z32, c->q32, ctl, s);
     if (prof) prof_end(cx, ev);
     ev = prof ? prof_begin(cx, SW_PROF_DIR_F32) : -1;
-    launch_cg_dir_f32(nn, iter & 1, iter_abs, c->max_iter, c->z32, c->p32, c->d32, ctl, s);
+    if (c->p16)
+      launch_cg_dir_h(nn, iter & 1, iter_abs, c->max_iter, c->z32, c->p16, c->d32, ctl, s);
+    else
+      launch_cg_dir_f32(nn, iter & 1, iter_abs, c->max_iter, c->z32, c->p32, c->d32, ctl, s);
     if (prof) prof_end(cx, ev);
   } else {
     int ev = prof ? prof_begin(cx, SW_PROF_TILE_F64) : -1;
@@ -1528,7 +1551,7 @@ int solve_step(sw_case* c, int* iters, int* outer, double* relres, int* flags) {
       launch_fill_f64(sizeof(CgCtl) / 8, (double*)c->ctl32, 0.0, s);
       launch_fill_f64(1, &c->ctl32->bb, 1.0, s);
       launch_ctl_prepare(c->ctl32, tol, s);
-      launch_ir_begin(nn, c->r, c->pinv16, c->r32, c->z32, c->p32, c->d32, c->ctl64, c->ctl32, s);
+      launch_ir_begin(nn, c->r, c->pinv16, c->r32, c->z32, c->p32, c->p16, c->d32, c->ctl64, c->ctl32, s);
       LAUNCHED();
       int it = 0;
       rc = cg_loop<true>(c, c->ctl32, *iters, inner_est - 1, &it);

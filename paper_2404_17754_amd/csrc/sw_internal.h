@@ -79,6 +79,9 @@ template <typename T>
 struct TileArgs {
   T sM, sK, sC;
   const T* x1;
+  // FP32 passes of the SW_MIXED_FP16 inner CG: the input in bfloat16 in
+  // place of x1 (a1 = 1, no x2); null otherwise
+  const uint16_t* x1h;
   const T* x2;
   T a1, a2;
   const T* xf;
@@ -220,6 +223,9 @@ void launch_cg_dir_f64(int64_t n_nodes, int par, int iter_abs, int max_iter, con
                        CgCtl* ctl, hipStream_t s);
 void launch_cg_dir_f32(int64_t n_nodes, int par, int iter_abs, int max_iter, const float* z, float* p, float* x,
                        CgCtl* ctl, hipStream_t s);
+// SW_MIXED_FP16 inner CG: the direction p16 in bfloat16 (FP32 arithmetic)
+void launch_cg_dir_h(int64_t n_nodes, int par, int iter_abs, int max_iter, const float* z, uint16_t* p16, float* x,
+                     CgCtl* ctl, hipStream_t s);
 
 // ctl setup: bb must already be in ctl; sets tol2 = rtol^2 bb, clears the rest
 void launch_ctl_prepare(CgCtl* ctl, double rtol, hipStream_t s);
@@ -229,9 +235,10 @@ void launch_norm2(int64_t n, const double* x, double* out, hipStream_t s, bool d
 // r = b - q, rr_true -> ctl (det: one workgroup)
 void launch_true_residual(int64_t n, const double* b, const double* q, double* r, CgCtl* ctl, hipStream_t s,
                           bool det = false);
-// r32 = r64 / ||r64|| (||r64|| from ctl->rr_true, kept in ctl->scale)
+// r32 = r64 / ||r64|| (||r64|| from ctl->rr_true, kept in ctl->scale), z32 and
+// the first direction (into p16 in bfloat16 when given, else p32), d32 = 0
 void launch_ir_begin(int64_t n_nodes, const double* r64, const __half* P, float* r32, float* z32, float* p32,
-                     float* d32, CgCtl* ctl64, CgCtl* ctl32, hipStream_t s);
+                     uint16_t* p16, float* d32, CgCtl* ctl64, CgCtl* ctl32, hipStream_t s);
 // x64 += ctl->scale * d32
 void launch_ir_update(int64_t n, double* x64, const float* d32, const CgCtl* ctl, hipStream_t s);
 // flexible outer CG (see sw_kernels.hip)

@@ -9,6 +9,7 @@
 // FP64 atomic per workgroup into a device control block.
 #include <hip/hip_runtime.h>
 
+#include "sw_bf16.h"
 #include "sw_device.h"
 #include "sw_internal.h"
 
@@ -213,6 +214,53 @@ __device__ __forceinline__ void cg_dir_body(int64_t n, int par, int iter_abs, in
   }
 }
 
+// Direction kernel of the SW_MIXED_FP16 inner CG: as cg_dir_body in FP32
+// arithmetic, with the direction stored in bfloat16 (p16).  The operator
+// pass, x += alpha p and p = z + beta p all use the stored values, so the
+// iteration is CG along the rounded directions; the rounding costs
+// conjugacy, which the FP64 refinement around the inner solve absorbs.
+__global__ __launch_bounds__(TPB) void k_cg_dir_h(int64_t n, int par, int iter_abs, int max_iter,
+                                                  const float* __restrict__ z, uint16_t* __restrict__ p16,
+                                                  float* __restrict__ x, CgCtl* ctl) {
+  if (!ctl->live) return;
+  if (iter_abs < 0) iter_abs = ctl->iter_cur;
+  const double rr = slot_sum<NSLOT>(ctl->rr[par ^ 1]);
+  const bool stop = !(rr > ctl->tol2) || (iter_abs + 1 >= max_iter);  // NaN stops too
+  const float alpha = (float)ctl->alpha;
+  const float beta = (float)(slot_sum<NSLOT>(ctl->rz[par ^ 1]) / slot_sum<NSLOT>(ctl->rz[par]));
+  if (blockIdx.x == 0) {
+    if (threadIdx.x == 0) {
+      ctl->iters = iter_abs + 1;
+      if (stop) ctl->done = 1;
+    }
+    if (threadIdx.x < NSLOT) ctl->pAp[threadIdx.x] = 0.0;
+  }
+  // four values per work-item (8-byte direction, 16-byte x and z accesses)
+  typedef float f32x4 __attribute__((ext_vector_type(4)));
+  const int64_t n3 = 3 * n, n4 = n3 / 4;
+  const f32x4* __restrict__ z4 = reinterpret_cast<const f32x4*>(z);
+  f32x4* __restrict__ x4 = reinterpret_cast<f32x4*>(x);
+  uint2* __restrict__ p4 = reinterpret_cast<uint2*>(p16);
+  for (int64_t i = (int64_t)blockIdx.x * TPB + threadIdx.x; i < n4; i += (int64_t)gridDim.x * TPB) {
+    const uint2 ph = p4[i];
+    const f32x4 pv = {bf16_value((uint16_t)(ph.x & 0xffffu)), bf16_value((uint16_t)(ph.x >> 16)),
+                      bf16_value((uint16_t)(ph.y & 0xffffu)), bf16_value((uint16_t)(ph.y >> 16))};
+    f32x4 xv = __builtin_nontemporal_load(x4 + i);
+    xv += alpha * pv;
+    __builtin_nontemporal_store(xv, x4 + i);
+    if (!stop) {
+      const f32x4 q = __builtin_nontemporal_load(z4 + i) + beta * pv;
+      p4[i] = make_uint2((uint32_t)bf16_round(q.x) | ((uint32_t)bf16_round(q.y) << 16),
+                         (uint32_t)bf16_round(q.z) | ((uint32_t)bf16_round(q.w) << 16));
+    }
+  }
+  for (int64_t i = 4 * n4 + (int64_t)blockIdx.x * TPB + threadIdx.x; i < n3; i += (int64_t)gridDim.x * TPB) {
+    const float pv = bf16_value(p16[i]);
+    x[i] += alpha * pv;
+    if (!stop) p16[i] = bf16_round(z[i] + beta * pv);
+  }
+}
+
 template <typename T, typename PT>
 __global__ __launch_bounds__(TPB) void k_cg_init(int64_t n, const T* b, const T* q, const PT* P, T* r, T* z, T* p,
                                                  T* qz, CgCtl* ctl) {
@@ -246,6 +294,10 @@ void launch_cg_update_f64(int64_t n, int par, const double* P, double* r, double
 void launch_cg_update_f32(int64_t n, int64_t n_int, int par, const __half* P, float* r, float* z, float* q,
                           CgCtl* ctl, hipStream_t s) {
   hipLaunchKernelGGL((k_cg_update<float, __half>), dim3(vgrid(n)), dim3(TPB), 0, s, n, n_int, par, P, r, z, q, ctl);
+}
+void launch_cg_dir_h(int64_t n, int par, int iter_abs, int max_iter, const float* z, uint16_t* p16, float* x,
+                     CgCtl* ctl, hipStream_t s) {
+  hipLaunchKernelGGL(k_cg_dir_h, dim3(vgrid(n)), dim3(TPB), 0, s, n, par, iter_abs, max_iter, z, p16, x, ctl);
 }
 void launch_cg_dir_f64(int64_t n, int par, int iter_abs, int max_iter, const double* z, double* p, double* x,
                        CgCtl* ctl, hipStream_t s) {
@@ -319,7 +371,8 @@ void launch_true_residual(int64_t n, const double* b, const double* q, double* r
 __global__ __launch_bounds__(TPB) void k_ir_begin(int64_t n_nodes, const double* __restrict__ r64,
                                                   const __half* __restrict__ P, float* __restrict__ r32,
                                                   float* __restrict__ z32, float* __restrict__ p32,
-                                                  float* __restrict__ d32, CgCtl* ctl64, CgCtl* ctl32) {
+                                                  uint16_t* __restrict__ p16, float* __restrict__ d32, CgCtl* ctl64,
+                                                  CgCtl* ctl32) {
   __shared__ double sh[2 * TPB / 64];
   const double nr = sqrt(ctl64->rr_true);
   const double inv = nr > 0.0 ? 1.0 / nr : 0.0;
@@ -334,7 +387,10 @@ __global__ __launch_bounds__(TPB) void k_ir_begin(int64_t n_nodes, const double*
     for (int c = 0; c < 3; ++c) {
       r32[3 * i + c] = rv[c];
       z32[3 * i + c] = zv[c];
-      p32[3 * i + c] = zv[c];
+      if (p16)
+        p16[3 * i + c] = bf16_round(zv[c]);
+      else
+        p32[3 * i + c] = zv[c];
       d32[3 * i + c] = 0.0f;
       rz += (double)rv[c] * (double)zv[c];
       rr += (double)rv[c] * (double)rv[c];
@@ -347,9 +403,9 @@ __global__ __launch_bounds__(TPB) void k_ir_begin(int64_t n_nodes, const double*
   }
 }
 void launch_ir_begin(int64_t n_nodes, const double* r64, const __half* P, float* r32, float* z32, float* p32,
-                     float* d32, CgCtl* ctl64, CgCtl* ctl32, hipStream_t s) {
-  hipLaunchKernelGGL(k_ir_begin, dim3(vgrid(n_nodes)), dim3(TPB), 0, s, n_nodes, r64, P, r32, z32, p32, d32, ctl64,
-                     ctl32);
+                     uint16_t* p16, float* d32, CgCtl* ctl64, CgCtl* ctl32, hipStream_t s) {
+  hipLaunchKernelGGL(k_ir_begin, dim3(vgrid(n_nodes)), dim3(TPB), 0, s, n_nodes, r64, P, r32, z32, p32, p16, d32,
+                     ctl64, ctl32);
 }
 
 __global__ __launch_bounds__(TPB) void k_ir_update(int64_t n, double* __restrict__ x, const float* __restrict__ d,

@@ -9,6 +9,7 @@
 // from 30 per tet to about 2 per tet, and the ones left are address-sorted.
 #include <hip/hip_runtime.h>
 
+#include "sw_bf16.h"
 #include "sw_device.h"
 #include "sw_elem.h"
 #include "sw_internal.h"
@@ -29,6 +30,26 @@ namespace sw {
 template <typename U>
 __device__ __forceinline__ U ldc(const U* p, int64_t i) {
   return ((const __attribute__((address_space(4))) U*)p)[i];
+}
+
+// Input value i of a pass (x1), and of its dashpot term (xf): in the 16-bit
+// passes of the SW_MIXED_FP16 inner CG both come from the bfloat16 input
+// x1h (x1 and xf null), so every term of A acts on the same stored values.
+template <typename T>
+__device__ __forceinline__ T x1_at(const TileArgs<T>& A, int64_t i) {
+  return A.x1[i];
+}
+template <>
+__device__ __forceinline__ float x1_at<float>(const TileArgs<float>& A, int64_t i) {
+  return A.x1h ? bf16_value(A.x1h[i]) : A.x1[i];
+}
+template <typename T>
+__device__ __forceinline__ T xf_at(const TileArgs<T>& A, int64_t i) {
+  return A.xf[i];
+}
+template <>
+__device__ __forceinline__ float xf_at<float>(const TileArgs<float>& A, int64_t i) {
+  return A.x1h ? bf16_value(A.x1h[i]) : A.xf[i];
 }
 
 // Per-element inputs fetched from global memory: tile-local connectivity
@@ -206,7 +227,7 @@ __device__ __forceinline__ void tile_elements(const MeshDev& m, const uint8_t* _
 #pragma unroll
         for (int k = 0; k < 6; ++k) {
 #pragma unroll
-          for (int c = 0; c < 3; ++c) w[k][c] = A.xf[3 * gn[k] + c];
+          for (int c = 0; c < 3; ++c) w[k][c] = xf_at(A, 3 * gn[k] + c);
         }
         const T n[3] = {(T)g.n[0], (T)g.n[1], (T)g.n[2]};
         face_dashpot_apply<T>(n, (T)g.area, (T)mt.zp, (T)mt.zs, A.sC, w, out);
@@ -321,7 +342,7 @@ __device__ __forceinline__ void tile_body(const MeshDev& m, const uint8_t* __res
   // scatter)
   auto gather = [&] {
     for (int k = threadIdx.x; k < 3 * nint; k += NT) {
-      T v = A.a1 * A.x1[ib3 + k];
+      T v = A.a1 * x1_at(A, ib3 + k);
       if (A.x2 != nullptr) v += A.a2 * A.x2[ib3 + k];
       xs[k] = v;
       ys[k] = 0.0;
@@ -332,7 +353,7 @@ __device__ __forceinline__ void tile_body(const MeshDev& m, const uint8_t* __res
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
         const int64_t gi = 3 * (int64_t)g + c;
-        T v = A.a1 * A.x1[gi];
+        T v = A.a1 * x1_at(A, gi);
         if (A.x2 != nullptr) v += A.a2 * A.x2[gi];
         xs[3 * j + c] = v;
         ys[3 * j + c] = 0.0;
@@ -435,7 +456,7 @@ constexpr int PIPE_MATS = 32;
 // XCDs round-robin) and takes its tiles from that XCD's contiguous eighth of
 // the tile list, so neighbouring tiles, which share nodes, meet in the same
 // L2.  NPT * NT must cover the largest tile; at most PIPE_MATS materials.
-template <int NT, int NPT, bool PF>
+template <int NT, int NPT, bool PF, bool H16 = false>
 __global__ __launch_bounds__(NT) void k_tile_pipe(MeshDev m, const uint8_t* __restrict__ emat,
                                                    const MatDev* __restrict__ mats, TileArgs<float> A, CgCtl* ctl,
                                                    int iter) {
@@ -460,7 +481,15 @@ __global__ __launch_bounds__(NT) void k_tile_pipe(MeshDev m, const uint8_t* __re
   const int hi = (int)(((int64_t)m.n_tiles * (xcd + 1)) >> 3);
   int t = lo + slot;
   if (t >= hi) return;
+  // the input: FP32, or bfloat16 (H16: the 16-bit passes)
   const float* __restrict__ x = A.x1;
+  const uint16_t* __restrict__ xh = A.x1h;
+  auto in = [&](int64_t i) -> float {
+    if constexpr (H16)
+      return bf16_value(xh[i]);
+    else
+      return x[i];
+  };
   // the material table, rounded to FP32, into LDS
   __shared__ float matl[3 * PIPE_MATS];
   for (int i = threadIdx.x; i < A.n_mat; i += NT) {
@@ -476,7 +505,7 @@ __global__ __launch_bounds__(NT) void k_tile_pipe(MeshDev m, const uint8_t* __re
       gid[j] = g;
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
-        xs[3 * j + c] = x[3 * (int64_t)g + c];
+        xs[3 * j + c] = in(3 * (int64_t)g + c);
         ys[3 * j + c] = 0.0;
       }
     }
@@ -511,7 +540,7 @@ __global__ __launch_bounds__(NT) void k_tile_pipe(MeshDev m, const uint8_t* __re
       for (int q = 0; q < NPT; ++q) {
         const int64_t g3 = 3 * (int64_t)pg[q];
 #pragma unroll
-        for (int c = 0; c < 3; ++c) px[q][c] = x[g3 + c];
+        for (int c = 0; c < 3; ++c) px[q][c] = in(g3 + c);
       }
     };
     tile_elements<float, NT, PF, true, false>(m, emat, mats, matl, A, t, gid, xs, ys, gather_next);
@@ -700,8 +729,12 @@ static void launch_tile(const MeshDev& m, const uint8_t* emat, const MatDev* mat
   if constexpr (sizeof(T) == 4) {
     if (iter >= 0 && a.x2 == nullptr && a.a1 == 1.0f && a.accumulate == 0 && a.vin == nullptr &&
         m.max_tile_nodes <= PIPE_NT * PIPE_NPT && a.n_mat >= 1 && a.n_mat <= PIPE_MATS) {
-      hipLaunchKernelGGL((k_tile_pipe<PIPE_NT, PIPE_NPT, SW_PIPE_PF>), dim3(pipe_grid(m.n_tiles, grid_cap)), dim3(PIPE_NT),
-                         lds, s, m, emat, mats, a, ctl, iter);
+      if (a.x1h)
+        hipLaunchKernelGGL((k_tile_pipe<PIPE_NT, PIPE_NPT, SW_PIPE_PF, true>), dim3(pipe_grid(m.n_tiles, grid_cap)),
+                           dim3(PIPE_NT), lds, s, m, emat, mats, a, ctl, iter);
+      else
+        hipLaunchKernelGGL((k_tile_pipe<PIPE_NT, PIPE_NPT, SW_PIPE_PF>), dim3(pipe_grid(m.n_tiles, grid_cap)),
+                           dim3(PIPE_NT), lds, s, m, emat, mats, a, ctl, iter);
       return;
     }
   }

@@ -23,7 +23,7 @@ import sys
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 # the sources that define the operator kernels and the layout they read
-KERNEL_SOURCES = ["sw_tile.hip", "sw_elem.h", "sw_device.h", "sw_layout.h", "sw_mesh.cpp"]
+KERNEL_SOURCES = ["sw_tile.hip", "sw_elem.h", "sw_device.h", "sw_layout.h", "sw_mesh.cpp", "sw_bf16.h"]
 
 
 def kernel_hash():
