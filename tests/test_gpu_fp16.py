@@ -91,7 +91,13 @@ def test_fp16_graph_replays_match_direct_launches(sw, ctx, small):
         _check(gc, ref, case.n_steps)
     ctx.set_graphs(True)
     (w0, it0), (w1, it1) = out[False], out[True]
-    assert np.abs(it0 - it1).max() <= 1 and _rel(w1, w0) < 1e-7
+    # the atomic sums add in a different order on every run; rounding p to
+    # bfloat16 can turn such a last-bit difference into a different rounded
+    # direction, and a step near its threshold into another refinement
+    # round's few iterations (measured: one step 53 against 49, totals 5
+    # apart in 2785), where FP32 directions differ by one at most
+    assert np.abs(it0 - it1).max() <= 8 and abs(int(it0.sum()) - int(it1.sum())) <= 0.01 * it0.sum(), (it0, it1)
+    assert _rel(w1, w0) < 1e-7
 
 
 def test_batch_rejects_fp16_cases(sw, ctx, small):
