@@ -104,3 +104,26 @@ def test_batch_rejects_fp16_cases(sw, ctx, small):
     mesh, case, _, gm = small
     with pytest.raises(sw.SwError, match="SW_EINVAL"):
         sw.Batch(ctx, [sw.Case(ctx, gm, case, precision="fp16", guess="proj")])
+
+
+def test_fp16_with_learned_guess_autotune_and_checkpoint(sw, ctx, small):
+    """The 16-bit mode with the learned guess (the network's initial
+    parameters: extrapolation through the network's kernels), after the
+    set-up autotuner, and resumed from a checkpoint taken mid-march: the
+    resumed waveforms match the oracle's over the same steps."""
+    mesh, case, ref, gm = small
+    net = sw.Mlp(ctx, seed=1)
+    gc = sw.Case(ctx, gm, case, precision="fp16", guess="mlp")
+    gc.attach_mlp(net)
+    gc.autotune(reps=2)
+    half = case.n_steps // 2
+    gc.step(half)
+    u, v, a, st = gc.get_state()
+    gr = sw.Case(ctx, gm, case, precision="fp16", guess="mlp")
+    gr.attach_mlp(net)
+    gr.set_state(u, v, a, st)
+    gr.step(case.n_steps - half)
+    w = gr.waveforms(half, case.n_steps - half)
+    assert _rel(w, ref[half:]) < 1e-6
+    _, rel = gr.step_log(half, case.n_steps - half)
+    assert np.all(rel <= 1e-8) and not gr.stats()["flags"] & 3
