@@ -2,9 +2,10 @@
 //
 // 1. Elements are ordered along a Morton (Z-order) curve of their centroids,
 //    which groups spatial neighbours whatever the input numbering.
-// 2. Consecutive elements form tiles, closed when the next element would
-//    exceed TILE_MAX_NODES distinct nodes or TILE_MAX_ELEMS elements, so a
-//    tile's node values and accumulators fit in one workgroup's LDS.
+// 2. Tiles come from recursive coordinate bisection of the element
+//    centroids into compact parts of at most TILE_MAX_ELEMS elements and
+//    TILE_MAX_NODES distinct nodes, so a tile's node values and accumulators
+//    fit in one workgroup's LDS; each part keeps the Morton order.
 // 3. Nodes are renumbered: every tile's interior nodes (touched by no other
 //    tile), tile by tile, then all shared nodes in the order tiles first
 //    touch them.  A tile's interior nodes are thus one contiguous id range
@@ -195,41 +196,76 @@ void build_layout(int64_t n_nodes, int64_t n_tets, int64_t n_faces, const double
     key[e] = {m, (int32_t)e};
   }
   std::sort(key.begin(), key.end());
-  // --- tiles (node-capped)
+  // --- tiles: recursive coordinate bisection of the element centroids.  A
+  // range is cut across its longest extent at the multiple of max_elems
+  // nearest its middle, so parts are compact blocks of max_elems elements
+  // (fewer nodes shared between tiles than runs of the Morton curve); a part
+  // over the node cap is halved again.  Parts are emitted depth first
+  // (neighbouring tiles stay neighbours in the list), each in Morton order.
   std::vector<int32_t> mark(n_nodes, -1);
-  L.elem_order.resize(n_tets);
-  L.tile_elem_off.push_back(0);
-  int32_t tile = 0, tile_nodes = 0, tile_elems = 0;
-  for (int64_t i = 0; i < n_tets; ++i) {
-    const int32_t e = key[i].second;
-    int add = 0;
-    for (int k = 0; k < 10; ++k) {
-      const int32_t n = tet10[10 * (int64_t)e + k];
-      bool dup = mark[n] == tile;
-      for (int j = 0; j < k && !dup; ++j) dup = tet10[10 * (int64_t)e + j] == n;
-      add += dup ? 0 : 1;
-    }
-    if (tile_elems > 0 && (tile_nodes + add > max_nodes || tile_elems + 1 > max_elems)) {
-      L.tile_elem_off.push_back((int32_t)i);
-      ++tile;
-      tile_nodes = 0;
-      tile_elems = 0;
-      add = 10;  // recount for the new tile
-      int distinct = 0;
-      for (int k = 0; k < 10; ++k) {
-        bool dup = false;
-        for (int j = 0; j < k && !dup; ++j) dup = tet10[10 * (int64_t)e + j] == tet10[10 * (int64_t)e + k];
-        distinct += dup ? 0 : 1;
+  {
+    std::vector<float> cen(3 * (size_t)n_tets);
+    std::vector<uint64_t> mkey(n_tets);
+    std::vector<int32_t> ids(n_tets);
+    for (int64_t i = 0; i < n_tets; ++i) {
+      const int32_t e = key[i].second;
+      ids[i] = e;
+      mkey[e] = key[i].first;
+      for (int d = 0; d < 3; ++d) {
+        double c = 0.0;
+        for (int k = 0; k < 4; ++k) c += 0.25 * xyz[3 * (int64_t)tet10[10 * (int64_t)e + k] + d];
+        cen[3 * (size_t)e + d] = (float)c;
       }
-      add = distinct;
     }
-    for (int k = 0; k < 10; ++k) mark[tet10[10 * (int64_t)e + k]] = tile;
-    tile_nodes += add;
-    ++tile_elems;
-    L.elem_order[i] = e;
+    int32_t stamp = 0;
+    auto distinct_nodes = [&](int64_t a, int64_t b) {
+      ++stamp;
+      int cnt = 0;
+      for (int64_t i = a; i < b; ++i)
+        for (int k = 0; k < 10; ++k) {
+          const int32_t n = tet10[10 * (int64_t)ids[i] + k];
+          if (mark[n] != stamp) {
+            mark[n] = stamp;
+            ++cnt;
+          }
+        }
+      return cnt;
+    };
+    L.elem_order.reserve(n_tets);
+    L.tile_elem_off.push_back(0);
+    std::vector<std::pair<int64_t, int64_t>> todo{{0, n_tets}};
+    while (!todo.empty()) {
+      const int64_t a = todo.back().first, b = todo.back().second;
+      todo.pop_back();
+      const int64_t n = b - a;
+      if (n == 1 || (n <= max_elems && distinct_nodes(a, b) <= max_nodes)) {
+        std::sort(ids.begin() + a, ids.begin() + b, [&](int32_t x, int32_t y) { return mkey[x] < mkey[y]; });
+        L.elem_order.insert(L.elem_order.end(), ids.begin() + a, ids.begin() + b);
+        L.tile_elem_off.push_back((int32_t)L.elem_order.size());
+        continue;
+      }
+      float lo3[3] = {3e38f, 3e38f, 3e38f}, hi3[3] = {-3e38f, -3e38f, -3e38f};
+      for (int64_t i = a; i < b; ++i)
+        for (int d = 0; d < 3; ++d) {
+          lo3[d] = std::min(lo3[d], cen[3 * (size_t)ids[i] + d]);
+          hi3[d] = std::max(hi3[d], cen[3 * (size_t)ids[i] + d]);
+        }
+      int ax = 0;
+      for (int d = 1; d < 3; ++d)
+        if (hi3[d] - lo3[d] > hi3[ax] - lo3[ax]) ax = d;
+      int64_t cut = n / 2;
+      if (n > max_elems) {
+        cut = (cut + max_elems / 2) / max_elems * max_elems;
+        cut = std::min<int64_t>(std::max<int64_t>(cut, max_elems), n - 1);
+      }
+      std::nth_element(ids.begin() + a, ids.begin() + a + cut, ids.begin() + b, [&](int32_t x, int32_t y) {
+        return cen[3 * (size_t)x + ax] < cen[3 * (size_t)y + ax];
+      });
+      todo.push_back({a + cut, b});
+      todo.push_back({a, a + cut});
+    }
   }
-  L.tile_elem_off.push_back((int32_t)n_tets);
-  const int32_t n_tiles = tile + 1;
+  const int32_t n_tiles = (int32_t)L.tile_elem_off.size() - 1;
   L.n_tiles = n_tiles;
   // --- element order inside each tile: position j holds the tile's
   // (j * S mod n)-th element along the Morton curve, S coprime to n.  The
