@@ -191,3 +191,30 @@ extern "C" int bank_cycles(int64_t nn, int64_t nt, int64_t nf, const double* xyz
   out[1] = at / n;
   return 0;
 }
+
+// Tile shape statistics of the layout with caps (max_nodes, max_elems):
+// out[0] tiles, out[1] fewest and out[2] most elements in a tile, out[3] the
+// share of tile-node entries that are shared nodes, out[4] tile-node entries
+// per mesh node.
+extern "C" int tile_stats(int64_t nn, int64_t nt, int64_t nf, const double* xyz, const int32_t* tet10,
+                          const int32_t* tri6, const int32_t* face_tet, const uint8_t* face_role, int32_t max_nodes,
+                          int32_t max_elems, double* out) {
+  HostLayout L;
+  sw::build_layout(nn, nt, nf, xyz, tet10, tri6, face_tet, face_role, L, max_nodes, max_elems);
+  int64_t entries = 0, shared = 0;
+  int lo = 1 << 30, hi = 0;
+  for (int32_t t = 0; t < L.n_tiles; ++t) {
+    const int n = L.tile_node_off[t + 1] - L.tile_node_off[t];
+    entries += n;
+    shared += n - L.tile_nint[t];
+    const int ne = L.tile_elem_off[t + 1] - L.tile_elem_off[t];
+    lo = std::min(lo, ne);
+    hi = std::max(hi, ne);
+  }
+  out[0] = L.n_tiles;
+  out[1] = lo;
+  out[2] = hi;
+  out[3] = (double)shared / (double)entries;
+  out[4] = (double)entries / (double)nn;
+  return 0;
+}
